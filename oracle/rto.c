@@ -1,0 +1,362 @@
+/*
+ * rto.c -- CPU oracle for the next-reaction random-time algorithm (NRRTA) of
+ * Liu & Wang, arXiv:2103.00405.
+ *
+ * TEST INFRASTRUCTURE ONLY: this is the plain, slow, obviously-correct
+ * reference for the GPU library.  Only the tests, the smoke check and the
+ * benchmark's CPU-baseline leg load it.  It shares no code with the GPU path.
+ *
+ * What it computes, per trajectory (paper section 4, Table 2, with the
+ * internal-time bookkeeping of the random time-change representation,
+ * Eq. 14-16, and the per-channel exponential gaps of Eq. 23-26):
+ *
+ *   state: t, X[N], and per channel k: T_k (internal time elapsed, Eq. 15),
+ *          P_k (internal time of the next firing of channel k), n_k (firings).
+ *   init : t = 0, X = x0, T_k = 0, n_k = 0, P_k = E(k, 0).
+ *   loop : a_k = c_k h_k(X)                          (Eq. 1-2)
+ *          gap_k = (P_k - T_k) / a_k  (+inf if a_k = 0, frozen channel)
+ *          mu = argmin_k gap_k, Delta = gap_mu       (Eq. 25)
+ *          stop if Delta = +inf (absorbed) or t + Delta > t_end
+ *          T_k += a_k Delta for k != mu, T_mu = P_mu (Eq. 15 over [t, t+Delta])
+ *          X += nu_mu, n_mu += 1, P_mu += E(mu, n_mu) (Eq. 26: only the fired
+ *          channel receives a fresh unit-exponential internal gap)
+ *   end  : T_k += a_k (t_end - t) for every k.
+ *
+ * Readings where the paper is silent (all fixed so that a second
+ * implementation can reproduce every bit):
+ *  - h_k = prod_j C(X_j, sigma_jk); C(X,2) = X(X-1)/2 (Eq. 2 prints X_k for X_j).
+ *  - The unfired channels keep their absolute next internal firing time P_k;
+ *    their remaining gap is P_k - T_k (Eq. 26 literally says the gap is kept).
+ *  - Arithmetic: IEEE binary64, round to nearest even.  h_k is exact in int64
+ *    and converted with one rounding; a_k = RN(c_k * h); inv_k = RN(1 / a_k);
+ *    gap_k = RN(RN(P_k - T_k) * inv_k), clamped below at 0; T update is one
+ *    fused multiply-add; E is RN(-ln u), correctly rounded.
+ *  - Ties: the lowest k wins.  A near-tie is counted when
+ *    RN(d2 - d1) <= RN(1e-12 * d1), d1 <= d2 the two smallest gaps.
+ *  - An event with t + Delta > t_end is not applied.
+ *  - Samples: before applying an event at t_new every grid point s_g < t_new
+ *    receives the current X (right-continuous path).  At the end every
+ *    remaining grid point receives the final X.  After an overflow or the
+ *    firing cap the remaining grid points receive -1.
+ *  - Overflow: an event that would take a count outside [0, 2^31-1] is not
+ *    applied; the trajectory stops with status OVERFLOW.
+ *  - E(seed, traj, net, k, n): Philox4x32-10 (Salmon, Moraes, Dror & Shaw,
+ *    SC'11), key (seed_lo, seed_hi), counter (n >> 1, k, traj, net); the
+ *    64-bit word is (w1:w0) for even n and (w3:w2) for odd n; m = word >> 11,
+ *    u = (m + 1) 2^-53 in (0, 1]; E = RN(-ln u), E(u = 1) = +0.
+ *  - seq_hash: h = 0xcbf29ce484222325, then h = (h ^ mu) * 0x100000001b3
+ *    (mod 2^64) for every applied event.
+ */
+#include "rto.h"
+
+#include <math.h>
+#include <pthread.h>
+#include <quadmath.h>
+#include <stdlib.h>
+#include <string.h>
+#include <unistd.h>
+
+#define TIE_NONE 0xFFFFFFFFu
+
+/* ---------------------------------------------------------------- Philox */
+/* Philox4x32 with 10 rounds, from the published definition: each round
+ * multiplies words 0 and 2 by M0 and M1, mixes the high halves with words
+ * 1 and 3 and the key, and the key is bumped by the Weyl constants between
+ * rounds. */
+void rto_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4])
+{
+    const uint32_t M0 = 0xD2511F53u, M1 = 0xCD9E8D57u;
+    const uint32_t W0 = 0x9E3779B9u, W1 = 0xBB67AE85u;
+    uint32_t x0 = ctr[0], x1 = ctr[1], x2 = ctr[2], x3 = ctr[3];
+    uint32_t k0 = key[0], k1 = key[1];
+    for (int round = 0; round < 10; round++) {
+        if (round > 0) { k0 += W0; k1 += W1; }
+        uint64_t p0 = (uint64_t)M0 * (uint64_t)x0;
+        uint64_t p1 = (uint64_t)M1 * (uint64_t)x2;
+        uint32_t y0 = (uint32_t)(p1 >> 32) ^ x1 ^ k0;
+        uint32_t y1 = (uint32_t)p1;
+        uint32_t y2 = (uint32_t)(p0 >> 32) ^ x3 ^ k1;
+        uint32_t y3 = (uint32_t)p0;
+        x0 = y0; x1 = y1; x2 = y2; x3 = y3;
+    }
+    out[0] = x0; out[1] = x1; out[2] = x2; out[3] = x3;
+}
+
+/* ------------------------------------------------------------ Exp(1) draw */
+/* RN(-ln u), u = (m+1) 2^-53.  The binary128 logarithm is accurate to a few
+ * units in its 113-bit last place; its rounding to binary64 is the correctly
+ * rounded result unless the binary128 value sits within 2^-105 (relative) of
+ * a binary64 rounding boundary, which is reported as a hard case (-1). */
+double rto_neglog_u53(uint64_t m)
+{
+    double u = (double)(m + 1) * 0x1p-53;          /* exact: m + 1 <= 2^53 */
+    if (u == 1.0) return 0.0;
+    __float128 q = -logq((__float128)u);
+    double d = (double)q;
+    __float128 dq = (__float128)d;
+    __float128 up = (__float128)nextafter(d, INFINITY);
+    __float128 dn = (__float128)nextafter(d, 0.0);
+    __float128 mid_up = (dq + up) / 2, mid_dn = (dq + dn) / 2; /* exact */
+    __float128 margin = q * 0x1p-105Q;
+    if (fabsq(q - mid_up) <= margin || fabsq(q - mid_dn) <= margin) return -1.0;
+    return d;
+}
+
+double rto_exp1(uint64_t seed, uint32_t traj, uint32_t net_id, uint32_t k, uint32_t n)
+{
+    uint32_t ctr[4] = { n >> 1, k, traj, net_id };
+    uint32_t key[2] = { (uint32_t)seed, (uint32_t)(seed >> 32) };
+    uint32_t w[4];
+    rto_philox4x32_10(ctr, key, w);
+    uint64_t word = (n & 1u) ? (((uint64_t)w[3] << 32) | w[2])
+                             : (((uint64_t)w[1] << 32) | w[0]);
+    return rto_neglog_u53(word >> 11);
+}
+
+/* ------------------------------------------------------------ propensity */
+/* C(x, s) for s in {0, 1, 2}, exact in int64. */
+static int64_t choose(int64_t x, int32_t s)
+{
+    if (s == 0) return 1;
+    if (s == 1) return x;
+    if (x < 2) return 0;
+    return x * (x - 1) / 2;
+}
+
+/* a_k = c_k * h_k(X), h_k = prod over reactant entries of C(X_j, sigma_j)
+ * (Eq. 1-2); the product has at most two factors (molecularity <= 2). */
+static double propensity(const rto_network* net, const int32_t* X, int k)
+{
+    int64_t h = 1;
+    for (int e = net->react_ptr[k]; e < net->react_ptr[k + 1]; e++)
+        h *= choose(X[net->react_species[e]], net->react_sigma[e]);
+    return net->c[k] * (double)h;
+}
+
+/* ------------------------------------------------------------ one path */
+typedef struct {
+    const rto_network* net;
+    const int32_t* nu_ptr;      /* net change nu_k as (species, delta) lists */
+    const int32_t* nu_species;
+    const int32_t* nu_delta;
+    const int32_t* x0;
+    int32_t x0_per_traj;
+    double t_end;
+    const double* s;
+    int32_t G;
+    uint64_t seed;
+    uint32_t net_id;
+    uint64_t traj_offset;
+    uint64_t max_firings;
+    int32_t *samples, *x_final;
+    uint32_t *n_out, *tie_step;
+    double *T_out, *t_last;
+    uint8_t* status;
+    uint64_t* seq_hash;
+    int64_t r_begin, r_end;
+    rto_stats stats;
+} job_t;
+
+static void write_sample(job_t* jb, int64_t r, int32_t g, const int32_t* X, int fill_invalid)
+{
+    int N = jb->net->N;
+    int32_t* dst = jb->samples + ((size_t)r * jb->G + g) * N;
+    for (int j = 0; j < N; j++) dst[j] = fill_invalid ? -1 : X[j];
+}
+
+static void simulate_path(job_t* jb, int64_t r, int32_t* X, double* T, double* P,
+                          double* a, double* inv, uint32_t* n)
+{
+    const rto_network* net = jb->net;
+    const int N = net->N, M = net->M;
+    const uint32_t traj = (uint32_t)(jb->traj_offset + (uint64_t)r);
+    const uint64_t seed = jb->seed;
+    const uint32_t nid = jb->net_id;
+
+    const int32_t* x0 = jb->x0 + (jb->x0_per_traj ? (size_t)r * N : 0);
+    for (int j = 0; j < N; j++) X[j] = x0[j];
+    double t = 0.0;
+    for (int k = 0; k < M; k++) {
+        T[k] = 0.0;
+        n[k] = 0;
+        P[k] = rto_exp1(seed, traj, nid, (uint32_t)k, 0);
+        if (P[k] < 0) jb->stats.hard_cases++;
+        a[k] = propensity(net, X, k);
+        inv[k] = a[k] > 0 ? 1.0 / a[k] : 0.0;
+    }
+    int32_t g = 0;
+    uint64_t fired = 0;
+    uint8_t st = RTO_OK;
+    uint32_t tie = TIE_NONE;
+    uint64_t hash = 0xcbf29ce484222325ull;
+
+    for (;;) {
+        /* gaps and argmin: lowest k among the minimal gaps; d2 is the second
+         * order statistic of the gaps */
+        int mu = -1;
+        double d1 = INFINITY, d2 = INFINITY;
+        for (int k = 0; k < M; k++) {
+            double d;
+            if (a[k] == 0.0) {
+                d = INFINITY;
+            } else {
+                d = (P[k] - T[k]) * inv[k];
+                if (d < 0.0) d = 0.0;
+            }
+            if (d < d1) { d2 = d1; d1 = d; mu = k; }
+            else if (d < d2) { d2 = d; }
+        }
+        if (d1 == INFINITY) { st = RTO_ABSORBED; break; }
+        double t_new = t + d1;
+        if (t_new > jb->t_end) break;
+        if (d2 - d1 <= 1e-12 * d1) {
+            jb->stats.near_ties++;
+            if (tie == TIE_NONE) tie = (uint32_t)fired;
+        }
+        while (g < jb->G && jb->s[g] < t_new) { write_sample(jb, r, g, X, 0); g++; }
+        /* the state jump must stay inside [0, 2^31 - 1] */
+        int ok = 1;
+        for (int e = jb->nu_ptr[mu]; e < jb->nu_ptr[mu + 1]; e++) {
+            int64_t v = (int64_t)X[jb->nu_species[e]] + jb->nu_delta[e];
+            if (v < 0 || v > INT32_MAX) ok = 0;
+        }
+        if (!ok) { st = RTO_OVERFLOW; break; }
+        if ((P[mu] - T[mu]) * inv[mu] < 0.0) jb->stats.clamps++;
+        /* internal times advance by a_k * Delta (Eq. 15); the fired channel
+         * lands exactly on its firing internal time */
+        for (int k = 0; k < M; k++)
+            if (k != mu) T[k] = fma(a[k], d1, T[k]);
+        T[mu] = P[mu];
+        t = t_new;
+        for (int e = jb->nu_ptr[mu]; e < jb->nu_ptr[mu + 1]; e++)
+            X[jb->nu_species[e]] += jb->nu_delta[e];
+        n[mu] += 1;
+        fired += 1;
+        hash = (hash ^ (uint64_t)(uint32_t)mu) * 0x100000001b3ull;
+        double E = rto_exp1(seed, traj, nid, (uint32_t)mu, n[mu]);
+        if (E < 0) jb->stats.hard_cases++;
+        P[mu] = P[mu] + E;
+        /* a_k is a pure function of X: recomputing every channel equals
+         * recomputing only the channels that read a changed species */
+        for (int k = 0; k < M; k++) {
+            a[k] = propensity(net, X, k);
+            inv[k] = a[k] > 0 ? 1.0 / a[k] : 0.0;
+        }
+        if (fired >= jb->max_firings) { st = RTO_MAX_FIRINGS; break; }
+    }
+
+    if (st == RTO_OK || st == RTO_ABSORBED) {
+        while (g < jb->G) { write_sample(jb, r, g, X, 0); g++; }
+        double dt = jb->t_end - t;
+        for (int k = 0; k < M; k++) T[k] = fma(a[k], dt, T[k]);
+    } else {
+        while (g < jb->G) { write_sample(jb, r, g, X, 1); g++; }
+    }
+
+    for (int k = 0; k < M; k++) {
+        jb->n_out[(size_t)r * M + k] = n[k];
+        jb->T_out[(size_t)r * M + k] = T[k];
+    }
+    for (int j = 0; j < N; j++) jb->x_final[(size_t)r * N + j] = X[j];
+    jb->t_last[r] = t;
+    jb->status[r] = st;
+    jb->seq_hash[r] = hash;
+    jb->tie_step[r] = tie;
+    jb->stats.firings += fired;
+    jb->stats.status_count[st]++;
+}
+
+static void* run_job(void* arg)
+{
+    job_t* jb = (job_t*)arg;
+    int N = jb->net->N, M = jb->net->M;
+    int32_t* X = (int32_t*)malloc(sizeof(int32_t) * (N > 0 ? N : 1));
+    double* T = (double*)malloc(sizeof(double) * (M > 0 ? M : 1));
+    double* P = (double*)malloc(sizeof(double) * (M > 0 ? M : 1));
+    double* a = (double*)malloc(sizeof(double) * (M > 0 ? M : 1));
+    double* inv = (double*)malloc(sizeof(double) * (M > 0 ? M : 1));
+    uint32_t* n = (uint32_t*)malloc(sizeof(uint32_t) * (M > 0 ? M : 1));
+    for (int64_t r = jb->r_begin; r < jb->r_end; r++) simulate_path(jb, r, X, T, P, a, inv, n);
+    free(X); free(T); free(P); free(a); free(inv); free(n);
+    return NULL;
+}
+
+/* Net change nu_k = products - reactants as a sparse list without zeros. */
+static void build_nu(const rto_network* net, int32_t* ptr, int32_t* sp, int32_t* dl)
+{
+    int pos = 0;
+    for (int k = 0; k < net->M; k++) {
+        ptr[k] = pos;
+        int start = pos;
+        for (int pass = 0; pass < 2; pass++) {
+            const int32_t* lp = pass == 0 ? net->react_ptr : net->prod_ptr;
+            const int32_t* ls = pass == 0 ? net->react_species : net->prod_species;
+            const int32_t* lm = pass == 0 ? net->react_sigma : net->prod_mult;
+            for (int e = lp[k]; e < lp[k + 1]; e++) {
+                int32_t d = pass == 0 ? -lm[e] : lm[e];
+                int found = 0;
+                for (int q = start; q < pos; q++)
+                    if (sp[q] == ls[e]) { dl[q] += d; found = 1; }
+                if (!found) { sp[pos] = ls[e]; dl[pos] = d; pos++; }
+            }
+        }
+        int w = start;
+        for (int q = start; q < pos; q++)
+            if (dl[q] != 0) { sp[w] = sp[q]; dl[w] = dl[q]; w++; }
+        pos = w;
+    }
+    ptr[net->M] = pos;
+}
+
+static int n_threads(int32_t req, int64_t R)
+{
+    long nt = req > 0 ? req : sysconf(_SC_NPROCESSORS_ONLN);
+    if (nt < 1) nt = 1;
+    if (nt > R) nt = (long)(R > 0 ? R : 1);
+    return (int)nt;
+}
+
+int rto_simulate(const rto_network* net, const int32_t* x0, int32_t x0_per_traj,
+                 double t_end, const double* sample_t, int32_t G,
+                 uint64_t seed, uint32_t net_id, uint64_t traj_offset, int64_t R,
+                 uint64_t max_firings,
+                 int32_t* samples, uint32_t* n_out, double* T_out, int32_t* x_final,
+                 double* t_last, uint8_t* status, uint64_t* seq_hash, uint32_t* tie_step,
+                 int32_t nthreads, rto_stats* stats)
+{
+    if (!net || net->N < 0 || net->M < 0 || R < 0 || G < 0) return RTO_E_INVALID;
+    if (R == 0) { if (stats) memset(stats, 0, sizeof(*stats)); return RTO_SUCCESS; }
+    size_t nnz = (size_t)(net->react_ptr[net->M] + net->prod_ptr[net->M]);
+    int32_t* nu_ptr = (int32_t*)malloc(sizeof(int32_t) * (net->M + 1));
+    int32_t* nu_sp = (int32_t*)malloc(sizeof(int32_t) * (nnz + 1));
+    int32_t* nu_dl = (int32_t*)malloc(sizeof(int32_t) * (nnz + 1));
+    build_nu(net, nu_ptr, nu_sp, nu_dl);
+
+    int nt = n_threads(nthreads, R);
+    job_t* jobs = (job_t*)calloc((size_t)nt, sizeof(job_t));
+    pthread_t* th = (pthread_t*)calloc((size_t)nt, sizeof(pthread_t));
+    for (int i = 0; i < nt; i++) {
+        job_t* jb = &jobs[i];
+        jb->net = net; jb->nu_ptr = nu_ptr; jb->nu_species = nu_sp; jb->nu_delta = nu_dl;
+        jb->x0 = x0; jb->x0_per_traj = x0_per_traj; jb->t_end = t_end; jb->s = sample_t;
+        jb->G = G; jb->seed = seed; jb->net_id = net_id; jb->traj_offset = traj_offset;
+        jb->max_firings = max_firings; jb->samples = samples; jb->x_final = x_final;
+        jb->n_out = n_out; jb->tie_step = tie_step; jb->T_out = T_out; jb->t_last = t_last;
+        jb->status = status; jb->seq_hash = seq_hash;
+        jb->r_begin = R * i / nt; jb->r_end = R * (i + 1) / nt;
+        pthread_create(&th[i], NULL, run_job, jb);
+    }
+    rto_stats tot;
+    memset(&tot, 0, sizeof(tot));
+    for (int i = 0; i < nt; i++) {
+        pthread_join(th[i], NULL);
+        tot.firings += jobs[i].stats.firings;
+        tot.near_ties += jobs[i].stats.near_ties;
+        tot.clamps += jobs[i].stats.clamps;
+        tot.hard_cases += jobs[i].stats.hard_cases;
+        for (int q = 0; q < 4; q++) tot.status_count[q] += jobs[i].stats.status_count[q];
+    }
+    if (stats) *stats = tot;
+    free(jobs); free(th); free(nu_ptr); free(nu_sp); free(nu_dl);
+    return tot.hard_cases ? RTO_E_HARDCASE : RTO_SUCCESS;
+}

@@ -1,0 +1,141 @@
+"""The oracle's pins are strong enough to catch plausible mistakes.
+
+Each case copies rto.c, plants one mistake (a dropped term, a wrong index, a
+wrong sign or scale, a reused random draw, a reversed comparison), builds the
+mutant with gcc and checks that at least one pin fails on it.  The mistakes
+are planted in a copy of the oracle on the CPU only.
+"""
+import math
+import os
+import shutil
+import subprocess
+import tempfile
+
+import numpy as np
+import pytest
+from scipy import stats
+
+import oracle
+from paper_2103_00405_amd import workloads as W
+
+ORACLE_DIR = os.path.dirname(os.path.abspath(oracle.__file__))
+
+MUTANTS = {
+    "homodimer_x_squared": ("return x * (x - 1) / 2;", "return x * x / 2;"),
+    "unfired_clock_frozen": ("if (k != mu) T[k] = fma(a[k], d1, T[k]);", "if (k != mu) T[k] = T[k];"),
+    "refresh_half_gap": ("P[mu] = P[mu] + E;", "P[mu] = P[mu] + 0.5 * E;"),
+    "reused_draw": ("(uint32_t)mu, n[mu]);", "(uint32_t)mu, n[mu] - 1);"),
+    "wrong_half_of_block": ("uint64_t word = (n & 1u) ?", "uint64_t word = (n & 0u) ?"),
+    "final_clock_not_advanced": ("for (int k = 0; k < M; k++) T[k] = fma(a[k], dt, T[k]);",
+                                 "for (int k = 0; k < M; k++) T[k] = T[k];"),
+    "rate_of_next_channel": ("return net->c[k] * (double)h;",
+                             "return net->c[(k + 1) % net->M] * (double)h;"),
+    "time_step_halved": ("double t_new = t + d1;", "double t_new = t + 0.5 * d1;"),
+    "argmax_instead_of_argmin": ("if (d < d1) { d2 = d1; d1 = d; mu = k; }",
+                                 "if (d1 == INFINITY || d > d1) { d2 = d1; d1 = d; mu = k; }"),
+    "jump_sign_flipped": ("X[jb->nu_species[e]] += jb->nu_delta[e];",
+                          "X[jb->nu_species[e]] -= jb->nu_delta[e];"),
+    "philox_key_not_bumped": ("if (round > 0) { k0 += W0; k1 += W1; }", "if (round > 0) { k0 += W0; }"),
+    "log_of_wrong_argument": ("double u = (double)(m + 1) * 0x1p-53;", "double u = (double)(m + 2) * 0x1p-53;"),
+}
+
+
+def _build_mutant(tmp, name):
+    old, new = MUTANTS[name]
+    src = open(os.path.join(ORACLE_DIR, "rto.c")).read()
+    assert src.count(old) == 1, name
+    for f in ("rto.h", "dm.c"):
+        shutil.copy(os.path.join(ORACLE_DIR, f), tmp)
+    with open(os.path.join(tmp, "rto.c"), "w") as f:
+        f.write(src.replace(old, new))
+    so = os.path.join(tmp, "librto_mut.so")
+    subprocess.run(["gcc", "-O2", "-fPIC", "-shared", "-ffp-contract=off", "-o", so,
+                    os.path.join(tmp, "rto.c"), os.path.join(tmp, "dm.c"),
+                    "-lquadmath", "-lpthread", "-lm"], check=True, capture_output=True)
+    return oracle.load_library(so)
+
+
+def _pin_failures(L):
+    """Run a quick subset of the law pins against library L; return failed names."""
+    failed = []
+
+    def sim(net, x0, t_end, grid, R, seed=1, **kw):
+        try:
+            return oracle.simulate(net, np.asarray(x0, np.int32), t_end, np.asarray(grid, float),
+                                   seed, R, _lib=L, **kw)
+        except RuntimeError:
+            return None
+
+    # 1. Exp(1) draws equal the correctly rounded -ln u of the Philox word
+    import mpmath
+    for (n, k) in [(0, 0), (1, 2), (2, 1), (5, 3)]:
+        w = oracle.philox4x32_10([n >> 1, k, 9, 0], [7, 0])
+        word = (int(w[3]) << 32 | int(w[2])) if n & 1 else (int(w[1]) << 32 | int(w[0]))
+        with mpmath.workdps(50):
+            ref = float(-mpmath.log(mpmath.mpf((word >> 11) + 1) / 2**53))
+        if L.rto_exp1(7, 9, 0, k, n) != ref:
+            failed.append("exp1")
+            break
+
+    # 2. birth-death transient law: Poisson(m(t)), mean and variance
+    k1, k2, T = 50.0, 1.0, 2.0
+    o = sim(W.birth_death(k1, k2), [0], T, [T], 8000, seed=5)
+    if o is None:
+        failed.append("bd_run")
+    else:
+        X = o["x_final"][:, 0].astype(float)
+        m = k1 / k2 * (1 - math.exp(-k2 * T))
+        if abs(X.mean() - m) > 4.5 * math.sqrt(m / X.size) or \
+                abs(X.var() - m) > 5 * m * math.sqrt(2.0 / X.size):
+            failed.append("bd_law")
+        # martingale n_k - T_k
+        S = o["n"].astype(float) - o["T"]
+        for kk in range(2):
+            ET = o["T"][:, kk].mean()
+            if abs(S[:, kk].mean()) > 4.5 * math.sqrt(ET / S.shape[0]):
+                failed.append("martingale")
+                break
+        if not np.allclose(o["T"][:, 0], k1 * T, rtol=1e-12):
+            failed.append("constant_rate_clock")
+
+    # 3. dimerisation CME (homodimer convention)
+    from test_oracle_law import _cme_dimer, _chisq_discrete
+    o = sim(W.dimerisation(0.05, 1.0), [30, 0], 0.8, [0.8], 8000, seed=8)
+    if o is None or _chisq_discrete(o["x_final"][:, 1], np.arange(16),
+                                    _cme_dimer(0.05, 1.0, 30, 0, 0.8)) < 1e-4:
+        failed.append("dimer_cme")
+
+    # 4. Eq. 5 state identity on a random network
+    rng = np.random.default_rng(5)
+    net = W.random_network(6, 14, rng)
+    x0 = rng.integers(0, 40, size=6).astype(np.int32)
+    o = sim(net, x0, 0.3, [0.3], 200)
+    if o is None:
+        failed.append("identity_run")
+    else:
+        from test_oracle_law import _nu_dense
+        pred = x0[None, :].astype(np.int64) + o["n"].astype(np.int64) @ _nu_dense(net)
+        if not np.array_equal(pred, o["x_final"].astype(np.int64)) or (o["x_final"] < 0).any():
+            failed.append("eq5_identity")
+
+    # 5. two-sample law against Gillespie's direct method (random network)
+    if o is not None:
+        d = oracle.dm_simulate(net, x0, 0.3, [0.3], 99, 3000)
+        o3 = sim(net, x0, 0.3, [0.3], 3000, seed=3)
+        ps = [stats.ks_2samp(o3["x_final"][:, j], d["samples"][:, 0, j]).pvalue for j in range(6)]
+        if min(ps) * 6 < 1e-4:
+            failed.append("dm_two_sample")
+    return failed
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("name", sorted(MUTANTS))
+def test_pins_catch_planted_mistake(name):
+    with tempfile.TemporaryDirectory() as tmp:
+        L = _build_mutant(tmp, name)
+        failed = _pin_failures(L)
+    assert failed, "mutant %s passed every pin" % name
+
+
+def test_pins_pass_on_the_real_oracle():
+    assert _pin_failures(oracle.lib()) == []
