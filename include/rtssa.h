@@ -1,0 +1,205 @@
+/*
+ * rtssa.h -- C ABI of the MI355X random-time stochastic simulation library.
+ *
+ * The library simulates mass-action chemical reaction networks with the next
+ * reaction random time algorithm (NRRTA) of Liu & Wang, "Parallel
+ * implementations of random time algorithm for chemical network stochastic
+ * simulations" (arXiv:2103.00405): section 4, Table 2, on the random
+ * time-change representation X(t) = X(0) + sum_k Y_k(T_k(t)) v_k of section 2
+ * (Eq. 14-16), with per-channel unit-exponential internal-time gaps (Eq. 23)
+ * of which only the fired channel's is refreshed (Eq. 26).
+ *
+ * Conventions.
+ *  - Every function returns an rtssa_status code (0 on success).  On failure
+ *    rtssa_last_error() returns a thread-local description.
+ *  - "device" pointers are HIP device memory (e.g. torch CUDA tensors);
+ *    "host" pointers are ordinary memory.  The caller owns every buffer it
+ *    passes; the library owns the handles it returns.
+ *  - Work is enqueued on the given hipStream_t (NULL = the default stream)
+ *    and is asynchronous unless a function says otherwise.
+ *  - Floating point is IEEE binary64 throughout; counts are exact integers.
+ *
+ * Per-trajectory arithmetic (the contract every mapping and the CPU
+ * reference follow bit for bit):
+ *   init : t = 0, X = x0, T_k = 0, n_k = 0, P_k = E(k, 0)
+ *   a_k  = RN(c_k * RN(h_k(X))), h_k = prod_j C(X_j, sigma_jk) in exact int64
+ *          (Eq. 1-2; C(X,2) = X(X-1)/2); inv_k = RN(1 / a_k)
+ *   gap_k = +inf if a_k = 0 (frozen channel, Table 2 note), else
+ *           max(0, RN(RN(P_k - T_k) * inv_k))
+ *   mu   = lowest k with the smallest gap (Eq. 25); Delta = gap_mu
+ *   stop (ABSORBED) if Delta = +inf; stop (OK) if t + Delta > t_end
+ *   near-tie when RN(d2 - Delta) <= RN(1e-12 * Delta), d2 the second smallest gap
+ *   grid points s_g < t + Delta receive X (right-continuous sampling)
+ *   stop (OVERFLOW) if X + v_mu leaves [0, 2^31 - 1] (jump not applied)
+ *   t += Delta; T_k = fma(a_k, Delta, T_k) for k != mu; T_mu = P_mu;
+ *   X += v_mu; n_mu += 1; P_mu = RN(P_mu + E(mu, n_mu)); recompute a, inv
+ *   stop (MAX_FIRINGS) once sum_k n_k reaches max_firings
+ *   end (OK, ABSORBED): remaining grid points receive X and
+ *       T_k = fma(a_k, RN(t_end - t), T_k); after OVERFLOW / MAX_FIRINGS the
+ *       remaining grid points receive -1 and T is left at the last event.
+ *   E(k, n) = RN(-ln u), correctly rounded, u = ((word >> 11) + 1) 2^-53 with
+ *       word the 64-bit half of the Philox4x32-10 block (Salmon et al., SC'11)
+ *       at counter (n >> 1, k, traj, net_id) under key (seed_lo, seed_hi):
+ *       (w1:w0) for even n, (w3:w2) for odd n.
+ *   seq_hash: h = 0xcbf29ce484222325; per applied event h = (h ^ mu) * 0x100000001b3.
+ */
+#ifndef RTSSA_H
+#define RTSSA_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ihipStream_t* rtssa_stream_t; /* same type as hipStream_t */
+
+typedef enum {
+    RTSSA_OK = 0,
+    RTSSA_E_INVALID = -1,     /* bad argument (shape, range, NULL, ordering) */
+    RTSSA_E_UNSUPPORTED = -2, /* molecularity > 2 (the paper's own limit) or size beyond a mapping */
+    RTSSA_E_HIP = -3,         /* a HIP runtime call failed */
+    RTSSA_E_NOMEM = -4        /* device or host allocation failed */
+} rtssa_status;
+
+/* per-trajectory end states */
+enum { RTSSA_TRAJ_OK = 0, RTSSA_TRAJ_ABSORBED = 1, RTSSA_TRAJ_OVERFLOW = 2,
+       RTSSA_TRAJ_MAX_FIRINGS = 3 };
+
+/* kernel mappings (work decomposition of one trajectory) */
+enum { RTSSA_MAP_AUTO = 0, RTSSA_MAP_THREAD = 1, RTSSA_MAP_WAVE = 2, RTSSA_MAP_WORKGROUP = 3 };
+
+#define RTSSA_TIE_NONE 0xFFFFFFFFu
+
+typedef struct rtssa_network rtssa_network;
+
+typedef struct {
+    uint64_t firings;         /* applied events over all trajectories */
+    uint64_t near_ties;       /* applied events with a near-tie (see above) */
+    uint64_t clamps;          /* applied events whose raw gap was negative */
+    uint64_t slow_logs;       /* Exp(1) draws that needed the accurate log phase */
+    uint64_t status_count[4]; /* trajectories per end state */
+    double kernel_ms;         /* device time of the simulation launch(es) */
+    int32_t mapping;          /* mapping that ran */
+    int32_t block;            /* workgroup size that ran */
+    int32_t grid;             /* workgroups launched */
+    int32_t reserved;
+} rtssa_stats;
+
+typedef struct {
+    uint64_t max_firings;  /* per trajectory; 0 = 10^7; at most 2^32 - 1 */
+    int32_t mapping;       /* RTSSA_MAP_*; 0 = chosen from the network size */
+    int32_t block;         /* workgroup size; 0 = the mapping's default */
+    int32_t grid;          /* workgroups of the persistent grid; 0 = fill the GPU */
+    int32_t reserved;
+} rtssa_options;
+
+/* Message for the last failure on this thread (never NULL). */
+const char* rtssa_last_error(void);
+
+/* Library version string. */
+const char* rtssa_version(void);
+
+/*
+ * Compile a network (paper Eq. 1-2, section 2; the paper's Table 4 model file
+ * carries the same information).  All arrays are host memory and are copied.
+ *   N species, M reactions (N, M >= 0).
+ *   Reaction k consumes react_sigma[e] molecules of species react_species[e]
+ *   for e in [react_ptr[k], react_ptr[k+1]) and produces prod_mult[e]
+ *   molecules of prod_species[e] for e in [prod_ptr[k], prod_ptr[k+1]).
+ *   c[k] >= 0 is the rate constant; 0 or within [1e-280, 1e280].
+ * Errors: RTSSA_E_INVALID for bad pointers, indices, coefficients < 1,
+ * repeated reactant species, non-monotone offsets or bad rates;
+ * RTSSA_E_UNSUPPORTED when sum_j sigma_jk > 2 (molecularity limit of the
+ * paper's GPU layout, section 5).  Builds the reactant table, the net-change
+ * lists v_k and the dependency graph D(mu) = {k : k reads a species that mu
+ * changes} (Gibson & Bruck, cited in section 5).
+ */
+int rtssa_network_create(int32_t N, int32_t M,
+                         const int32_t* react_ptr, const int32_t* react_species,
+                         const int32_t* react_sigma,
+                         const int32_t* prod_ptr, const int32_t* prod_species,
+                         const int32_t* prod_mult, const double* c,
+                         rtssa_network** out);
+
+/* Free a network handle and its device tables (NULL is ignored). */
+int rtssa_network_destroy(rtssa_network* net);
+
+/* Replace the rate constants (host array [M]); same validation as create.
+ * Synchronous with respect to the host; do not call while a simulation of
+ * this network is in flight. */
+int rtssa_network_set_rates(rtssa_network* net, const double* c);
+
+/* Query sizes of a compiled network: N, M, dependency-graph edges, and the
+ * mapping the automatic choice selects. Any output pointer may be NULL. */
+int rtssa_network_info(const rtssa_network* net, int32_t* N, int32_t* M,
+                       int64_t* dep_edges, int32_t* auto_mapping);
+
+/*
+ * Simulate trajectories traj_offset .. traj_offset + R - 1 of the network on
+ * the GPU (the whole hot path of section 4, Table 2, in one launch).
+ *   x0        device int32 [N] (x0_per_traj = 0) or [R][N] (x0_per_traj = 1);
+ *             counts must be >= 0.
+ *   t_end     finite, >= 0.
+ *   sample_t  device float64 [G], non-decreasing, within [0, t_end]
+ *             (read once by the host for validation; may be NULL when G = 0).
+ *   seed      Philox key; net_id is the fourth counter word.
+ *   traj_offset + R <= 2^32.
+ * Outputs, all device memory, any of them may be NULL to skip it:
+ *   samples   int32, element (r, g, j) at r*s_stride_r + g*s_stride_g + j*s_stride_n
+ *   n_out     uint32 [R][M] firings per channel
+ *   T_out     float64 [R][M] internal times T_k(t_end) (Eq. 15)
+ *   x_final   int32 [R][N]; t_last float64 [R] time of the last applied event
+ *   status    uint8 [R] RTSSA_TRAJ_*; seq_hash uint64 [R]
+ *   tie_step  uint32 [R] index of the first near-tie event, RTSSA_TIE_NONE if none
+ * stats (host, may be NULL): when given, the call waits for the stream and
+ * fills it; otherwise the call returns without waiting.
+ * opt may be NULL (defaults).  Device scratch (a few hundred bytes of
+ * counters) is allocated stream-ordered by this call.
+ */
+int rtssa_simulate(const rtssa_network* net, const int32_t* x0, int32_t x0_per_traj,
+                   double t_end, const double* sample_t, int32_t G,
+                   uint64_t seed, uint32_t net_id, uint64_t traj_offset, int64_t R,
+                   int32_t* samples, int64_t s_stride_r, int64_t s_stride_g,
+                   int64_t s_stride_n,
+                   uint32_t* n_out, double* T_out, int32_t* x_final, double* t_last,
+                   uint8_t* status, uint64_t* seq_hash, uint32_t* tie_step,
+                   const rtssa_options* opt, rtssa_stream_t stream, rtssa_stats* stats);
+
+/*
+ * Score-function gradient of E[f(X_T)] with respect to log c_k.  For mass
+ * action a_k = c_k h_k (Eq. 1), so the derivative of the path log-likelihood
+ * in log c_k is n_k - T_k(t_end), read directly from the internal clocks of
+ * Eq. 15.  With baseline = 1 the leave-one-out mean b_r = (sum f - f_r)/(R-1)
+ * is subtracted (unbiased); baseline = 0 uses b = 0.
+ *   f [R], n [R][M], T [R][M]: device inputs.
+ *   grad [M], se [M]: device outputs (se = standard error of the mean of the
+ *   per-path terms; se may be NULL).  R >= 1, M >= 1.
+ */
+int rtssa_score_grad(const double* f, const uint32_t* n, const double* T, int64_t R,
+                     int32_t M, int32_t baseline, double* grad, double* se,
+                     rtssa_stream_t stream);
+
+/* ---------------------------------------------------------------------
+ * Test hooks: the library's own Philox and -ln(u), for checking its
+ * arithmetic element by element.  The *_host variants run the same source
+ * compiled for the CPU; the device variants launch a kernel.
+ */
+/* out[i] = RN(-ln((m[i]+1) 2^-53)); force_accurate = 1 skips the fast phase;
+ * slow (may be NULL) receives 1 where the accurate phase ran. */
+int rtssa_debug_neglog(const uint64_t* m, double* out, uint8_t* slow, int64_t count,
+                       int32_t force_accurate, rtssa_stream_t stream);
+double rtssa_debug_neglog_host(uint64_t m, int32_t force_accurate, int32_t* slow);
+/* The fast phase's double-double approximation yh + yl of -ln u (m < 2^53 - 1). */
+void rtssa_debug_neglog_fast_host(uint64_t m, double* yh, double* yl);
+/* out[4i..4i+3] = Philox4x32-10(ctr[4i..4i+3], key) */
+int rtssa_debug_philox(const uint32_t* ctr, uint32_t key0, uint32_t key1, uint32_t* out,
+                       int64_t count, rtssa_stream_t stream);
+void rtssa_debug_philox_host(const uint32_t ctr[4], uint32_t key0, uint32_t key1,
+                             uint32_t out[4]);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

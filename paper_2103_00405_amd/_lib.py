@@ -1,0 +1,81 @@
+"""ctypes loader for librtssa.so (argument marshalling only).
+
+The library is built in-tree by ``paper_2103_00405_amd/build.py``.  There is
+no fallback: if the shared object is missing or fails to load, every entry
+point raises.
+"""
+import ctypes as C
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "librtssa.so")
+
+_lib = None
+
+vp = C.c_void_p
+i32, i64, u32, u64, f64 = C.c_int32, C.c_int64, C.c_uint32, C.c_uint64, C.c_double
+
+
+class Stats(C.Structure):
+    _fields_ = [("firings", u64), ("near_ties", u64), ("clamps", u64), ("slow_logs", u64),
+                ("status_count", u64 * 4), ("kernel_ms", f64), ("mapping", i32),
+                ("block", i32), ("grid", i32), ("reserved", i32)]
+
+    def as_dict(self):
+        return dict(firings=int(self.firings), near_ties=int(self.near_ties),
+                    clamps=int(self.clamps), slow_logs=int(self.slow_logs),
+                    status_count=[int(x) for x in self.status_count],
+                    kernel_ms=float(self.kernel_ms), mapping=int(self.mapping),
+                    block=int(self.block), grid=int(self.grid))
+
+
+class Options(C.Structure):
+    _fields_ = [("max_firings", u64), ("mapping", i32), ("block", i32), ("grid", i32),
+                ("reserved", i32)]
+
+
+SIGNATURES = {
+    "rtssa_last_error": (C.c_char_p, []),
+    "rtssa_version": (C.c_char_p, []),
+    "rtssa_network_create": (C.c_int, [i32, i32, vp, vp, vp, vp, vp, vp, vp, C.POINTER(vp)]),
+    "rtssa_network_destroy": (C.c_int, [vp]),
+    "rtssa_network_set_rates": (C.c_int, [vp, vp]),
+    "rtssa_network_info": (C.c_int, [vp, vp, vp, vp, vp]),
+    "rtssa_simulate": (C.c_int, [vp, vp, i32, f64, vp, i32, u64, u32, u64, i64, vp, i64, i64,
+                                 i64, vp, vp, vp, vp, vp, vp, vp, C.POINTER(Options), vp,
+                                 C.POINTER(Stats)]),
+    "rtssa_score_grad": (C.c_int, [vp, vp, vp, i64, i32, i32, vp, vp, vp]),
+    "rtssa_debug_neglog": (C.c_int, [vp, vp, vp, i64, i32, vp]),
+    "rtssa_debug_neglog_host": (f64, [u64, i32, C.POINTER(i32)]),
+    "rtssa_debug_neglog_fast_host": (None, [u64, C.POINTER(f64), C.POINTER(f64)]),
+    "rtssa_debug_philox": (C.c_int, [vp, u32, u32, vp, i64, vp]),
+    "rtssa_debug_philox_host": (None, [vp, u32, u32, vp]),
+}
+
+
+class RtssaError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__("rtssa error %d: %s" % (code, msg))
+        self.code = code
+
+
+def lib():
+    """Load librtssa.so; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError("librtssa.so is not built; run paper_2103_00405_amd/build.py "
+                               "(or __graft_entry__.build()) first")
+        L = C.CDLL(LIB_PATH)
+        for name, (res, args) in SIGNATURES.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+def check(rc):
+    if rc != 0:
+        raise RtssaError(rc, lib().rtssa_last_error().decode())
+    return rc

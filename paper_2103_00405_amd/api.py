@@ -1,0 +1,175 @@
+"""Python face of librtssa: networks, ensemble simulation, score gradients.
+
+Only argument marshalling happens here: every step of a simulation runs in
+the HIP kernels behind the C ABI.  PyTorch provides device memory and the
+current stream.  There is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+from typing import Callable, Optional
+
+import numpy as np
+import torch
+
+from . import _lib
+from ._lib import Options, Stats, check, lib
+
+MAP_AUTO, MAP_THREAD, MAP_WAVE, MAP_WORKGROUP = 0, 1, 2, 3
+TRAJ_OK, TRAJ_ABSORBED, TRAJ_OVERFLOW, TRAJ_MAX_FIRINGS = 0, 1, 2, 3
+TIE_NONE = 0xFFFFFFFF
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+def _stream(device) -> C.c_void_p:
+    return C.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+def _require_gpu(device):
+    if not torch.cuda.is_available():
+        raise RuntimeError("rtssa needs a ROCm GPU; none is visible")
+    return torch.device(device)
+
+
+class Network:
+    """A compiled mass-action network (device tables owned by the library).
+
+    ``spec`` is any object with N, M, react_ptr, react_species, react_sigma,
+    prod_ptr, prod_species, prod_mult and c (see ``workloads.NetSpec``)."""
+
+    def __init__(self, spec, device="cuda"):
+        self.device = _require_gpu(device)
+        self.N, self.M = int(spec.N), int(spec.M)
+        arrs = [np.ascontiguousarray(getattr(spec, k), dtype=np.int32) for k in
+                ("react_ptr", "react_species", "react_sigma", "prod_ptr", "prod_species",
+                 "prod_mult")]
+        c = np.ascontiguousarray(spec.c, dtype=np.float64)
+        arrs = [a if a.size else np.zeros(1, np.int32) for a in arrs]
+        if c.size == 0:
+            c = np.zeros(1, np.float64)
+        self._keep = arrs + [c]
+        self._h = C.c_void_p()
+        with torch.cuda.device(self.device):
+            check(lib().rtssa_network_create(self.N, self.M, *[a.ctypes.data for a in arrs],
+                                             c.ctypes.data, C.byref(self._h)))
+        self.c = c[: self.M].copy()
+
+    def set_rates(self, c):
+        c = np.ascontiguousarray(c, dtype=np.float64)
+        if c.size != self.M:
+            raise ValueError("expected %d rates" % self.M)
+        with torch.cuda.device(self.device):
+            check(lib().rtssa_network_set_rates(self._h, c.ctypes.data))
+        self.c = c.copy()
+
+    def info(self):
+        N, M, mp = C.c_int32(), C.c_int32(), C.c_int32()
+        dep = C.c_int64()
+        check(lib().rtssa_network_info(self._h, C.byref(N), C.byref(M), C.byref(dep), C.byref(mp)))
+        return dict(N=N.value, M=M.value, dep_edges=dep.value, auto_mapping=mp.value)
+
+    @property
+    def handle(self):
+        return self._h
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h and _lib._lib is not None:
+            _lib._lib.rtssa_network_destroy(h)
+            self._h = None
+
+
+def simulate(net: Network, x0, t_end: float, sample_t, R: int, seed: int = 1, net_id: int = 0,
+             traj_offset: int = 0, max_firings: int = 10_000_000, mapping: int = MAP_AUTO,
+             block: int = 0, grid: int = 0, want=("samples", "n", "T", "x_final", "t_last",
+                                                  "status", "tie_step"),
+             with_hash: bool = False, stats: bool = True, out: Optional[dict] = None):
+    """Run R trajectories on the GPU; returns a dict of device tensors (+ 'stats').
+
+    x0 is [N] (shared) or [R, N] (per trajectory), host or device.  sample_t is
+    the sorted sample grid within [0, t_end].  ``want`` selects the outputs to
+    produce; ``out`` may supply preallocated tensors with the same keys."""
+    dev = net.device
+    N, M, R = net.N, net.M, int(R)
+    x0 = torch.as_tensor(np.asarray(x0) if not torch.is_tensor(x0) else x0, dtype=torch.int32)
+    if x0.numel() and int(x0.min()) < 0:
+        raise ValueError("initial counts must be >= 0")
+    x0 = x0.to(dev).contiguous()
+    per_traj = 1 if x0.dim() == 2 else 0
+    if per_traj and tuple(x0.shape) != (R, N):
+        raise ValueError("x0 must be [N] or [R, N]")
+    s = torch.as_tensor(np.asarray(sample_t, dtype=np.float64) if not torch.is_tensor(sample_t)
+                        else sample_t, dtype=torch.float64).to(dev).contiguous()
+    G = int(s.numel())
+    o = {} if out is None else dict(out)
+    shapes = dict(samples=((R, G, N), torch.int32), n=((R, M), torch.int32),
+                  T=((R, M), torch.float64), x_final=((R, N), torch.int32),
+                  t_last=((R,), torch.float64), status=((R,), torch.uint8),
+                  tie_step=((R,), torch.int32), seq_hash=((R,), torch.int64))
+    keys = set(want) | ({"seq_hash"} if with_hash else set())
+    for k in keys:
+        if k not in o:
+            shape, dt = shapes[k]
+            o[k] = torch.empty(shape, dtype=dt, device=dev)
+    smp = o.get("samples")
+    st_r, st_g, st_n = (smp.stride() if smp is not None else (0, 0, 0))
+    opt = Options(int(max_firings), int(mapping), int(block), int(grid), 0)
+    st = Stats()
+    with torch.cuda.device(dev):
+        check(lib().rtssa_simulate(net.handle, _ptr(x0), per_traj, float(t_end),
+                                   _ptr(s) if G else None, G, int(seed) & (2**64 - 1),
+                                   int(net_id), int(traj_offset), R, _ptr(smp), st_r, st_g, st_n,
+                                   _ptr(o.get("n")), _ptr(o.get("T")), _ptr(o.get("x_final")),
+                                   _ptr(o.get("t_last")), _ptr(o.get("status")),
+                                   _ptr(o.get("seq_hash")), _ptr(o.get("tie_step")),
+                                   C.byref(opt), _stream(dev), C.byref(st) if stats else None))
+    if stats:
+        o["stats"] = st.as_dict()
+    return o
+
+
+def score_grad(f: torch.Tensor, n: torch.Tensor, T: torch.Tensor, baseline: bool = True):
+    """Score-function estimate of d E[f] / d log c_k and its standard error."""
+    dev = f.device
+    R, M = int(n.shape[0]), int(n.shape[1])
+    f = f.to(torch.float64).contiguous()
+    n = n.contiguous()
+    T = T.to(torch.float64).contiguous()
+    grad = torch.empty(M, dtype=torch.float64, device=dev)
+    se = torch.empty(M, dtype=torch.float64, device=dev)
+    with torch.cuda.device(dev):
+        check(lib().rtssa_score_grad(_ptr(f), _ptr(n), _ptr(T), R, M, 1 if baseline else 0,
+                                     _ptr(grad), _ptr(se), _stream(dev)))
+    return grad, se
+
+
+class _Expectation(torch.autograd.Function):
+    """E[f(X_T)] as a differentiable function of log c (score-function backward)."""
+
+    @staticmethod
+    def forward(ctx, log_c, net, f, x0, t_end, R, seed, baseline):
+        c = torch.exp(log_c.detach().to(torch.float64)).cpu().numpy()
+        net.set_rates(c)
+        o = simulate(net, x0, t_end, [t_end], R, seed=seed, want=("x_final", "n", "T", "status"),
+                     stats=False)
+        fx = f(o["x_final"]).to(torch.float64)
+        ctx.save_for_backward(fx, o["n"], o["T"])
+        ctx.baseline = baseline
+        ctx.results = o
+        return fx.mean()
+
+    @staticmethod
+    def backward(ctx, grad_out):
+        fx, n, T = ctx.saved_tensors
+        g, _ = score_grad(fx, n, T, baseline=ctx.baseline)
+        return (grad_out.to(torch.float64) * g).to(grad_out.dtype), None, None, None, None, None, None, None
+
+
+def expectation(log_c: torch.Tensor, net: Network, f: Callable, x0, t_end: float, R: int,
+                seed: int = 1, baseline: bool = True) -> torch.Tensor:
+    """Monte-Carlo E[f(X(t_end))] over R trajectories; differentiable in log_c
+    through the score n_k - T_k(t_end) of each path."""
+    return _Expectation.apply(log_c, net, f, x0, t_end, R, seed, baseline)

@@ -1,0 +1,156 @@
+// kernels_misc.hip -- score-function gradient (backward) and test-hook kernels.
+#define RT_HD __device__ __forceinline__
+#define RT_LOG_CONST __constant__
+#include <hip/hip_runtime.h>
+#include <math.h>
+
+#include "internal.h"
+#include "rt_math.h"
+
+namespace {
+
+constexpr int kRedBlock = 256;
+
+// Deterministic block sum of f over a contiguous row chunk.
+__global__ __launch_bounds__(kRedBlock) void rt_sum_f_kernel(const double* f, int64_t R,
+                                                             int64_t chunk, double* part)
+{
+    __shared__ double sh[kRedBlock];
+    const int64_t r0 = (int64_t)blockIdx.x * chunk;
+    const int64_t r1 = r0 + chunk < R ? r0 + chunk : R;
+    double acc = 0.0;
+    for (int64_t r = r0 + threadIdx.x; r < r1; r += kRedBlock) acc += f[r];
+    sh[threadIdx.x] = acc;
+    __syncthreads();
+    for (int w = kRedBlock / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[blockIdx.x] = sh[0];
+}
+
+// Per block and channel: sum_r y_rk and sum_r y_rk^2 with
+// y_rk = (f_r - b_r)(n_rk - T_rk), b_r the leave-one-out mean of f.
+__global__ __launch_bounds__(kRedBlock) void rt_score_part_kernel(
+    const double* f, const uint32_t* n, const double* T, int64_t R, int32_t M,
+    int32_t baseline, int64_t chunk, const double* fpart, int nb, double* out)
+{
+    __shared__ double s1[kRedBlock], s2[kRedBlock];
+    double F = 0.0;
+    for (int b = 0; b < nb; ++b) F += fpart[b];
+    const double denom = R > 1 ? (double)(R - 1) : 1.0;
+    const int64_t r0 = (int64_t)blockIdx.x * chunk;
+    const int64_t r1 = r0 + chunk < R ? r0 + chunk : R;
+    const int kk = M < kRedBlock ? M : kRedBlock;
+    const int tpk = kRedBlock / kk;
+    const int tid = threadIdx.x;
+    for (int kb = 0; kb < M; kb += kk) {
+        const int k = kb + tid % kk;
+        const int q = tid / kk;
+        double a1 = 0.0, a2 = 0.0;
+        if (q < tpk && k < M) {
+            for (int64_t r = r0 + q; r < r1; r += tpk) {
+                const double fr = f[r];
+                const double b = baseline ? (F - fr) / denom : 0.0;
+                const double y = (fr - b) * ((double)n[r * M + k] - T[r * M + k]);
+                a1 += y;
+                a2 += y * y;
+            }
+        }
+        s1[tid] = a1;
+        s2[tid] = a2;
+        __syncthreads();
+        if (tid < kk && kb + tid < M) {
+            double t1 = 0.0, t2 = 0.0;
+            for (int qq = 0; qq < tpk; ++qq) { t1 += s1[qq * kk + tid]; t2 += s2[qq * kk + tid]; }
+            out[((int64_t)blockIdx.x * M + kb + tid) * 2 + 0] = t1;
+            out[((int64_t)blockIdx.x * M + kb + tid) * 2 + 1] = t2;
+        }
+        __syncthreads();
+    }
+}
+
+__global__ void rt_score_final_kernel(const double* part, int nb, int32_t M, int64_t R,
+                                      double* grad, double* se)
+{
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= M) return;
+    double t1 = 0.0, t2 = 0.0;
+    for (int b = 0; b < nb; ++b) {
+        t1 += part[((int64_t)b * M + k) * 2 + 0];
+        t2 += part[((int64_t)b * M + k) * 2 + 1];
+    }
+    const double Rd = (double)R;
+    grad[k] = t1 / Rd;
+    if (se) {
+        double var = R > 1 ? (t2 - t1 * (t1 / Rd)) / (Rd - 1.0) : 0.0;
+        se[k] = var > 0.0 ? sqrt(var / Rd) : 0.0;
+    }
+}
+
+__global__ void rt_debug_neglog_kernel(const uint64_t* m, double* out, uint8_t* slow,
+                                       int64_t count, int force)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= count) return;
+    bool s = false;
+    out[i] = rt_neglog_u53(m[i], force != 0, &s);
+    if (slow) slow[i] = s ? 1 : 0;
+}
+
+__global__ void rt_debug_philox_kernel(const uint32_t* ctr, uint32_t k0, uint32_t k1,
+                                       uint32_t* out, int64_t count)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= count) return;
+    rt_u4 c = {ctr[4 * i], ctr[4 * i + 1], ctr[4 * i + 2], ctr[4 * i + 3]};
+    rt_u4 w = rt_philox4x32_10(c, k0, k1);
+    out[4 * i] = w.x;
+    out[4 * i + 1] = w.y;
+    out[4 * i + 2] = w.z;
+    out[4 * i + 3] = w.w;
+}
+
+}  // namespace
+
+int rt_launch_score_grad(const double* f, const uint32_t* n, const double* T, int64_t R,
+                         int32_t M, int32_t baseline, double* grad, double* se,
+                         hipStream_t stream)
+{
+    int nb = (int)((R + 4095) / 4096);
+    if (nb > 256) nb = 256;
+    if (nb < 1) nb = 1;
+    const int64_t chunk = (R + nb - 1) / nb;
+    double* buf = nullptr;
+    const size_t bytes = sizeof(double) * ((size_t)nb + (size_t)nb * M * 2);
+    if (hipMallocAsync((void**)&buf, bytes, stream) != hipSuccess)
+        return rt_fail(RTSSA_E_NOMEM, "score workspace allocation failed");
+    double* fpart = buf;
+    double* part = buf + nb;
+    hipLaunchKernelGGL(rt_sum_f_kernel, dim3(nb), dim3(kRedBlock), 0, stream, f, R, chunk, fpart);
+    hipLaunchKernelGGL(rt_score_part_kernel, dim3(nb), dim3(kRedBlock), 0, stream, f, n, T, R, M,
+                       baseline, chunk, fpart, nb, part);
+    hipLaunchKernelGGL(rt_score_final_kernel, dim3((M + 255) / 256), dim3(256), 0, stream, part,
+                       nb, M, R, grad, se);
+    hipError_t e = hipGetLastError();
+    hipFreeAsync(buf, stream);
+    return e == hipSuccess ? RTSSA_OK : rt_fail(RTSSA_E_HIP, "score kernel launch failed");
+}
+
+int rt_launch_debug_neglog(const uint64_t* m, double* out, uint8_t* slow, int64_t count,
+                           int force, hipStream_t stream)
+{
+    if (count <= 0) return RTSSA_OK;
+    hipLaunchKernelGGL(rt_debug_neglog_kernel, dim3((unsigned)((count + 255) / 256)), dim3(256), 0,
+                       stream, m, out, slow, count, force);
+    return hipGetLastError() == hipSuccess ? RTSSA_OK : rt_fail(RTSSA_E_HIP, "launch failed");
+}
+
+int rt_launch_debug_philox(const uint32_t* ctr, uint32_t k0, uint32_t k1, uint32_t* out,
+                           int64_t count, hipStream_t stream)
+{
+    if (count <= 0) return RTSSA_OK;
+    hipLaunchKernelGGL(rt_debug_philox_kernel, dim3((unsigned)((count + 255) / 256)), dim3(256), 0,
+                       stream, ctr, k0, k1, out, count);
+    return hipGetLastError() == hipSuccess ? RTSSA_OK : rt_fail(RTSSA_E_HIP, "launch failed");
+}

@@ -1,0 +1,216 @@
+// network.cpp -- host-side network compiler: validation and device tables.
+//
+// The paper stores the reactant, stoichiometric and update matrices as sparse
+// COO lists and limits reactions to two reactant molecules so the tables fit
+// on-chip (section 5).  Here a reaction becomes one 8-byte reactant record
+// (kind, s0, s1), the net change v_k a short (species, delta) list, and the
+// dependency graph D(mu) -- the channels whose propensity reads a species
+// that mu changes (Gibson & Bruck, cited in section 5) -- a CSR list.
+#include <math.h>
+#include <string.h>
+
+#include <algorithm>
+#include <map>
+#include <set>
+
+#include "internal.h"
+
+static int validate_rate(double c, int k)
+{
+    if (!(c >= 0.0) || !isfinite(c) || (c != 0.0 && (c < 1e-280 || c > 1e280)))
+        return rt_fail(RTSSA_E_INVALID, "rate c[" + std::to_string(k) +
+                       "] must be 0 or within [1e-280, 1e280]");
+    return RTSSA_OK;
+}
+
+static int upload(rtssa_network* n)
+{
+    // one device allocation; each table 256-byte aligned
+    struct part { const void* src; size_t bytes; size_t off; };
+    std::vector<part> parts = {
+        {n->react.data(), n->react.size() * sizeof(int2), 0},
+        {n->c.data(), n->c.size() * sizeof(double), 0},
+        {n->nu_ptr.data(), n->nu_ptr.size() * sizeof(int32_t), 0},
+        {n->nu_sp.data(), n->nu_sp.size() * sizeof(int32_t), 0},
+        {n->nu_dl.data(), n->nu_dl.size() * sizeof(int32_t), 0},
+        {n->dep_ptr.data(), n->dep_ptr.size() * sizeof(int32_t), 0},
+        {n->dep_idx.data(), n->dep_idx.size() * sizeof(int32_t), 0},
+        {n->nu_dense.data(), n->nu_dense.size() * sizeof(int32_t), 0},
+    };
+    size_t off = 0;
+    for (auto& p : parts) {
+        p.off = off;
+        off += (p.bytes + 255) / 256 * 256 + 256;
+    }
+    if (hipGetDevice(&n->device) != hipSuccess) return rt_fail(RTSSA_E_HIP, "hipGetDevice failed");
+    if (hipMalloc(&n->dev_block, off) != hipSuccess) {
+        n->dev_block = nullptr;
+        return rt_fail(RTSSA_E_NOMEM, "device allocation of network tables failed");
+    }
+    char* base = (char*)n->dev_block;
+    for (auto& p : parts)
+        if (p.bytes && hipMemcpy(base + p.off, p.src, p.bytes, hipMemcpyHostToDevice) != hipSuccess)
+            return rt_fail(RTSSA_E_HIP, "copy of network tables failed");
+    n->dev.N = n->N;
+    n->dev.M = n->M;
+    n->dev.react = (const int2*)(base + parts[0].off);
+    n->dev.c = (const double*)(base + parts[1].off);
+    n->dev.nu_ptr = (const int32_t*)(base + parts[2].off);
+    n->dev.nu_sp = (const int32_t*)(base + parts[3].off);
+    n->dev.nu_dl = (const int32_t*)(base + parts[4].off);
+    n->dev.dep_ptr = (const int32_t*)(base + parts[5].off);
+    n->dev.dep_idx = (const int32_t*)(base + parts[6].off);
+    n->dev.nu_dense = n->nu_dense.empty() ? nullptr : (const int32_t*)(base + parts[7].off);
+    return RTSSA_OK;
+}
+
+extern "C" int rtssa_network_create(int32_t N, int32_t M, const int32_t* react_ptr,
+                                    const int32_t* react_species, const int32_t* react_sigma,
+                                    const int32_t* prod_ptr, const int32_t* prod_species,
+                                    const int32_t* prod_mult, const double* c,
+                                    rtssa_network** out)
+{
+    if (!out) return rt_fail(RTSSA_E_INVALID, "out is NULL");
+    *out = nullptr;
+    if (N < 0 || M < 0 || N > RT_SPECIES_MASK)
+        return rt_fail(RTSSA_E_INVALID, "N and M must be >= 0 and N < 2^29");
+    if (!react_ptr || !prod_ptr || (M > 0 && !c))
+        return rt_fail(RTSSA_E_INVALID, "react_ptr, prod_ptr and c must not be NULL");
+    if (react_ptr[0] != 0 || prod_ptr[0] != 0)
+        return rt_fail(RTSSA_E_INVALID, "react_ptr[0] and prod_ptr[0] must be 0");
+    for (int k = 0; k < M; ++k)
+        if (react_ptr[k + 1] < react_ptr[k] || prod_ptr[k + 1] < prod_ptr[k])
+            return rt_fail(RTSSA_E_INVALID, "offsets must be non-decreasing");
+    if ((react_ptr[M] > 0 && (!react_species || !react_sigma)) ||
+        (prod_ptr[M] > 0 && (!prod_species || !prod_mult)))
+        return rt_fail(RTSSA_E_INVALID, "species/coefficient arrays must not be NULL");
+
+    rtssa_network* n = new rtssa_network();
+    n->N = N;
+    n->M = M;
+    n->react.resize(std::max(M, 1));
+    n->c.assign(std::max(M, 1), 0.0);
+    n->nu_ptr.assign(M + 1, 0);
+    std::vector<std::vector<int>> readers(N);   // species -> channels reading it
+    std::vector<std::vector<std::pair<int, int>>> nu(M);
+    for (int k = 0; k < M; ++k) {
+        int rc = validate_rate(c[k], k);
+        if (rc) { delete n; return rc; }
+        n->c[k] = c[k];
+        int order = 0, sp[2] = {-1, -1}, sg[2] = {0, 0}, cnt = 0;
+        std::map<int, int> delta;
+        for (int e = react_ptr[k]; e < react_ptr[k + 1]; ++e) {
+            int j = react_species[e], s = react_sigma[e];
+            if (j < 0 || j >= N || s < 1) {
+                delete n;
+                return rt_fail(RTSSA_E_INVALID, "reaction " + std::to_string(k) +
+                               ": bad reactant species or coefficient");
+            }
+            for (int q = 0; q < cnt; ++q)
+                if (sp[q] == j) {
+                    delete n;
+                    return rt_fail(RTSSA_E_INVALID, "reaction " + std::to_string(k) +
+                                   ": repeated reactant species (give one entry with its coefficient)");
+                }
+            order += s;
+            if (order > 2) {
+                delete n;
+                return rt_fail(RTSSA_E_UNSUPPORTED, "reaction " + std::to_string(k) +
+                               ": more than two reactant molecules");
+            }
+            sp[cnt] = j;
+            sg[cnt] = s;
+            cnt++;
+            delta[j] -= s;
+        }
+        int kind = RT_H_ZERO, s0 = 0, s1 = 0;
+        if (cnt == 1 && sg[0] == 1) { kind = RT_H_ONE; s0 = sp[0]; }
+        else if (cnt == 1 && sg[0] == 2) { kind = RT_H_PAIR; s0 = sp[0]; }
+        else if (cnt == 2) { kind = RT_H_TWO; s0 = sp[0]; s1 = sp[1]; }
+        n->react[k] = make_int2(s0 | (kind << 29), s1);
+        for (int q = 0; q < cnt; ++q) readers[sp[q]].push_back(k);
+        for (int e = prod_ptr[k]; e < prod_ptr[k + 1]; ++e) {
+            int j = prod_species[e], m = prod_mult[e];
+            if (j < 0 || j >= N || m < 1 || m > (1 << 20)) {
+                delete n;
+                return rt_fail(RTSSA_E_INVALID, "reaction " + std::to_string(k) +
+                               ": bad product species or multiplicity");
+            }
+            delta[j] += m;
+        }
+        for (auto& kv : delta)
+            if (kv.second != 0) nu[k].push_back(kv);
+    }
+    if (M == 0) n->react[0] = make_int2(0, 0);
+    // net change lists
+    for (int k = 0; k < M; ++k) {
+        n->nu_ptr[k] = (int)n->nu_sp.size();
+        for (auto& kv : nu[k]) { n->nu_sp.push_back(kv.first); n->nu_dl.push_back(kv.second); }
+        n->max_nu = std::max<int32_t>(n->max_nu, (int32_t)nu[k].size());
+    }
+    n->nu_ptr[M] = (int)n->nu_sp.size();
+    if (n->nu_sp.empty()) { n->nu_sp.push_back(0); n->nu_dl.push_back(0); }
+    // dependency graph
+    n->dep_ptr.assign(M + 1, 0);
+    for (int k = 0; k < M; ++k) {
+        std::set<int> d;
+        for (auto& kv : nu[k])
+            for (int r : readers[kv.first]) d.insert(r);
+        n->dep_ptr[k] = (int)n->dep_idx.size();
+        for (int r : d) n->dep_idx.push_back(r);
+        n->max_dep = std::max<int32_t>(n->max_dep, (int32_t)d.size());
+    }
+    n->dep_ptr[M] = (int)n->dep_idx.size();
+    if (n->dep_idx.empty()) n->dep_idx.push_back(0);
+    // dense net change for small networks
+    if (M <= RT_THREAD_MAX_M && N <= RT_THREAD_MAX_N && M > 0 && N > 0) {
+        n->nu_dense.assign((size_t)M * N, 0);
+        for (int k = 0; k < M; ++k)
+            for (auto& kv : nu[k]) n->nu_dense[(size_t)k * N + kv.first] = kv.second;
+    }
+    int rc = upload(n);
+    if (rc) { rtssa_network_destroy(n); return rc; }
+    *out = n;
+    return RTSSA_OK;
+}
+
+extern "C" int rtssa_network_destroy(rtssa_network* net)
+{
+    if (!net) return RTSSA_OK;
+    if (net->dev_block) {
+        int cur = -1;
+        hipGetDevice(&cur);
+        if (net->device >= 0 && cur != net->device) hipSetDevice(net->device);
+        hipFree(net->dev_block);
+        if (cur >= 0 && cur != net->device) hipSetDevice(cur);
+    }
+    delete net;
+    return RTSSA_OK;
+}
+
+extern "C" int rtssa_network_set_rates(rtssa_network* net, const double* c)
+{
+    if (!net || (!c && net->M > 0)) return rt_fail(RTSSA_E_INVALID, "NULL argument");
+    for (int k = 0; k < net->M; ++k) {
+        int rc = validate_rate(c[k], k);
+        if (rc) return rc;
+    }
+    for (int k = 0; k < net->M; ++k) net->c[k] = c[k];
+    if (net->M > 0 &&
+        hipMemcpy((void*)net->dev.c, net->c.data(), sizeof(double) * net->M,
+                  hipMemcpyHostToDevice) != hipSuccess)
+        return rt_fail(RTSSA_E_HIP, "copy of rates failed");
+    return RTSSA_OK;
+}
+
+extern "C" int rtssa_network_info(const rtssa_network* net, int32_t* N, int32_t* M,
+                                  int64_t* dep_edges, int32_t* auto_mapping)
+{
+    if (!net) return rt_fail(RTSSA_E_INVALID, "net is NULL");
+    if (N) *N = net->N;
+    if (M) *M = net->M;
+    if (dep_edges) *dep_edges = net->dep_ptr.empty() ? 0 : net->dep_ptr[net->M];
+    if (auto_mapping) *auto_mapping = rt_thread_supported(net->M, net->N) ? RTSSA_MAP_THREAD
+                                                                          : RTSSA_MAP_WAVE;
+    return RTSSA_OK;
+}

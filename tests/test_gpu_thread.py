@@ -1,0 +1,216 @@
+"""GPU parity of the thread-per-trajectory mapping against the CPU oracle.
+
+Bit-exact comparison of every output (sampled states, firing counts,
+internal times, final states, last event times, end states, firing-sequence
+hashes, first near-tie indices and the aggregate counters) on the same seeded
+inputs; at the full ensemble size the oracle recomputes spread blocks of
+trajectories and every trajectory is checked against Eq. 5.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2103_00405_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def _api():
+    from paper_2103_00405_amd import api
+    return api
+
+
+def _np(t):
+    return t.cpu().numpy()
+
+
+def _run_both(spec, x0, t_end, grid, R, seed=1, net_id=0, traj_offset=0, max_firings=10**7,
+              **kw):
+    api = _api()
+    net = api.Network(spec)
+    g = api.simulate(net, x0, t_end, grid, R, seed=seed, net_id=net_id, traj_offset=traj_offset,
+                     max_firings=max_firings, with_hash=True, **kw)
+    torch.cuda.synchronize()
+    ref = oracle.simulate(spec, x0, t_end, grid, seed, R, net_id=net_id, traj_offset=traj_offset,
+                          max_firings=max_firings)
+    return g, ref
+
+
+def _assert_same(g, ref, check_stats=True):
+    assert np.array_equal(_np(g["samples"]), ref["samples"])
+    assert np.array_equal(_np(g["n"]).view(np.uint32), ref["n"])
+    assert np.array_equal(_np(g["T"]).view(np.uint64), ref["T"].view(np.uint64))
+    assert np.array_equal(_np(g["x_final"]), ref["x_final"])
+    assert np.array_equal(_np(g["t_last"]).view(np.uint64), ref["t_last"].view(np.uint64))
+    assert np.array_equal(_np(g["status"]), ref["status"])
+    assert np.array_equal(_np(g["seq_hash"]).view(np.uint64), ref["seq_hash"])
+    assert np.array_equal(_np(g["tie_step"]).view(np.uint32), ref["tie_step"])
+    if check_stats:
+        gs, rs = g["stats"], ref["stats"]
+        assert gs["firings"] == rs["firings"]
+        assert gs["near_ties"] == rs["near_ties"]
+        assert gs["clamps"] == rs["clamps"]
+        assert gs["status_count"] == rs["status_count"]
+
+
+def test_lv_small_every_trajectory_bit_exact():
+    w = W.lv_small()
+    g, ref = _run_both(w.net, w.x0, w.t_end, w.sample_t, w.R, seed=w.seed)
+    _assert_same(g, ref)
+    assert g["stats"]["mapping"] == _api().MAP_THREAD
+    assert ref["stats"]["firings"] > 1_000_000
+
+
+@pytest.mark.parametrize("seed", [11, 12, 13, 14, 15, 16])
+def test_random_small_networks_bit_exact(seed):
+    rng = np.random.default_rng(seed)
+    M = int(rng.integers(1, 9))
+    N = int(rng.integers(1, 9))
+    spec = W.random_network(N, M, rng, logc=(-1.0, 1.0), bimol_scale=0.05)
+    x0 = rng.integers(0, 60, size=N).astype(np.int32)
+    t_end = 2.0
+    grid = np.sort(rng.uniform(0, t_end, size=17))
+    g, ref = _run_both(spec, x0, t_end, grid, 300, seed=seed, net_id=seed)
+    _assert_same(g, ref)
+
+
+def test_homodimer_and_bimolecular_channels():
+    g, ref = _run_both(W.dimerisation(0.05, 1.0), np.array([300, 20], np.int32), 3.0,
+                       W.uniform_grid(3.0, 31), 500, seed=5)
+    _assert_same(g, ref)
+
+
+def test_birth_death_gradient_config_bit_exact():
+    w = W.bd_gradient(R=4096)
+    g, ref = _run_both(w.net, w.x0, w.t_end, w.sample_t, w.R, seed=w.seed)
+    _assert_same(g, ref)
+
+
+def test_edge_cases():
+    # empty network: every trajectory is absorbed at t = 0
+    spec0 = W.from_reactions(2, [])
+    g, ref = _run_both(spec0, np.array([3, 4], np.int32), 1.0, [0.0, 1.0], 5)
+    _assert_same(g, ref)
+    assert (_np(g["status"]) == 1).all()
+    # no species: 0 -> 0 fires at a constant rate
+    spec1 = W.from_reactions(0, [({}, {}, 7.0)])
+    g, ref = _run_both(spec1, np.zeros(0, np.int32), 2.0, [1.0], 64)
+    _assert_same(g, ref)
+    # t_end = 0 and an empty sample grid
+    w = W.lv_small(8)
+    g, ref = _run_both(w.net, w.x0, 0.0, [0.0], 8)
+    _assert_same(g, ref)
+    g, ref = _run_both(w.net, w.x0, 3.0, np.zeros(0), 8)
+    _assert_same(g, ref)
+    # overflow stops before the jump
+    spec2 = W.from_reactions(1, [({0: 1}, {0: 2}, 1.0)])
+    g, ref = _run_both(spec2, np.array([2**31 - 10], np.int32), 100.0, [1e-12, 100.0], 7)
+    _assert_same(g, ref)
+    assert (_np(g["status"]) == 2).all()
+    # firing cap
+    g, ref = _run_both(w.net, w.x0, w.t_end, w.sample_t, 8, max_firings=777)
+    _assert_same(g, ref)
+    assert (_np(g["status"]) == 3).all()
+    # absorbing start
+    g, ref = _run_both(W.pure_death(1.0), np.array([0], np.int32), 5.0, [0.0, 5.0], 3)
+    _assert_same(g, ref)
+
+
+def test_per_trajectory_initial_states():
+    w = W.lv_small(200)
+    rng = np.random.default_rng(3)
+    x0 = rng.integers(0, 150, size=(200, 2)).astype(np.int32)
+    g, ref = _run_both(w.net, x0, 5.0, W.uniform_grid(5.0, 11), 200)
+    _assert_same(g, ref)
+
+
+def test_schedule_independence():
+    """Identical bits for any block size, grid size, trajectory split or sample layout."""
+    api = _api()
+    w = W.lv_small(300)
+    net = api.Network(w.net)
+    base = api.simulate(net, w.x0, 8.0, W.uniform_grid(8.0, 9), 300, with_hash=True)
+    for block, grid in ((64, 1), (128, 3), (256, 0), (192, 2)):
+        o = api.simulate(net, w.x0, 8.0, W.uniform_grid(8.0, 9), 300, with_hash=True, block=block,
+                         grid=grid)
+        for k in ("samples", "n", "T", "x_final", "seq_hash", "status"):
+            assert torch.equal(o[k], base[k]), (block, grid, k)
+    a = api.simulate(net, w.x0, 8.0, W.uniform_grid(8.0, 9), 120, traj_offset=0, with_hash=True)
+    b = api.simulate(net, w.x0, 8.0, W.uniform_grid(8.0, 9), 180, traj_offset=120, with_hash=True)
+    for k in ("samples", "n", "T", "seq_hash"):
+        assert torch.equal(torch.cat([a[k], b[k]]), base[k]), k
+    # samples written through transposed strides ([G][N][R] storage)
+    st = torch.empty((9, 2, 300), dtype=torch.int32, device="cuda")
+    o = api.simulate(net, w.x0, 8.0, W.uniform_grid(8.0, 9), 300,
+                     out={"samples": st.permute(2, 0, 1)})
+    assert torch.equal(st.permute(2, 0, 1), base["samples"])
+
+
+def test_full_ensemble_bench_configuration():
+    """The ensemble-throughput workload at full size (2^20 trajectories) in the
+    launch configuration the benchmark times: spread blocks bit-exact against
+    the oracle, Eq. 5 on every trajectory."""
+    api = _api()
+    w = W.lv_ensemble()
+    net = api.Network(w.net)
+    g = api.simulate(net, w.x0, w.t_end, w.sample_t, w.R, seed=w.seed,
+                     want=("samples", "n", "T", "x_final", "status"))
+    torch.cuda.synchronize()
+    st = g["stats"]
+    assert st["firings"] == int(g["n"].to(torch.int64).sum())
+    # Eq. 5: X(t_end) = x0 + sum_k n_k v_k for every trajectory
+    nu = torch.tensor([[1, 0], [-1, 1], [0, -1]], dtype=torch.int64, device="cuda")
+    pred = torch.tensor(w.x0, dtype=torch.int64, device="cuda") + g["n"].to(torch.int64) @ nu
+    assert torch.equal(pred, g["x_final"].to(torch.int64))
+    ok = g["status"] <= 1
+    assert torch.equal(g["samples"][ok][:, -1, :], g["x_final"][ok])
+    # spread blocks recomputed by the oracle
+    for off in (0, 333_331, 777_777, w.R - 40):
+        ref = oracle.simulate(w.net, w.x0, w.t_end, w.sample_t, w.seed, 40, traj_offset=off)
+        sl = slice(off, off + 40)
+        assert np.array_equal(_np(g["samples"][sl]), ref["samples"])
+        assert np.array_equal(_np(g["n"][sl]).view(np.uint32), ref["n"])
+        assert np.array_equal(_np(g["T"][sl]).view(np.uint64), ref["T"].view(np.uint64))
+        assert np.array_equal(_np(g["status"][sl]), ref["status"])
+
+
+def test_device_neglog_and_philox_match():
+    api = _api()
+    from paper_2103_00405_amd._lib import lib, check
+    import ctypes as C
+    rng = np.random.default_rng(7)
+    m = rng.integers(0, 2**53, size=1 << 20, dtype=np.uint64)
+    m[:4] = [0, 2**53 - 1, 2**53 - 3, 2**52 - 1]
+    md = torch.from_numpy(m.view(np.int64)).cuda()
+    out = torch.empty(m.size, dtype=torch.float64, device="cuda")
+    slow = torch.empty(m.size, dtype=torch.uint8, device="cuda")
+    stream = C.c_void_p(torch.cuda.current_stream().cuda_stream)
+    check(lib().rtssa_debug_neglog(C.c_void_p(md.data_ptr()), C.c_void_p(out.data_ptr()),
+                                   C.c_void_p(slow.data_ptr()), m.size, 0, stream))
+    o = out.cpu().numpy()
+    L = lib()
+    s = C.c_int32()
+    for i in list(range(0, m.size, 97)) + [0, 1, 2, 3]:
+        assert o[i] == L.rtssa_debug_neglog_host(int(m[i]), 0, C.byref(s)), i
+    for i in range(0, m.size, 4099):
+        v = oracle.neglog_u53(int(m[i]))
+        if v >= 0:
+            assert o[i] == v, i
+    # accurate phase on the device
+    check(lib().rtssa_debug_neglog(C.c_void_p(md.data_ptr()), C.c_void_p(out.data_ptr()),
+                                   C.c_void_p(slow.data_ptr()), 4096, 1, stream))
+    o = out[:4096].cpu().numpy()
+    sl = slow[:4096].cpu().numpy()
+    assert sl[1] == 0 and (np.delete(sl, 1) == 1).all()   # m[1] is u = 1, answered exactly
+    for i in range(4096):
+        assert o[i] == L.rtssa_debug_neglog_host(int(m[i]), 1, C.byref(s)), i
+    # Philox blocks
+    ctr = rng.integers(0, 2**32, size=(5000, 4), dtype=np.uint64).astype(np.uint32)
+    cd = torch.from_numpy(ctr.view(np.int32)).cuda()
+    od = torch.empty((5000, 4), dtype=torch.int32, device="cuda")
+    check(lib().rtssa_debug_philox(C.c_void_p(cd.data_ptr()), 0x1234, 0xABCD,
+                                   C.c_void_p(od.data_ptr()), 5000, stream))
+    got = od.cpu().numpy().view(np.uint32)
+    for i in range(0, 5000, 7):
+        assert np.array_equal(got[i], oracle.philox4x32_10(ctr[i], [0x1234, 0xABCD]))
