@@ -161,7 +161,8 @@ def test_full_ensemble_bench_configuration():
     assert st["firings"] == int(g["n"].to(torch.int64).sum())
     # Eq. 5: X(t_end) = x0 + sum_k n_k v_k for every trajectory
     nu = torch.tensor([[1, 0], [-1, 1], [0, -1]], dtype=torch.int64, device="cuda")
-    pred = torch.tensor(w.x0, dtype=torch.int64, device="cuda") + g["n"].to(torch.int64) @ nu
+    pred = torch.tensor(w.x0, dtype=torch.int64, device="cuda") + \
+        (g["n"].to(torch.int64)[:, :, None] * nu[None]).sum(1)
     assert torch.equal(pred, g["x_final"].to(torch.int64))
     ok = g["status"] <= 1
     assert torch.equal(g["samples"][ok][:, -1, :], g["x_final"][ok])
