@@ -158,6 +158,7 @@ class _Expectation(torch.autograd.Function):
         fx = f(o["x_final"]).to(torch.float64)
         ctx.save_for_backward(fx, o["n"], o["T"])
         ctx.baseline = baseline
+        ctx.param_device = log_c.device
         ctx.results = o
         return fx.mean()
 
@@ -165,7 +166,8 @@ class _Expectation(torch.autograd.Function):
     def backward(ctx, grad_out):
         fx, n, T = ctx.saved_tensors
         g, _ = score_grad(fx, n, T, baseline=ctx.baseline)
-        return (grad_out.to(torch.float64) * g).to(grad_out.dtype), None, None, None, None, None, None, None
+        g = g.to(ctx.param_device)
+        return (grad_out.to(torch.float64).to(g.device) * g), None, None, None, None, None, None, None
 
 
 def expectation(log_c: torch.Tensor, net: Network, f: Callable, x0, t_end: float, R: int,
