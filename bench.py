@@ -39,6 +39,9 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--block", type=int, default=0)
     ap.add_argument("--grid", type=int, default=0)
+    ap.add_argument("--calibrate-copy-mib", type=int, default=0,
+                    help="after the timed steps, run one device copy of this size so that "
+                         "profiler byte counters can be scaled against known traffic")
     return ap.parse_args()
 
 
@@ -136,6 +139,13 @@ def main():
         "near_ties": st["near_ties"],
         "slow_logs": st["slow_logs"],
     }
+    if args.calibrate_copy_mib:
+        nb = args.calibrate_copy_mib << 20
+        src = torch.ones(nb // 4, dtype=torch.int32, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        res["calibration_copy_bytes"] = nb
     if not args.no_cpu_baseline:
         res["cpu_baseline"] = cpu_baseline(w, args.cpu_seconds)
     print(json.dumps(res), flush=True)

@@ -8,7 +8,7 @@ import ctypes as C
 import os
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "librtssa.so")
+LIB_PATH = os.environ.get("RTSSA_LIB") or os.path.join(HERE, "librtssa.so")
 
 _lib = None
 

@@ -77,9 +77,12 @@ class Network:
 
     def __del__(self):
         h = getattr(self, "_h", None)
-        if h and _lib._lib is not None:
-            _lib._lib.rtssa_network_destroy(h)
-            self._h = None
+        try:
+            if h and _lib._lib is not None:
+                _lib._lib.rtssa_network_destroy(h)
+        except Exception:      # interpreter shutdown: module globals may be gone
+            pass
+        self._h = None
 
 
 def simulate(net: Network, x0, t_end: float, sample_t, R: int, seed: int = 1, net_id: int = 0,

@@ -101,7 +101,7 @@ extern "C" int rtssa_simulate(const rtssa_network* net, const int32_t* x0, int32
         hipEventCreate(&ev0);
         hipEventCreate(&ev1);
     }
-    rc = rt_launch_zero_ws(ws, stream);
+    rc = rt_launch_zero_ws(ws, &p, stream);
     if (!rc && stats) hipEventRecord(ev0, stream);
     int grid_used = 0, block_used = o.block;
     if (!rc) {

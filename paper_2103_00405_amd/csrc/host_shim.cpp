@@ -10,7 +10,8 @@
 extern "C" double rtssa_debug_neglog_host(uint64_t m, int32_t force_accurate, int32_t* slow)
 {
     bool s = false;
-    double v = rt_neglog_u53(m, force_accurate != 0, &s);
+    uint32_t sc[RT_LOG_SCRATCH];
+    double v = rt_neglog_u53(m, force_accurate != 0, &s, sc);
     if (slow) *slow = s ? 1 : 0;
     return v;
 }

@@ -1,6 +1,7 @@
 // internal.h -- library-internal types shared by the host code and the kernels.
 #pragma once
 #include <hip/hip_runtime.h>
+#include <stddef.h>
 #include <stdint.h>
 
 #include <string>
@@ -45,12 +46,13 @@ struct rtssa_network {
     rt_net_dev dev{};
 };
 
-// Counters written by the kernels (device workspace).
-struct rt_ws {
-    unsigned long long firings, near_ties, clamps, slow_logs;
-    unsigned long long status_count[4];
-    unsigned long long next_traj;   // work-queue head of persistent kernels
-    unsigned long long pad[7];
+
+// Fields the per-firing path reads; passed by value.
+struct rt_hot_params {
+    double t_end;
+    uint32_t key0, key1, net_id, traj_offset;
+    uint32_t max_firings;
+    int32_t pad;
 };
 
 struct rt_sim_params {
@@ -71,7 +73,18 @@ struct rt_sim_params {
     uint8_t* status;
     unsigned long long* seq_hash;
     uint32_t* tie_step;
-    rt_ws* ws;
+    struct rt_ws* ws;
+};
+
+// Device workspace: counters written by the kernels, the work-queue head of
+// the persistent kernels, and a copy of the launch parameters that rare code
+// paths read through a pointer (keeping them out of scalar registers).
+struct rt_ws {
+    unsigned long long firings, near_ties, clamps, slow_logs;
+    unsigned long long status_count[4];
+    unsigned long long next_traj;
+    unsigned long long pad[7];
+    rt_sim_params params;
 };
 
 // error reporting (api.cpp)
@@ -80,7 +93,7 @@ int rt_fail(int code, const std::string& msg);
 // kernels.hip
 int rt_launch_thread(const rtssa_network* net, const rt_sim_params& p, int block, int grid,
                      hipStream_t stream, int* grid_used);
-int rt_launch_zero_ws(rt_ws* ws, hipStream_t stream);
+int rt_launch_zero_ws(rt_ws* ws, const rt_sim_params* params, hipStream_t stream);
 int rt_launch_score_grad(const double* f, const uint32_t* n, const double* T, int64_t R,
                          int32_t M, int32_t baseline, double* grad, double* se,
                          hipStream_t stream);

@@ -1,11 +1,9 @@
 // kernels_misc.hip -- score-function gradient (backward) and test-hook kernels.
-#define RT_HD __device__ __forceinline__
-#define RT_LOG_CONST __constant__
 #include <hip/hip_runtime.h>
 #include <math.h>
 
 #include "internal.h"
-#include "rt_math.h"
+#include "rt_device.h"
 
 namespace {
 
@@ -88,14 +86,18 @@ __global__ void rt_score_final_kernel(const double* part, int nb, int32_t M, int
     }
 }
 
-__global__ void rt_debug_neglog_kernel(const uint64_t* m, double* out, uint8_t* slow,
-                                       int64_t count, int force)
+__global__ __launch_bounds__(256) void rt_debug_neglog_kernel(const uint64_t* m, double* out,
+                                                               uint8_t* slow, int64_t count,
+                                                               int force)
 {
+    __shared__ uint32_t log_scratch[4][RT_LOG_SCRATCH];
+    __shared__ unsigned long long slow_count[256];
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= count) return;
-    bool s = false;
-    out[i] = rt_neglog_u53(m[i], force != 0, &s);
-    if (slow) slow[i] = s ? 1 : 0;
+    slow_count[threadIdx.x] = 0ull;
+    out[i] = rt_neglog_wave(m[i], force != 0, &slow_count[threadIdx.x],
+                            log_scratch[threadIdx.x >> 6]);
+    if (slow) slow[i] = slow_count[threadIdx.x] ? 1 : 0;
 }
 
 __global__ void rt_debug_philox_kernel(const uint32_t* ctr, uint32_t k0, uint32_t k1,

@@ -9,12 +9,10 @@
 // The step is the next reaction random time algorithm (section 4, Table 2)
 // in the internal-time form of Eq. 14-16: gaps (P_k - T_k)/a_k, argmin
 // (Eq. 25), internal-time advance, jump, and one fresh Exp(1) (Eq. 26).
-#define RT_HD __device__ __forceinline__
-#define RT_LOG_CONST __constant__
 #include <hip/hip_runtime.h>
 
 #include "internal.h"
-#include "rt_math.h"
+#include "rt_device.h"
 
 namespace {
 
@@ -56,9 +54,15 @@ __device__ __forceinline__ double propensity(int kind, int s0, int s1, double c,
     return c * u64_to_f64(h);
 }
 
+#ifndef RT_THREAD_MIN_WAVES
+#define RT_THREAD_MIN_WAVES 4
+#endif
+
 template <int MT, int NT>
-__global__ __launch_bounds__(256) void rt_thread_kernel(rt_sim_params P, rt_net_dev net)
+__global__ __launch_bounds__(256, RT_THREAD_MIN_WAVES) void rt_thread_kernel(
+    rt_hot_params H, rt_ws* __restrict__ ws, rt_net_dev net)
 {
+    const rt_sim_params& P = ws->params;   // read only on rare paths
     // ---- network, uniform across the grid
     int kind[MT], s0[MT], s1[MT], nu[MT][NT];
     double c[MT];
@@ -78,91 +82,39 @@ __global__ __launch_bounds__(256) void rt_thread_kernel(rt_sim_params P, rt_net_
             nu[k][j] = (k < net.M && j < net.N) ? net.nu_dense[k * net.N + j] : 0;
     }
     const int N = net.N, M = net.M;
-    const bool want_hash = P.seq_hash != nullptr;
+    const bool want_hash = ws->params.seq_hash != nullptr;
+    __shared__ uint32_t log_scratch[4][RT_LOG_SCRATCH];     // one slice per wave
+    uint32_t* sc = log_scratch[threadIdx.x >> 6];
 
-    // ---- lane counters
-    unsigned long long c_fired = 0, c_ties = 0, c_clamps = 0, c_slow = 0;
-    unsigned long long c_st[4] = {0, 0, 0, 0};
-
+    // counters live in the device workspace and change only on rare events
     // ---- trajectory state
     int32_t X[NT];
     double T[MT], Pk[MT], a[MT], inv[MT];
     uint32_t n[MT];
+#pragma unroll
+    for (int j = 0; j < NT; ++j) X[j] = 0;
+#pragma unroll
+    for (int k = 0; k < MT; ++k) { T[k] = 0.0; Pk[k] = 0.0; a[k] = 0.0; inv[k] = 0.0; n[k] = 0; }
     double t = 0.0, s_next = 0.0;
     int32_t g = 0;
     uint32_t fired = 0, tie = kTieNone, traj = 0;
     unsigned long long hash = kFnvOffset;
     int64_t r = 0;
 
-    auto refresh_rates = [&]() {
-#pragma unroll
-        for (int k = 0; k < MT; ++k) {
-            a[k] = propensity<NT>(kind[k], s0[k], s1[k], c[k], X);
-            inv[k] = a[k] > 0.0 ? 1.0 / a[k] : 0.0;
-        }
-    };
-    auto start = [&](int64_t rr) {
-        r = rr;
-        traj = P.traj_offset + (uint32_t)rr;
-        const int32_t* x0 = P.x0 + (P.x0_per_traj ? rr * N : 0);
-#pragma unroll
-        for (int j = 0; j < NT; ++j) X[j] = j < N ? x0[j] : 0;
-        t = 0.0;
-        g = 0;
-        s_next = P.G > 0 ? P.s[0] : __builtin_inf();
-        fired = 0;
-        tie = kTieNone;
-        hash = kFnvOffset;
-#pragma unroll
-        for (int k = 0; k < MT; ++k) {
-            T[k] = 0.0;
-            n[k] = 0;
-            bool slow = false;
-            Pk[k] = rt_exp1(P.key0, P.key1, traj, P.net_id, (uint32_t)k, 0u, &slow);
-            c_slow += slow;
-        }
-        refresh_rates();
-    };
     auto write_sample = [&](int32_t gg, bool invalid) {
         int32_t* dst = P.samples + r * P.ss_r + (int64_t)gg * P.ss_g;
 #pragma unroll
         for (int j = 0; j < NT; ++j)
             if (j < N) dst[j * P.ss_n] = invalid ? -1 : X[j];
     };
-    auto finish = [&](int st) {
-        const bool good = st == RTSSA_TRAJ_OK || st == RTSSA_TRAJ_ABSORBED;
-        if (P.samples)
-            for (int32_t gg = g; gg < P.G; ++gg) write_sample(gg, !good);
-        if (good) {
-            const double dt = P.t_end - t;
-#pragma unroll
-            for (int k = 0; k < MT; ++k) T[k] = fma(a[k], dt, T[k]);
-        }
-        if (P.n_out) {
-#pragma unroll
-            for (int k = 0; k < MT; ++k) if (k < M) P.n_out[r * M + k] = n[k];
-        }
-        if (P.T_out) {
-#pragma unroll
-            for (int k = 0; k < MT; ++k) if (k < M) P.T_out[r * M + k] = T[k];
-        }
-        if (P.x_final) {
-#pragma unroll
-            for (int j = 0; j < NT; ++j) if (j < N) P.x_final[r * N + j] = X[j];
-        }
-        if (P.t_last) P.t_last[r] = t;
-        if (P.status) P.status[r] = (uint8_t)st;
-        if (P.seq_hash) P.seq_hash[r] = hash;
-        if (P.tie_step) P.tie_step[r] = tie;
-        c_fired += fired;
-        c_st[st] += 1;
-    };
 
-    int64_t rr = (int64_t)atomicAdd(&P.ws->next_traj, 1ull);
-    bool active = rr < P.R;
-    if (active) start(rr);
-
-    while (active) {
+    // Each pass is one firing of every active lane.  The common path is
+    // straight-line; every rare event (start or end of a trajectory, a sample
+    // point, a near-tie, a clamped gap, an overflow, the firing cap) is
+    // handled in one branch entered only when some lane of the wave needs it.
+    bool active = true, fresh = true, capped = false;
+    while (__ballot(active) != 0ull) {
+        if (!active) continue;
         // gaps and argmin (lowest k wins ties; d2 = second smallest gap)
         double d1 = __builtin_inf(), d2 = __builtin_inf();
         int mu = 0;
@@ -178,97 +130,149 @@ __global__ __launch_bounds__(256) void rt_thread_kernel(rt_sim_params P, rt_net_
             mu = lt ? k : mu;
             clamped = lt ? (raw < 0.0) : clamped;
         }
-        int st = -1;
         const double t_new = t + d1;
-        if (d1 == __builtin_inf()) {
-            st = RTSSA_TRAJ_ABSORBED;
-        } else if (t_new > P.t_end) {
-            st = RTSSA_TRAJ_OK;
-        } else {
-            if (d2 - d1 <= 1e-12 * d1) {
-                c_ties += 1;
-                tie = tie == kTieNone ? fired : tie;
-            }
-            while (s_next < t_new) {
-                if (P.samples) write_sample(g, false);
-                ++g;
-                s_next = g < P.G ? P.s[g] : __builtin_inf();
-            }
-            // jump v_mu, checked against [0, 2^31 - 1]
-            int32_t Xn[NT];
-            bool ok = true;
+        const bool absorbed = d1 == __builtin_inf();
+        const bool term = absorbed || t_new > H.t_end;
+        // jump v_mu, checked against [0, 2^31 - 1]
+        int32_t Xn[NT];
+        bool ok = true;
 #pragma unroll
-            for (int j = 0; j < NT; ++j) {
-                int32_t dl = nu[0][j];
+        for (int j = 0; j < NT; ++j) {
+            int32_t dl = nu[0][j];
 #pragma unroll
-                for (int k = 1; k < MT; ++k) dl = (mu == k) ? nu[k][j] : dl;
-                const int64_t v = (int64_t)X[j] + dl;
-                ok = ok && v >= 0 && v <= 0x7FFFFFFF;
-                Xn[j] = (int32_t)v;
-            }
-            if (!ok) {
-                st = RTSSA_TRAJ_OVERFLOW;
-            } else {
-                c_clamps += clamped;
-                // internal times advance by a_k Delta (Eq. 15); the fired
-                // channel lands exactly on its firing internal time
-                uint32_t n_mu = 0;
-                double p_mu = 0.0;
-#pragma unroll
-                for (int k = 0; k < MT; ++k) {
-                    const bool f = mu == k;
-                    T[k] = f ? Pk[k] : fma(a[k], d1, T[k]);
-                    n[k] += f ? 1u : 0u;
-                    n_mu = f ? n[k] : n_mu;
-                    p_mu = f ? Pk[k] : p_mu;
+            for (int k = 1; k < MT; ++k) dl = (mu == k) ? nu[k][j] : dl;
+            const int64_t v = (int64_t)X[j] + dl;
+            ok = ok && v >= 0 && v <= 0x7FFFFFFF;
+            Xn[j] = (int32_t)v;
+        }
+        const bool live = !fresh && !capped;          // a trajectory is in progress
+        const bool event = live && !term;             // this pass may apply an event
+        const bool near_tie = event && d2 - d1 <= 1e-12 * d1;
+        const bool rare = !live || term || near_tie || clamped || !ok || s_next < t_new;
+        if (__builtin_expect(__ballot(rare) != 0ull, 0)) {
+            if (event) {
+                if (near_tie) {
+                    atomicAdd(&ws->near_ties, 1ull);
+                    tie = tie == kTieNone ? fired : tie;
                 }
-#pragma unroll
-                for (int j = 0; j < NT; ++j) X[j] = Xn[j];
-                t = t_new;
-                ++fired;
-                if (want_hash) hash = (hash ^ (unsigned long long)(uint32_t)mu) * kFnvPrime;
-                bool slow = false;
-                const double E = rt_exp1(P.key0, P.key1, traj, P.net_id, (uint32_t)mu, n_mu, &slow);
-                c_slow += slow;
-                p_mu = p_mu + E;
-#pragma unroll
-                for (int k = 0; k < MT; ++k) Pk[k] = (mu == k) ? p_mu : Pk[k];
-                refresh_rates();
-                if (fired >= P.max_firings) st = RTSSA_TRAJ_MAX_FIRINGS;
+                while (s_next < t_new) {
+                    if (P.samples) write_sample(g, false);
+                    ++g;
+                    s_next = g < P.G ? P.s[g] : __builtin_inf();
+                }
+                if (ok && clamped) atomicAdd(&ws->clamps, 1ull);
             }
+            const bool stop = !live || term || !ok;
+            if (stop && !fresh) {
+                // end of the trajectory
+                const int st = capped ? RTSSA_TRAJ_MAX_FIRINGS
+                                      : (absorbed ? RTSSA_TRAJ_ABSORBED
+                                                  : (term ? RTSSA_TRAJ_OK : RTSSA_TRAJ_OVERFLOW));
+                const bool good = st == RTSSA_TRAJ_OK || st == RTSSA_TRAJ_ABSORBED;
+                if (P.samples)
+                    for (int32_t gg = g; gg < P.G; ++gg) write_sample(gg, !good);
+                if (good) {
+                    const double dt = H.t_end - t;
+#pragma unroll
+                    for (int k = 0; k < MT; ++k) T[k] = fma(a[k], dt, T[k]);
+                }
+                if (P.n_out) {
+#pragma unroll
+                    for (int k = 0; k < MT; ++k) if (k < M) P.n_out[r * M + k] = n[k];
+                }
+                if (P.T_out) {
+#pragma unroll
+                    for (int k = 0; k < MT; ++k) if (k < M) P.T_out[r * M + k] = T[k];
+                }
+                if (P.x_final) {
+#pragma unroll
+                    for (int j = 0; j < NT; ++j) if (j < N) P.x_final[r * N + j] = X[j];
+                }
+                if (P.t_last) P.t_last[r] = t;
+                if (P.status) P.status[r] = (uint8_t)st;
+                if (P.seq_hash) P.seq_hash[r] = hash;
+                if (P.tie_step) P.tie_step[r] = tie;
+                atomicAdd(&ws->firings, (unsigned long long)fired);
+                atomicAdd(&ws->status_count[st], 1ull);
+            }
+            if (stop) {
+                // take the next trajectory from the work queue
+                const int64_t rr = (int64_t)atomicAdd(&ws->next_traj, 1ull);
+                fresh = false;
+                capped = false;
+                active = rr < P.R;
+                if (active) {
+                    r = rr;
+                    traj = H.traj_offset + (uint32_t)rr;
+                    const int32_t* x0 = P.x0 + (P.x0_per_traj ? rr * N : 0);
+#pragma unroll
+                    for (int j = 0; j < NT; ++j) X[j] = j < N ? x0[j] : 0;
+                    t = 0.0;
+                    g = 0;
+                    s_next = P.G > 0 ? P.s[0] : __builtin_inf();
+                    fired = 0;
+                    tie = kTieNone;
+                    hash = kFnvOffset;
+#pragma unroll
+                    for (int k = 0; k < MT; ++k) {
+                        T[k] = 0.0;
+                        n[k] = 0;
+                        a[k] = propensity<NT>(kind[k], s0[k], s1[k], c[k], X);
+                        inv[k] = 1.0 / a[k];
+                    }
+                    // first internal firing times, one draw at a time
+#pragma unroll 1
+                    for (int k = 0; k < MT; ++k) {
+                        const double E0 = rt_exp1_wave(H.key0, H.key1, traj, H.net_id, (uint32_t)k,
+                                                       0u, &ws->slow_logs, sc);
+#pragma unroll
+                        for (int q = 0; q < MT; ++q) Pk[q] = q == k ? E0 : Pk[q];
+                    }
+                }
+            }
+            if (__ballot(stop) != 0ull) continue;   // started lanes compute their first gaps
         }
-        if (st >= 0) {
-            finish(st);
-            rr = (int64_t)atomicAdd(&P.ws->next_traj, 1ull);
-            active = rr < P.R;
-            if (active) start(rr);
+        // internal times advance by a_k Delta (Eq. 15); the fired channel
+        // lands exactly on its firing internal time
+        uint32_t n_mu = 0;
+        double p_mu = 0.0;
+#pragma unroll
+        for (int k = 0; k < MT; ++k) {
+            const bool f = mu == k;
+            T[k] = f ? Pk[k] : fma(a[k], d1, T[k]);
+            n[k] += f ? 1u : 0u;
+            n_mu = f ? n[k] : n_mu;
+            p_mu = f ? Pk[k] : p_mu;
         }
+#pragma unroll
+        for (int j = 0; j < NT; ++j) X[j] = Xn[j];
+        t = t_new;
+        ++fired;
+        if (want_hash) hash = (hash ^ (unsigned long long)(uint32_t)mu) * kFnvPrime;
+        p_mu = p_mu + rt_exp1_wave(H.key0, H.key1, traj, H.net_id, (uint32_t)mu, n_mu,
+                                   &ws->slow_logs, sc);
+        // a_k is a pure function of X; inv_k = RN(1 / a_k) (+inf for a dead
+        // channel, whose gap is +inf by the a_k = 0 test and never reads it)
+#pragma unroll
+        for (int k = 0; k < MT; ++k) {
+            Pk[k] = (mu == k) ? p_mu : Pk[k];
+            a[k] = propensity<NT>(kind[k], s0[k], s1[k], c[k], X);
+            inv[k] = 1.0 / a[k];
+        }
+        capped = fired >= H.max_firings;
     }
 
-    // one atomic per counter and wave (lanes are converged here)
-    unsigned long long v[8] = {c_fired, c_ties, c_clamps, c_slow, c_st[0], c_st[1], c_st[2], c_st[3]};
-#pragma unroll
-    for (int q = 0; q < 8; ++q)
-#pragma unroll
-        for (int off = 32; off > 0; off >>= 1) v[q] += __shfl_xor(v[q], off, 64);
-    if ((threadIdx.x & 63) == 0) {
-        atomicAdd(&P.ws->firings, v[0]);
-        atomicAdd(&P.ws->near_ties, v[1]);
-        atomicAdd(&P.ws->clamps, v[2]);
-        atomicAdd(&P.ws->slow_logs, v[3]);
-#pragma unroll
-        for (int q = 0; q < 4; ++q) atomicAdd(&P.ws->status_count[q], v[4 + q]);
-    }
 }
 
-__global__ void rt_zero_ws_kernel(rt_ws* ws)
+__global__ void rt_zero_ws_kernel(rt_ws* ws, rt_sim_params params)
 {
     unsigned long long* w = (unsigned long long*)ws;
-    const int nw = (int)(sizeof(rt_ws) / sizeof(unsigned long long));
+    const int nw = (int)(offsetof(rt_ws, params) / sizeof(unsigned long long));
     for (int i = threadIdx.x; i < nw; i += blockDim.x) w[i] = 0ull;
+    if (threadIdx.x == 0) ws->params = params;
 }
 
-typedef void (*thread_kernel_t)(rt_sim_params, rt_net_dev);
+typedef void (*thread_kernel_t)(rt_hot_params, rt_ws*, rt_net_dev);
 
 template <int MT, int NT>
 int launch_mn(const rt_sim_params& p, const rt_net_dev& net, int block, int grid,
@@ -287,7 +291,14 @@ int launch_mn(const rt_sim_params& p, const rt_net_dev& net, int block, int grid
         grid = (int)std::max<int64_t>(1, std::min<int64_t>(need, full));
     }
     if (grid_used) *grid_used = grid;
-    hipLaunchKernelGGL(kfn, dim3(grid), dim3(block), 0, stream, p, net);
+    rt_hot_params h{};
+    h.t_end = p.t_end;
+    h.key0 = p.key0;
+    h.key1 = p.key1;
+    h.net_id = p.net_id;
+    h.traj_offset = p.traj_offset;
+    h.max_firings = p.max_firings;
+    hipLaunchKernelGGL(kfn, dim3(grid), dim3(block), 0, stream, h, p.ws, net);
     return hipGetLastError() == hipSuccess ? RTSSA_OK : rt_fail(RTSSA_E_HIP, "thread kernel launch failed");
 }
 
@@ -329,8 +340,8 @@ int rt_launch_thread(const rtssa_network* net, const rt_sim_params& p, int block
     }
 }
 
-int rt_launch_zero_ws(rt_ws* ws, hipStream_t stream)
+int rt_launch_zero_ws(rt_ws* ws, const rt_sim_params* params, hipStream_t stream)
 {
-    hipLaunchKernelGGL(rt_zero_ws_kernel, dim3(1), dim3(64), 0, stream, ws);
+    hipLaunchKernelGGL(rt_zero_ws_kernel, dim3(1), dim3(64), 0, stream, ws, *params);
     return hipGetLastError() == hipSuccess ? RTSSA_OK : rt_fail(RTSSA_E_HIP, "workspace clear failed");
 }

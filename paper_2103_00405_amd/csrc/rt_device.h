@@ -1,0 +1,47 @@
+// rt_device.h -- device-side wrappers of the numeric core for the kernels.
+#pragma once
+#define RT_HD __device__ __forceinline__
+#define RT_LOG_CONST __constant__
+#include <hip/hip_runtime.h>
+
+#include "rt_math.h"
+
+// RN(-ln u) for the wave's active lanes.  The fast phase runs in every lane;
+// lanes whose rounding it cannot certify (about one draw in 2^17) take turns
+// on the wave's LDS slice sc (RT_LOG_SCRATCH words) for the accurate phase
+// and add one to the device counter *slow.
+__device__ __forceinline__ double rt_neglog_wave(uint64_t m, bool force_accurate,
+                                                 unsigned long long* slow, uint32_t* sc)
+{
+    int e, i;
+    double z;
+    rt_neglog_reduce(m, e, i, z);
+    double y = 0.0;
+    bool need = m != 0x1FFFFFFFFFFFFFull;                     // u = 1 gives +0
+    if (need && !force_accurate) {
+        double yh, yl;
+        rt_neglog_fast(e, i, z, yh, yl);
+        y = yh;
+        need = !rt_rounding_certain(yh, yl);
+    }
+    unsigned long long pending = __ballot(need);
+    if (__builtin_expect(pending != 0ull, 0)) {
+        const int me = (int)(threadIdx.x & 63u);
+        while (pending) {
+            const int lane = __ffsll((long long)pending) - 1;
+            if (lane == me) {
+                y = rt_neglog_accurate(e, i, z, sc);
+                atomicAdd(slow, 1ull);
+            }
+            pending &= pending - 1ull;
+        }
+    }
+    return y;
+}
+
+__device__ __forceinline__ double rt_exp1_wave(uint32_t k0, uint32_t k1, uint32_t traj,
+                                               uint32_t net, uint32_t k, uint32_t n,
+                                               unsigned long long* slow, uint32_t* sc)
+{
+    return rt_neglog_wave(rt_draw_m53(k0, k1, traj, net, k, n), false, slow, sc);
+}

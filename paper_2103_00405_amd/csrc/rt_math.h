@@ -13,13 +13,14 @@
 //                     unit-exponential internal-time gaps (paper Eq. 23, 26).
 //   rt_neglog_u53     correctly rounded -ln(u), u = (m+1) 2^-53, so that a
 //                     draw ln(1/r) has one exact binary64 value.
-//   rt_exp1           the draw of the n-th refresh of channel k.
+//   rt_draw_m53       the 53-bit integer behind the n-th draw of channel k.
 #pragma once
 #include <stdint.h>
 
 #ifndef RT_HD
 #error "define RT_HD and RT_LOG_CONST before including rt_math.h"
 #endif
+
 
 #include "log_tables.inc"
 
@@ -68,135 +69,109 @@ RT_HD void rt_twosum(double a, double b, double& s, double& e)
 // ------------------------------------- accurate phase: 288-bit fixed point
 // Values are two's-complement integers of RT_LOG_LIMBS 32-bit limbs
 // (little-endian) in units of 2^-256: 32 integer bits, 256 fraction bits.
-struct rt_fix { uint32_t w[RT_LOG_LIMBS]; };
+// The routines work in a caller-provided buffer of RT_LOG_SCRATCH words (the
+// kernels give each wave a slice of LDS and let the lanes that need this
+// rare phase take turns), so they add no register pressure to the hot loop.
+#define RT_LOG_SCRATCH (2 * RT_LOG_LIMBS + 2)
 
-RT_HD void rt_fix_load(rt_fix& a, const uint32_t* src)
+// p <- c - p
+RT_HD void rt_fix_rsub_const(uint32_t* p, const uint32_t* c)
 {
-    for (int i = 0; i < RT_LOG_LIMBS; ++i) a.w[i] = src[i];
-}
-
-RT_HD void rt_fix_add(rt_fix& a, const rt_fix& b)
-{
-    uint64_t carry = 0;
+    uint64_t borrow = 0;
     for (int i = 0; i < RT_LOG_LIMBS; ++i) {
-        uint64_t s = (uint64_t)a.w[i] + b.w[i] + carry;
-        a.w[i] = (uint32_t)s;
-        carry = s >> 32;
+        uint64_t d = (uint64_t)c[i] - p[i] - borrow;
+        p[i] = (uint32_t)d;
+        borrow = (d >> 32) & 1u;
     }
 }
 
-RT_HD void rt_fix_neg(rt_fix& a)
+// p <- p + c * s, s a small non-negative integer
+RT_HD void rt_fix_add_mul_const(uint32_t* p, const uint32_t* c, uint32_t s)
+{
+    uint64_t carry = 0;
+    for (int i = 0; i < RT_LOG_LIMBS; ++i) {
+        uint64_t t = (uint64_t)c[i] * s + p[i] + carry;
+        p[i] = (uint32_t)t;
+        carry = t >> 32;
+    }
+}
+
+RT_HD void rt_fix_neg(uint32_t* p)
 {
     uint64_t carry = 1;
     for (int i = 0; i < RT_LOG_LIMBS; ++i) {
-        uint64_t s = (uint64_t)(~a.w[i]) + carry;
-        a.w[i] = (uint32_t)s;
-        carry = s >> 32;
+        uint64_t t = (uint64_t)(~p[i]) + carry;
+        p[i] = (uint32_t)t;
+        carry = t >> 32;
     }
 }
 
-RT_HD void rt_fix_sub(rt_fix& a, const rt_fix& b)
+// p <- p * Z / 2^61 truncated toward zero, |Z| < 2^63: the product of a
+// fixed-point value by z = Z 2^-61.  tmp holds RT_LOG_LIMBS + 2 words.
+RT_HD void rt_fix_mul_z(uint32_t* p, int64_t Z, uint32_t* tmp)
 {
-    rt_fix nb = b;
-    rt_fix_neg(nb);
-    rt_fix_add(a, nb);
-}
-
-RT_HD bool rt_fix_isneg(const rt_fix& a) { return (a.w[RT_LOG_LIMBS - 1] >> 31) != 0; }
-
-// a <- a * s for a small non-negative integer s (no overflow in use).
-RT_HD void rt_fix_mul_small(rt_fix& a, uint32_t s)
-{
-    uint64_t carry = 0;
-    for (int i = 0; i < RT_LOG_LIMBS; ++i) {
-        uint64_t p = (uint64_t)a.w[i] * s + carry;
-        a.w[i] = (uint32_t)p;
-        carry = p >> 32;
-    }
-}
-
-// a <- a * Z / 2^61 truncated toward zero, for a signed integer |Z| < 2^63: the product of a
-// fixed-point value by z = Z 2^-61.  Truncation error below one unit 2^-256.
-RT_HD void rt_fix_mul_z(rt_fix& a, int64_t Z)
-{
-    bool neg = rt_fix_isneg(a) != (Z < 0);
-    rt_fix m = a;
-    if (rt_fix_isneg(m)) rt_fix_neg(m);
-    uint64_t az = Z < 0 ? (uint64_t)(-Z) : (uint64_t)Z;
-    uint32_t zl = (uint32_t)az, zh = (uint32_t)(az >> 32);
-    // product of RT_LOG_LIMBS limbs by 2 limbs -> RT_LOG_LIMBS + 2 limbs
-    uint32_t p[RT_LOG_LIMBS + 2];
-    for (int i = 0; i < RT_LOG_LIMBS + 2; ++i) p[i] = 0;
+    const bool pneg = (p[RT_LOG_LIMBS - 1] >> 31) != 0;
+    const bool neg = pneg != (Z < 0);
+    if (pneg) rt_fix_neg(p);
+    const uint64_t az = Z < 0 ? (uint64_t)(-Z) : (uint64_t)Z;
+    for (int i = 0; i < RT_LOG_LIMBS + 2; ++i) tmp[i] = 0;
     for (int j = 0; j < 2; ++j) {
-        uint32_t zj = j == 0 ? zl : zh;
+        const uint32_t zj = (uint32_t)(az >> (32 * j));
         uint64_t carry = 0;
         for (int i = 0; i < RT_LOG_LIMBS; ++i) {
-            uint64_t t = (uint64_t)m.w[i] * zj + p[i + j] + carry;
-            p[i + j] = (uint32_t)t;
+            uint64_t t = (uint64_t)p[i] * zj + tmp[i + j] + carry;
+            tmp[i + j] = (uint32_t)t;
             carry = t >> 32;
         }
-        p[RT_LOG_LIMBS + j] += (uint32_t)carry;
+        tmp[RT_LOG_LIMBS + j] += (uint32_t)carry;
     }
     // shift right by 61 = 32 + 29 bits
-    for (int i = 0; i < RT_LOG_LIMBS; ++i) {
-        uint32_t lo = p[i + 1], hi = (i + 2 < RT_LOG_LIMBS + 2) ? p[i + 2] : 0u;
-        m.w[i] = (lo >> 29) | (hi << 3);
-    }
-    if (neg) rt_fix_neg(m);
-    a = m;
+    for (int i = 0; i < RT_LOG_LIMBS; ++i) p[i] = (tmp[i + 1] >> 29) | (tmp[i + 2] << 3);
+    if (neg) rt_fix_neg(p);
 }
 
 // Round a non-negative fixed-point value to the nearest binary64 (ties even).
-RT_HD double rt_fix_to_double(const rt_fix& a)
+RT_HD double rt_fix_to_double(const uint32_t* a)
 {
     int top = -1;
     for (int i = RT_LOG_LIMBS - 1; i >= 0 && top < 0; --i)
-        if (a.w[i]) top = 32 * i + (31 - __builtin_clz(a.w[i]));
+        if (a[i]) top = 32 * i + (31 - __builtin_clz(a[i]));
     if (top < 0) return 0.0;
-    // bit b of the integer is a.w[b / 32] >> (b % 32)
     uint64_t mant = 0;
     for (int b = top; b > top - 53; --b) {
-        uint32_t bit = b >= 0 ? (a.w[b >> 5] >> (b & 31)) & 1u : 0u;
+        uint32_t bit = b >= 0 ? (a[b >> 5] >> (b & 31)) & 1u : 0u;
         mant = (mant << 1) | bit;
     }
-    int rb = top - 53;                       // rounding bit position
-    uint32_t round_bit = rb >= 0 ? (a.w[rb >> 5] >> (rb & 31)) & 1u : 0u;
+    const int rb = top - 53;                        // rounding bit position
+    const uint32_t round_bit = rb >= 0 ? (a[rb >> 5] >> (rb & 31)) & 1u : 0u;
     bool sticky = false;
-    for (int b = rb - 1; b >= 0 && !sticky; --b)
-        sticky = ((a.w[b >> 5] >> (b & 31)) & 1u) != 0;
+    for (int b = rb - 1; b >= 0 && !sticky; --b) sticky = ((a[b >> 5] >> (b & 31)) & 1u) != 0;
     if (round_bit && (sticky || (mant & 1u))) mant += 1;
-    int expo = top - 52 - RT_LOG_FRAC;       // value = mant * 2^expo
+    int expo = top - 52 - RT_LOG_FRAC;              // value = mant * 2^expo
     if (mant == (1ull << 53)) { mant >>= 1; expo += 1; }
-    // mant < 2^53 is exact in binary64; scaling by a power of two is exact
-    double d = (double)mant;
-    uint64_t scale_bits = (uint64_t)(1023 + expo) << 52;   // expo within normal range here
-    return d * rt_u2d(scale_bits);
+    const double d = (double)mant;                  // exact: mant <= 2^53
+    return d * rt_u2d((uint64_t)(1023 + expo) << 52);
 }
 
-// -ln(u) = -e ln2 + ln r - ln(1 + z), each term to about 2^-250 absolute.
-RT_HD double rt_neglog_accurate(int e, int i, double z)
+// -ln(u) = -e ln2 + ln r - ln(1 + z), each term to about 2^-250 absolute, in
+// the buffer sc of RT_LOG_SCRATCH words.
+RT_HD double rt_neglog_accurate(int e, int i, double z, uint32_t* sc)
 {
+    uint32_t* p = sc;
+    uint32_t* tmp = sc + RT_LOG_LIMBS;
     // z = Z 2^-61 exactly (|z| <= 2^-8 is a multiple of 2^-61)
-    int64_t Z = (int64_t)(z * 0x1p61);
+    const int64_t Z = (int64_t)(z * 0x1p61);
     // Horner: p = sum_{j=0..KMAX} (-z)^j / (j + 1);  ln(1 + z) = z p
-    rt_fix p;
-    rt_fix_load(p, RT_INVK_FIX[RT_LOG_KMAX]);
+    for (int q = 0; q < RT_LOG_LIMBS; ++q) p[q] = RT_INVK_FIX[RT_LOG_KMAX][q];
     for (int j = RT_LOG_KMAX - 1; j >= 0; --j) {
-        rt_fix_mul_z(p, Z);
-        rt_fix c;
-        rt_fix_load(c, RT_INVK_FIX[j]);
-        rt_fix_sub(c, p);
-        p = c;
+        rt_fix_mul_z(p, Z, tmp);
+        rt_fix_rsub_const(p, RT_INVK_FIX[j]);
     }
-    rt_fix_mul_z(p, Z);                       // p = ln(1 + z)
-    rt_fix y;
-    rt_fix_load(y, RT_LN2_FIX);
-    rt_fix_mul_small(y, (uint32_t)(-e));      // -e ln 2, e <= 0
-    rt_fix lnr;
-    rt_fix_load(lnr, RT_LNR_FIX[i]);
-    rt_fix_add(y, lnr);
-    rt_fix_sub(y, p);
-    return rt_fix_to_double(y);
+    rt_fix_mul_z(p, Z, tmp);                        // p = ln(1 + z)
+    rt_fix_neg(p);
+    rt_fix_add_mul_const(p, RT_LNR_FIX[i], 1u);     // + ln r
+    rt_fix_add_mul_const(p, RT_LN2_FIX, (uint32_t)(-e));  // + (-e) ln 2, e <= 0
+    return rt_fix_to_double(p);
 }
 
 // ------------------------------------------------- correctly rounded -ln u
@@ -260,10 +235,10 @@ RT_HD bool rt_rounding_certain(double yh, double yl)
     return yl + err < half_up && yl - err > -half_dn;
 }
 
-// RN(-ln u) for u = (m + 1) 2^-53, m < 2^53.  When the fast phase cannot
-// certify its rounding (about one call in 2^17) the accurate phase decides.
+// RN(-ln u) for u = (m + 1) 2^-53, m < 2^53, in one lane: when the fast
+// phase cannot certify its rounding the accurate phase decides in sc.
 // *slow is set when the accurate phase ran.
-RT_HD double rt_neglog_u53(uint64_t m, bool force_accurate, bool* slow)
+RT_HD double rt_neglog_u53(uint64_t m, bool force_accurate, bool* slow, uint32_t* sc)
 {
     if (m == 0x1FFFFFFFFFFFFFull) return 0.0;                 // u = 1
     int e, i;
@@ -275,17 +250,18 @@ RT_HD double rt_neglog_u53(uint64_t m, bool force_accurate, bool* slow)
         if (rt_rounding_certain(yh, yl)) return yh;
     }
     if (slow) *slow = true;
-    return rt_neglog_accurate(e, i, z);
+    return rt_neglog_accurate(e, i, z, sc);
 }
 
-// E(seed, traj, net, k, n): block at counter (n >> 1, k, traj, net) under key
-// (seed_lo, seed_hi); the 64-bit word is (w1:w0) for even n and (w3:w2) for
-// odd n; u = ((word >> 11) + 1) 2^-53.
-RT_HD double rt_exp1(uint32_t k0, uint32_t k1, uint32_t traj, uint32_t net, uint32_t k,
-                     uint32_t n, bool* slow)
+// The 53-bit integer m of the draw E(seed, traj, net, k, n): the Philox block
+// at counter (n >> 1, k, traj, net) under key (seed_lo, seed_hi); the 64-bit
+// word is (w1:w0) for even n and (w3:w2) for odd n; m = word >> 11, and the
+// draw is E = RN(-ln((m + 1) 2^-53)).
+RT_HD uint64_t rt_draw_m53(uint32_t k0, uint32_t k1, uint32_t traj, uint32_t net, uint32_t k,
+                           uint32_t n)
 {
     rt_u4 c = {n >> 1, k, traj, net};
     rt_u4 w = rt_philox4x32_10(c, k0, k1);
     uint64_t word = (n & 1u) ? (((uint64_t)w.w << 32) | w.z) : (((uint64_t)w.y << 32) | w.x);
-    return rt_neglog_u53(word >> 11, false, slow);
+    return word >> 11;
 }
