@@ -25,6 +25,22 @@ static int check_hip(hipError_t e, const char* what)
     return rt_fail(RTSSA_E_HIP, std::string(what) + ": " + hipGetErrorString(e));
 }
 
+// Mapping chosen from the network size: thread-per-trajectory for register-
+// sized networks, one wavefront for up to 64 x 16 channels, else a workgroup.
+int rt_auto_mapping(const rtssa_network* net)
+{
+    if (rt_thread_supported(net->M, net->N)) return RTSSA_MAP_THREAD;
+    if (net->M <= 512) return RTSSA_MAP_WAVE;
+    return RTSSA_MAP_WORKGROUP;
+}
+
+int rt_auto_group_size(int M)
+{
+    if (M <= 1024) return 256;
+    if (M <= 4096) return 1024;
+    return 1024;
+}
+
 extern "C" int rtssa_simulate(const rtssa_network* net, const int32_t* x0, int32_t x0_per_traj,
                               double t_end, const double* sample_t, int32_t G, uint64_t seed,
                               uint32_t net_id, uint64_t traj_offset, int64_t R, int32_t* samples,
@@ -66,7 +82,7 @@ extern "C" int rtssa_simulate(const rtssa_network* net, const int32_t* x0, int32
 
     int mapping = o.mapping;
     if (mapping == RTSSA_MAP_AUTO)
-        mapping = rt_thread_supported(net->M, net->N) ? RTSSA_MAP_THREAD : RTSSA_MAP_WAVE;
+        mapping = rt_auto_mapping(net);
 
     rt_ws* ws = nullptr;
     int rc = check_hip(hipMallocAsync((void**)&ws, sizeof(rt_ws), stream), "workspace allocation");
@@ -108,8 +124,15 @@ extern "C" int rtssa_simulate(const rtssa_network* net, const int32_t* x0, int32
         if (mapping == RTSSA_MAP_THREAD) {
             if (block_used <= 0) block_used = 256;
             rc = rt_launch_thread(net, p, block_used, o.grid, stream, &grid_used);
+        } else if (mapping == RTSSA_MAP_WAVE || mapping == RTSSA_MAP_WORKGROUP) {
+            if (mapping == RTSSA_MAP_WAVE) block_used = 64;
+            else if (block_used <= 0) block_used = rt_auto_group_size(net->M);
+            if (block_used != 64 && block_used != 256 && block_used != 512 && block_used != 1024)
+                rc = rt_fail(RTSSA_E_INVALID, "group size must be 64, 256, 512 or 1024");
+            else
+                rc = rt_launch_group(net, p, block_used, o.grid, stream, &grid_used);
         } else {
-            rc = rt_fail(RTSSA_E_UNSUPPORTED, "mapping not available for this network yet");
+            rc = rt_fail(RTSSA_E_INVALID, "unknown mapping");
         }
     }
     if (!rc && stats) {

@@ -87,8 +87,10 @@ struct rt_ws {
     rt_sim_params params;
 };
 
-// error reporting (api.cpp)
+// error reporting and mapping choice (api.cpp)
 int rt_fail(int code, const std::string& msg);
+int rt_auto_mapping(const rtssa_network* net);
+int rt_auto_group_size(int M);
 
 // kernels.hip
 int rt_launch_thread(const rtssa_network* net, const rt_sim_params& p, int block, int grid,
@@ -102,3 +104,7 @@ int rt_launch_debug_neglog(const uint64_t* m, double* out, uint8_t* slow, int64_
 int rt_launch_debug_philox(const uint32_t* ctr, uint32_t k0, uint32_t k1, uint32_t* out,
                            int64_t count, hipStream_t stream);
 int rt_thread_supported(int M, int N);
+int rt_launch_group(const rtssa_network* net, const rt_sim_params& p, int L, int grid,
+                    hipStream_t stream, int* grid_used);
+int rt_group_slots(int M, int L);
+size_t rt_group_lds_bytes(int N, int M);

@@ -210,7 +210,6 @@ extern "C" int rtssa_network_info(const rtssa_network* net, int32_t* N, int32_t*
     if (N) *N = net->N;
     if (M) *M = net->M;
     if (dep_edges) *dep_edges = net->dep_ptr.empty() ? 0 : net->dep_ptr[net->M];
-    if (auto_mapping) *auto_mapping = rt_thread_supported(net->M, net->N) ? RTSSA_MAP_THREAD
-                                                                          : RTSSA_MAP_WAVE;
+    if (auto_mapping) *auto_mapping = rt_auto_mapping(net);
     return RTSSA_OK;
 }

@@ -1,0 +1,159 @@
+"""GPU parity of the wavefront- and workgroup-per-trajectory mappings.
+
+Every output is compared bit for bit with the CPU oracle on random networks
+that exercise every reaction kind (order 0, 1, homodimer, heterodimer) and
+several channel-to-lane layouts; the same network run through different
+mappings and group sizes must give identical bits; the large random network
+(N = 1000, M = 4000) is checked on full trajectories and, at its full
+ensemble size, by Eq. 5 on every trajectory."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2103_00405_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+KEYS = ("samples", "n", "T", "x_final", "t_last", "status", "seq_hash", "tie_step")
+
+
+def _api():
+    from paper_2103_00405_amd import api
+    return api
+
+
+def _np(t):
+    return t.cpu().numpy()
+
+
+def _assert_same(g, ref, stats=True):
+    assert np.array_equal(_np(g["samples"]), ref["samples"])
+    assert np.array_equal(_np(g["n"]).view(np.uint32), ref["n"])
+    assert np.array_equal(_np(g["T"]).view(np.uint64), ref["T"].view(np.uint64))
+    assert np.array_equal(_np(g["x_final"]), ref["x_final"])
+    assert np.array_equal(_np(g["t_last"]).view(np.uint64), ref["t_last"].view(np.uint64))
+    assert np.array_equal(_np(g["status"]), ref["status"])
+    assert np.array_equal(_np(g["seq_hash"]).view(np.uint64), ref["seq_hash"])
+    assert np.array_equal(_np(g["tie_step"]).view(np.uint32), ref["tie_step"])
+    if stats:
+        for k in ("firings", "near_ties", "clamps", "status_count"):
+            assert g["stats"][k] == ref["stats"][k], k
+
+
+def _net(N, M, seed, logc=(-1.0, 1.0), bimol=0.05):
+    rng = np.random.default_rng(seed)
+    spec = W.random_network(N, M, rng, logc=logc, bimol_scale=bimol)
+    x0 = rng.integers(0, 80, size=N).astype(np.int32)
+    return spec, x0
+
+
+def _t_end_for(spec, x0, firings):
+    return float(firings / max(W.initial_total_rate(spec, x0), 1e-9))
+
+
+@pytest.mark.parametrize("N,M,mapping,block,seed", [
+    (6, 12, 2, 0, 1), (10, 40, 2, 0, 2), (30, 100, 2, 0, 3), (80, 300, 2, 0, 4),
+    (64, 513, 2, 0, 5), (40, 200, 3, 256, 6), (200, 900, 3, 256, 7), (300, 1500, 3, 512, 8),
+    (500, 2000, 3, 1024, 9), (1000, 4000, 3, 1024, 10), (8, 8, 3, 1024, 11), (5, 65, 2, 0, 12),
+])
+def test_random_networks_bit_exact(N, M, mapping, block, seed):
+    api = _api()
+    spec, x0 = _net(N, M, seed)
+    t_end = _t_end_for(spec, x0, 1500)
+    grid = np.sort(np.random.default_rng(seed).uniform(0, t_end, size=9))
+    R = 24
+    net = api.Network(spec)
+    g = api.simulate(net, x0, t_end, grid, R, seed=seed, net_id=seed, mapping=mapping,
+                     block=block, with_hash=True)
+    torch.cuda.synchronize()
+    assert g["stats"]["mapping"] == mapping
+    ref = oracle.simulate(spec, x0, t_end, grid, seed, R, net_id=seed)
+    _assert_same(g, ref)
+    assert ref["stats"]["firings"] > 50 * R
+
+
+def test_mappings_agree_on_the_same_network():
+    """Thread, wavefront and workgroup mappings (and group sizes) give identical bits."""
+    api = _api()
+    w = W.lv_small(128)
+    net = api.Network(w.net)
+    runs = []
+    for mapping, block in ((1, 0), (2, 0), (3, 256), (3, 1024)):
+        o = api.simulate(net, w.x0, 6.0, W.uniform_grid(6.0, 13), 128, mapping=mapping,
+                         block=block, with_hash=True)
+        assert o["stats"]["mapping"] == mapping
+        runs.append(o)
+    for o in runs[1:]:
+        for k in KEYS:
+            assert torch.equal(o[k], runs[0][k]), k
+    spec, x0 = _net(20, 60, 21)
+    net2 = api.Network(spec)
+    t_end = _t_end_for(spec, x0, 800)
+    a = api.simulate(net2, x0, t_end, [t_end], 50, mapping=2, with_hash=True)
+    for block in (256, 512):
+        b = api.simulate(net2, x0, t_end, [t_end], 50, mapping=3, block=block, with_hash=True)
+        for k in KEYS:
+            assert torch.equal(a[k], b[k]), (block, k)
+
+
+def test_group_edge_cases():
+    api = _api()
+    # overflow stops before the jump
+    spec = W.from_reactions(2, [({0: 1}, {0: 2}, 1.0), ({1: 1}, {}, 1.0)])
+    net = api.Network(spec)
+    x0 = np.array([2**31 - 10, 5], np.int32)
+    for mapping in (2, 3):
+        g = api.simulate(net, x0, 100.0, [1e-12, 100.0], 6, mapping=mapping, with_hash=True)
+        ref = oracle.simulate(spec, x0, 100.0, [1e-12, 100.0], 1, 6)
+        _assert_same(g, ref)
+    # firing cap and absorbing states, per-trajectory initial states
+    spec2, x02 = _net(12, 30, 31)
+    net2 = api.Network(spec2)
+    t_end = _t_end_for(spec2, x02, 3000)
+    x0r = np.tile(x02, (16, 1))
+    x0r[3] = 0
+    for mapping in (2, 3):
+        g = api.simulate(net2, x0r, t_end, W.uniform_grid(t_end, 5), 16, mapping=mapping,
+                         max_firings=500, with_hash=True)
+        ref = oracle.simulate(spec2, x0r, t_end, W.uniform_grid(t_end, 5), 1, 16, max_firings=500)
+        _assert_same(g, ref)
+    # traj_offset split and grid size
+    a = api.simulate(net2, x02, t_end, [t_end], 40, mapping=2, with_hash=True)
+    b1 = api.simulate(net2, x02, t_end, [t_end], 15, mapping=2, traj_offset=0, with_hash=True,
+                      grid=3)
+    b2 = api.simulate(net2, x02, t_end, [t_end], 25, mapping=2, traj_offset=15, with_hash=True,
+                      grid=1)
+    for k in ("n", "T", "seq_hash"):
+        assert torch.equal(torch.cat([b1[k], b2[k]]), a[k]), k
+
+
+def test_large_random_network_full_trajectories():
+    """N = 1000, M = 4000, t_end for about 1e5 firings: two full trajectories
+    bit-exact against the oracle; the full 512-trajectory ensemble satisfies
+    Eq. 5 and every status is a regular end state."""
+    api = _api()
+    w = W.large_random()
+    net = api.Network(w.net)
+    g = api.simulate(net, w.x0, w.t_end, w.sample_t, w.R, seed=w.seed, with_hash=True)
+    torch.cuda.synchronize()
+    st = g["stats"]
+    assert st["mapping"] == api.MAP_WORKGROUP
+    assert st["firings"] > 50 * w.R * 1000
+    # Eq. 5 on every trajectory
+    n = _np(g["n"]).astype(np.int64)
+    X = np.tile(w.x0.astype(np.int64), (w.R, 1))
+    for k in range(w.net.M):
+        for e in range(w.net.react_ptr[k], w.net.react_ptr[k + 1]):
+            X[:, w.net.react_species[e]] -= w.net.react_sigma[e] * n[:, k]
+        for e in range(w.net.prod_ptr[k], w.net.prod_ptr[k + 1]):
+            X[:, w.net.prod_species[e]] += w.net.prod_mult[e] * n[:, k]
+    assert np.array_equal(X, _np(g["x_final"]).astype(np.int64))
+    # two full trajectories recomputed by the oracle
+    for off in (0, 300):
+        ref = oracle.simulate(w.net, w.x0, w.t_end, w.sample_t, w.seed, 1, traj_offset=off)
+        sl = slice(off, off + 1)
+        assert np.array_equal(_np(g["samples"][sl]), ref["samples"])
+        assert np.array_equal(_np(g["n"][sl]).view(np.uint32), ref["n"])
+        assert np.array_equal(_np(g["T"][sl]).view(np.uint64), ref["T"].view(np.uint64))
+        assert np.array_equal(_np(g["seq_hash"][sl]).view(np.uint64), ref["seq_hash"])
