@@ -1,15 +1,23 @@
 """Benchmark: reaction firings per second of the random-time SSA ensemble on
 one MI355X, with a roofline figure and the CPU oracle timed beside it.
 
-Default workload: Lotka-Volterra (c = 10, 0.01, 10; x0 = (1000, 1000);
+Headline workload: Lotka-Volterra (c = 10, 0.01, 10; x0 = (1000, 1000);
 t_end = 5; 101-point grid; 2^20 trajectories), thread-per-trajectory mapping.
 A step is one full ensemble simulation (every trajectory to t_end) with all
-outputs written to HBM.
+outputs written to HBM; inputs are resident before the timed region.
+
+Secondary measurements (attached to the same JSON line, or alone with
+--workload): the large random network (N = 1000, M = 4000, 512 trajectories,
+workgroup mapping) and the gradient form (score-function gradient evals/s
+against plain expectation evals/s and against coupled finite differences at
+equal standard error, birth-death and Lotka-Volterra, 2^18 trajectories).
 
     python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu-baseline]
+                    [--workload lv_ensemble|large_random|gradient|all]
 """
 import argparse
 import json
+import math
 import os
 import sys
 import time
@@ -18,14 +26,22 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 # Issue-slot count of one firing of the method for a 3-channel, 2-species
-# network on CDNA (full-rate VALU op = 1 slot; 32-bit integer multiplies,
-# 32x32->64 products and v_rcp_f64 = 4 slots).  Derivation per item:
+# network on CDNA (full-rate VALU op = 1 slot; 32-bit integer products and
+# v_rcp_f64 = 4 slots).  Derivation per item:
 #   gaps 3x(sub, mul, max, cmp, 2 sel) 18; argmin with second minimum 15;
-#   near-tie 3; time/termination/sample checks 3; internal-time update 3x3 9;
-#   jump with overflow check 10; firing counts 6; Philox4x32-10 10x(2 products
-#   x4 + 2 xor3) 100; 53-bit uniform 8; correctly rounded log fast phase 55;
-#   P refresh 8; three propensities with reciprocals 51.
+#   near-tie, time, termination and sample checks 6; internal-time update 9;
+#   jump with overflow check 10; firing counts 6; Philox4x32-10 10x(2
+#   products x4 + 2 xor3) 100; 53-bit uniform 8; correctly rounded log fast
+#   phase 55; P refresh 8; three propensities with reciprocals 51.
 ALG_SLOTS_PER_FIRING_LV = 286
+# Per firing of an M-channel network in the workgroup mapping: per channel
+# T update (1), gap (sub, mul, max, cmp, 2 sel = 6), argmin with second
+# minimum (5); plus the draw (~163 as above) and about 20 dependent
+# propensities with reciprocals (~17 each).
+def alg_slots_group(M, deps=20):
+    return 12 * M + 163 + 17 * deps
+
+
 PEAK_LANE_SLOTS = 256 * 4 * 16 * 2.4e9   # CUs x SIMDs x lanes x clock = 3.93e13 /s
 
 
@@ -35,6 +51,8 @@ def parse():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--trajectories", type=int, default=1 << 20)
+    ap.add_argument("--workload", default="all",
+                    choices=["all", "lv_ensemble", "large_random", "gradient"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--block", type=int, default=0)
@@ -45,16 +63,17 @@ def parse():
     return ap.parse_args()
 
 
-def cpu_baseline(w, target_s):
-    import numpy as np
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
 
+
+def cpu_baseline(w, target_s):
     import oracle
     threads = max(1, min(16, os.cpu_count() or 1))
-    probe_R = 2 * threads
+    probe_R = threads
     t0 = time.perf_counter()
-    o = oracle.simulate(w.net, w.x0, w.t_end, w.sample_t, w.seed, probe_R, threads=threads)
-    dt = time.perf_counter() - t0
-    per_traj = dt / probe_R
+    oracle.simulate(w.net, w.x0, w.t_end, w.sample_t, w.seed, probe_R, threads=threads)
+    per_traj = (time.perf_counter() - t0) / probe_R
     R = int(max(threads, min(w.R, target_s / max(per_traj, 1e-9))))
     R = (R // threads) * threads or threads
     t0 = time.perf_counter()
@@ -66,18 +85,8 @@ def cpu_baseline(w, target_s):
             "sample": "first %d of the %d trajectories (%d firings, %.1f s)" % (R, w.R, fir, dt)}
 
 
-def main():
-    args = parse()
-    if args.gpus != 1:
-        print("bench.py measures one GPU only; --gpus %d is not supported (trajectory "
-              "sharding across GPUs is described in DESIGN.md, not run)" % args.gpus,
-              file=sys.stderr)
-        sys.exit(2)
+def run_ensemble(api, w, steps, warmup, block=0, grid=0, mapping=0):
     import torch
-
-    from paper_2103_00405_amd import api, workloads as W
-
-    w = W.lv_ensemble(args.trajectories)
     dev = torch.device("cuda:0")
     net = api.Network(w.net, device=dev)
     R, G, N, M = w.R, len(w.sample_t), w.net.N, w.net.M
@@ -93,27 +102,139 @@ def main():
 
     def step():
         return api.simulate(net, x0, w.t_end, s, R, seed=w.seed, out=out, want=tuple(out),
-                            block=args.block, grid=args.grid)["stats"]
+                            block=block, grid=grid, mapping=mapping)["stats"]
 
-    for i in range(args.warmup):
+    for i in range(warmup):
         st = step()
-        print("warmup %d: %.1f ms, %d firings" % (i, st["kernel_ms"], st["firings"]),
-              file=sys.stderr, flush=True)
+        log("%s warmup %d: %.1f ms, %d firings" % (w.name, i, st["kernel_ms"], st["firings"]))
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     firings, kms = 0, []
-    for i in range(args.steps):
+    for i in range(steps):
         st = step()
         firings += st["firings"]
         kms.append(st["kernel_ms"])
-        print("step %d: %.1f ms, %d firings" % (i, st["kernel_ms"], st["firings"]),
-              file=sys.stderr, flush=True)
+        log("%s step %d: %.1f ms, %d firings" % (w.name, i, st["kernel_ms"], st["firings"]))
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    value = firings / wall
-    k_avg_s = sum(kms) / len(kms) / 1e3
-    fir_per_launch = firings / args.steps
-    achieved = ALG_SLOTS_PER_FIRING_LV * fir_per_launch / k_avg_s
+    return dict(firings=firings, wall=wall, kernel_s=sum(kms) / len(kms) / 1e3, stats=st,
+                firings_per_step=firings / steps)
+
+
+def bench_large(api, W, steps, warmup):
+    w = W.large_random()
+    r = run_ensemble(api, w, steps, warmup)
+    slots = alg_slots_group(w.net.M)
+    ach = slots * r["firings_per_step"] / r["kernel_s"]
+    return {"workload": "large_random_network", "N": w.net.N, "M": w.net.M, "trajectories": w.R,
+            "t_end": w.t_end, "value": r["firings"] / r["wall"], "unit": "firings/s",
+            "ms_per_step": r["wall"] / steps * 1e3, "firings_per_step": r["firings_per_step"],
+            "mapping": "workgroup", "block": r["stats"]["block"], "grid": r["stats"]["grid"],
+            "roofline": {"bound": "alu", "achieved": ach / 1e12, "peak": PEAK_LANE_SLOTS / 1e12,
+                         "unit": "Tslot/s", "frac": ach / PEAK_LANE_SLOTS,
+                         "slots_per_firing": slots, "kernel_ms": r["kernel_s"] * 1e3}}
+
+
+def bench_gradient(api, W, reps=3):
+    """Gradient evals/s (forward + f + backward kernel) vs plain evals/s
+    (forward + f), and vs central finite differences in log c (2M extra
+    forwards with common random numbers) at equal standard error."""
+    import numpy as np
+    import torch
+    res = {}
+    for w in (W.bd_gradient(), W.lv_gradient()):
+        net = api.Network(w.net)
+        R, M = w.R, w.net.M
+        x0 = torch.tensor(w.x0, dtype=torch.int32, device="cuda")
+        grid = torch.tensor([w.t_end], dtype=torch.float64, device="cuda")
+        out = {"x_final": torch.empty((R, w.net.N), dtype=torch.int32, device="cuda"),
+               "n": torch.empty((R, M), dtype=torch.int32, device="cuda"),
+               "T": torch.empty((R, M), dtype=torch.float64, device="cuda")}
+
+        def forward(seed, c=None):
+            if c is not None:
+                net.set_rates(c)
+            o = api.simulate(net, x0, w.t_end, grid, R, seed=seed, out=out,
+                             want=("x_final", "n", "T"), stats=False)
+            return o["x_final"][:, 0].to(torch.float64)
+
+        def plain(seed):
+            f = forward(seed)
+            return float(f.mean())
+
+        def grad(seed):
+            f = forward(seed)
+            g, se = api.score_grad(f, out["n"], out["T"])
+            return g, se
+
+        def fd(seed):
+            c0 = np.array(w.net.c)
+            ds = []
+            for k in range(M):
+                vals = []
+                for sgn in (1, -1):
+                    c = c0.copy()
+                    c[k] *= math.exp(sgn * 1e-3)
+                    vals.append(forward(seed, c))
+                ds.append((vals[0] - vals[1]) / 2e-3)
+            net.set_rates(c0)
+            return ds
+
+        timings = {}
+        for name, fn in (("plain", plain), ("gradient", grad), ("fd", fd)):
+            fn(100)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for i in range(reps):
+                last = fn(101 + i)
+            torch.cuda.synchronize()
+            timings[name] = (time.perf_counter() - t0) / reps
+            if name == "gradient":
+                g_last, se_last = last
+            if name == "fd":
+                fd_last = last
+        se_score = se_last.cpu().numpy()
+        se_fd = np.array([float(d.std() / math.sqrt(R)) for d in fd_last])
+        # cost to reach a common standard error scales with time x variance
+        eq = [(timings["fd"] * se_fd[k] ** 2) / (timings["gradient"] * se_score[k] ** 2)
+              for k in range(M)]
+        res[w.name] = {"trajectories": R, "M": M,
+                       "plain_evals_per_s": 1.0 / timings["plain"],
+                       "gradient_evals_per_s": 1.0 / timings["gradient"],
+                       "gradient_vs_plain": timings["plain"] / timings["gradient"],
+                       "fd_evals_per_s": 1.0 / timings["fd"],
+                       "gradient": [float(v) for v in g_last.cpu().numpy()],
+                       "se_score": [float(v) for v in se_score],
+                       "se_fd": [float(v) for v in se_fd],
+                       "score_vs_fd_at_equal_se": [float(v) for v in eq]}
+        log("%s: plain %.1f/s, gradient %.1f/s, fd %.2f/s" % (
+            w.name, 1 / timings["plain"], 1 / timings["gradient"], 1 / timings["fd"]))
+    return res
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only; --gpus %d is not supported (trajectory "
+              "sharding across GPUs is described in DESIGN.md, not run)" % args.gpus,
+              file=sys.stderr)
+        sys.exit(2)
+    import torch
+
+    from paper_2103_00405_amd import api, workloads as W
+
+    if args.workload in ("large_random", "gradient"):
+        out = bench_large(api, W, args.steps, args.warmup) if args.workload == "large_random" \
+            else bench_gradient(api, W)
+        print(json.dumps(out), flush=True)
+        return
+
+    w = W.lv_ensemble(args.trajectories)
+    r = run_ensemble(api, w, args.steps, args.warmup, args.block, args.grid)
+    st = r["stats"]
+    value = r["firings"] / r["wall"]
+    achieved = ALG_SLOTS_PER_FIRING_LV * r["firings_per_step"] / r["kernel_s"]
+    N, M, G = w.net.N, w.net.M, len(w.sample_t)
     res = {
         "metric": "reaction firings/sec per GPU (ensemble)",
         "value": value,
@@ -121,31 +242,35 @@ def main():
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": wall / args.steps * 1e3,
+        "ms_per_step": r["wall"] / args.steps * 1e3,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": "lotka_volterra_ensemble", "N": N, "M": M, "trajectories": R,
+        "config": {"workload": "lotka_volterra_ensemble", "N": N, "M": M, "trajectories": w.R,
                    "t_end": w.t_end, "grid_points": G, "x0": [int(v) for v in w.x0],
                    "c": [float(v) for v in w.net.c], "mapping": "thread", "block": st["block"],
                    "grid": st["grid"], "parallelism": "trajectories"},
-        "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_LANE_SLOTS / 1e12,
-                     "unit": "Tslot/s", "frac": achieved / PEAK_LANE_SLOTS, "traffic": None,
-                     "kernel": "rt_thread_kernel<3,2>", "kernel_ms": k_avg_s * 1e3,
+        "roofline": {"bound": "alu", "achieved": achieved / 1e12,
+                     "peak": PEAK_LANE_SLOTS / 1e12, "unit": "Tslot/s",
+                     "frac": achieved / PEAK_LANE_SLOTS, "traffic": None,
+                     "kernel": "rt_thread_kernel<3,2>", "kernel_ms": r["kernel_s"] * 1e3,
                      "slots_per_firing": ALG_SLOTS_PER_FIRING_LV},
-        "firings_per_step": fir_per_launch,
+        "firings_per_step": r["firings_per_step"],
         "near_ties": st["near_ties"],
         "slow_logs": st["slow_logs"],
     }
     if args.calibrate_copy_mib:
         nb = args.calibrate_copy_mib << 20
-        src = torch.ones(nb // 4, dtype=torch.int32, device=dev)
+        src = torch.ones(nb // 4, dtype=torch.int32, device="cuda:0")
         dst = torch.empty_like(src)
         dst.copy_(src)
         torch.cuda.synchronize()
         res["calibration_copy_bytes"] = nb
+    if args.workload == "all":
+        res["secondary"] = {"large_random": bench_large(api, W, 2, 1),
+                            "gradient": bench_gradient(api, W)}
     if not args.no_cpu_baseline:
         res["cpu_baseline"] = cpu_baseline(w, args.cpu_seconds)
     print(json.dumps(res), flush=True)

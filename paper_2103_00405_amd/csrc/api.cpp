@@ -19,37 +19,108 @@ int rt_fail(int code, const std::string& msg)
 extern "C" const char* rtssa_last_error(void) { return g_last_error.c_str(); }
 extern "C" const char* rtssa_version(void) { return "rtssa 0.1 (gfx950)"; }
 
-static int check_hip(hipError_t e, const char* what)
+int check_hip(hipError_t e, const char* what)
 {
     if (e == hipSuccess) return RTSSA_OK;
     return rt_fail(RTSSA_E_HIP, std::string(what) + ": " + hipGetErrorString(e));
 }
 
 // Mapping chosen from the network size: thread-per-trajectory for register-
-// sized networks, one wavefront for up to 64 x 16 channels, else a workgroup.
+// sized networks, sub-wavefront groups (4..64 lanes) up to 512 channels, a
+// workgroup beyond.
 int rt_auto_mapping(const rtssa_network* net)
 {
     if (rt_thread_supported(net->M, net->N)) return RTSSA_MAP_THREAD;
-    if (net->M <= 512) return RTSSA_MAP_WAVE;
+    if (net->M <= 512 && net->max_nu <= 64) return RTSSA_MAP_WAVE;
     return RTSSA_MAP_WORKGROUP;
 }
 
 int rt_auto_group_size(int M)
 {
-    if (M <= 1024) return 256;
-    if (M <= 4096) return 1024;
+    (void)M;
     return 1024;
 }
 
-extern "C" int rtssa_simulate(const rtssa_network* net, const int32_t* x0, int32_t x0_per_traj,
-                              double t_end, const double* sample_t, int32_t G, uint64_t seed,
-                              uint32_t net_id, uint64_t traj_offset, int64_t R, int32_t* samples,
-                              int64_t s_stride_r, int64_t s_stride_g, int64_t s_stride_n,
-                              uint32_t* n_out, double* T_out, int32_t* x_final, double* t_last,
-                              uint8_t* status, uint64_t* seq_hash, uint32_t* tie_step,
-                              const rtssa_options* opt, rtssa_stream_t stream_, rtssa_stats* stats)
+// Lanes per trajectory of the sub-wave mapping: the requested value, or the
+// fewest lanes holding every channel in at most 8 slots; never fewer lanes
+// than species changed by one reaction.
+int rt_pick_lanes(const rtssa_network* net, int requested)
 {
-    hipStream_t stream = (hipStream_t)stream_;
+    int L = requested > 0 ? requested : rt_subwave_lanes(net->M);
+    while (L < 64 && L < net->max_nu) L <<= 1;
+    return L;
+}
+
+// Launch one class with the given mapping; block = lanes per trajectory for
+// the sub-wave mapping, threads per trajectory for the workgroup mapping,
+// workgroup size for the thread mapping.
+int rt_launch_class(int mapping, int max_M, int max_N, int max_nu, const rt_class_dev& C,
+                    int block, int grid, int64_t lanes, hipStream_t stream, int* block_used,
+                    int* grid_used)
+{
+    if (mapping == RTSSA_MAP_THREAD) {
+        if (block <= 0) block = 256;
+        *block_used = block;
+        return rt_launch_thread(max_M, max_N, C, block, grid, stream, grid_used, lanes);
+    }
+    if (mapping == RTSSA_MAP_WAVE) {
+        int L = block > 0 ? block : rt_subwave_lanes(max_M);
+        while (L < 64 && L < max_nu) L <<= 1;
+        if (L != 4 && L != 8 && L != 16 && L != 32 && L != 64)
+            return rt_fail(RTSSA_E_INVALID, "sub-wave lanes per trajectory must be 4..64, a power of 2");
+        if (max_M > 8 * L) return rt_fail(RTSSA_E_UNSUPPORTED, "too many channels for this lane count");
+        if (max_nu > L) return rt_fail(RTSSA_E_UNSUPPORTED, "a reaction changes more species than lanes");
+        *block_used = L;
+        return rt_launch_subwave(max_M, C, L, grid, stream, grid_used);
+    }
+    if (mapping == RTSSA_MAP_WORKGROUP) {
+        int L = block > 0 ? block : rt_auto_group_size(max_M);
+        if (L != 64 && L != 128 && L != 256 && L != 512 && L != 1024)
+            return rt_fail(RTSSA_E_INVALID, "group size must be 64, 128, 256, 512 or 1024");
+        if (max_nu > 64) return rt_fail(RTSSA_E_UNSUPPORTED, "a reaction changes more than 64 species");
+        *block_used = L;
+        return rt_launch_group(max_M, max_N, max_M, C, L, grid, stream, grid_used);
+    }
+    return rt_fail(RTSSA_E_INVALID, "unknown mapping");
+}
+
+// Item descriptor of one run (host copy).
+rt_item_dev rt_make_item(const rtssa_network* net, const int32_t* x0, int32_t x0_per_traj,
+                         double t_end, const double* sample_t, int32_t G, uint32_t net_id,
+                         uint64_t traj_offset, int64_t R, int32_t* samples, int64_t s_stride_r,
+                         int64_t s_stride_g, int64_t s_stride_n, uint32_t* n_out, double* T_out,
+                         int32_t* x_final, double* t_last, uint8_t* status, uint64_t* seq_hash,
+                         uint32_t* tie_step)
+{
+    rt_item_dev it{};
+    it.net = net->dev;
+    it.x0 = x0;
+    it.x0_per_traj = x0_per_traj;
+    it.G = G;
+    it.t_end = t_end;
+    it.s = sample_t;
+    it.net_id = net_id;
+    it.traj_offset = (uint32_t)traj_offset;
+    it.R = R;
+    it.samples = samples;
+    it.ss_r = s_stride_r;
+    it.ss_g = s_stride_g;
+    it.ss_n = s_stride_n;
+    it.n_out = n_out;
+    it.T_out = T_out;
+    it.x_final = x_final;
+    it.t_last = t_last;
+    it.status = status;
+    it.seq_hash = (unsigned long long*)seq_hash;
+    it.tie_step = tie_step;
+    return it;
+}
+
+// Validates the sample grid (read once from the device) and the run sizes.
+int rt_check_run(const rtssa_network* net, const int32_t* x0, int32_t x0_per_traj, double t_end,
+                 const double* sample_t, int32_t G, uint64_t traj_offset, int64_t R,
+                 hipStream_t stream)
+{
     if (!net) return rt_fail(RTSSA_E_INVALID, "net is NULL");
     if (R < 0 || G < 0) return rt_fail(RTSSA_E_INVALID, "R and G must be >= 0");
     if (!(t_end >= 0.0) || !isfinite(t_end)) return rt_fail(RTSSA_E_INVALID, "t_end must be finite and >= 0");
@@ -58,15 +129,7 @@ extern "C" int rtssa_simulate(const rtssa_network* net, const int32_t* x0, int32
     if (R > 0 && !x0 && net->N > 0) return rt_fail(RTSSA_E_INVALID, "x0 is NULL");
     if (G > 0 && !sample_t) return rt_fail(RTSSA_E_INVALID, "sample_t is NULL with G > 0");
     if (x0_per_traj != 0 && x0_per_traj != 1) return rt_fail(RTSSA_E_INVALID, "x0_per_traj must be 0 or 1");
-    rtssa_options o{};
-    if (opt) o = *opt;
-    uint64_t maxf = o.max_firings ? o.max_firings : 10000000ull;
-    if (maxf > 0xFFFFFFFFull) return rt_fail(RTSSA_E_INVALID, "max_firings must be < 2^32");
-    if (stats) memset(stats, 0, sizeof(*stats));
-    if (R == 0) return RTSSA_OK;
-
-    // the sample grid must be sorted and inside [0, t_end]
-    if (G > 0) {
+    if (G > 0 && R > 0) {
         std::vector<double> s(G);
         int rc = check_hip(hipMemcpyAsync(s.data(), sample_t, sizeof(double) * G,
                                           hipMemcpyDeviceToHost, stream), "reading sample_t");
@@ -79,76 +142,84 @@ extern "C" int rtssa_simulate(const rtssa_network* net, const int32_t* x0, int32
                 return rt_fail(RTSSA_E_INVALID, "sample_t must be non-decreasing");
         }
     }
+    return RTSSA_OK;
+}
 
-    int mapping = o.mapping;
-    if (mapping == RTSSA_MAP_AUTO)
-        mapping = rt_auto_mapping(net);
+void rt_fill_stats(rtssa_stats* stats, const rt_ws& h)
+{
+    stats->firings += h.firings;
+    stats->near_ties += h.near_ties;
+    stats->clamps += h.clamps;
+    stats->slow_logs += h.slow_logs;
+    for (int q = 0; q < 4; ++q) stats->status_count[q] += h.status_count[q];
+}
 
-    rt_ws* ws = nullptr;
-    int rc = check_hip(hipMallocAsync((void**)&ws, sizeof(rt_ws), stream), "workspace allocation");
+struct rt_run_scratch {
+    rt_ws ws;
+    rt_item_dev item;
+    int64_t unit_start[2];
+    unsigned long long item_next[2];
+};
+
+extern "C" int rtssa_simulate(const rtssa_network* net, const int32_t* x0, int32_t x0_per_traj,
+                              double t_end, const double* sample_t, int32_t G, uint64_t seed,
+                              uint32_t net_id, uint64_t traj_offset, int64_t R, int32_t* samples,
+                              int64_t s_stride_r, int64_t s_stride_g, int64_t s_stride_n,
+                              uint32_t* n_out, double* T_out, int32_t* x_final, double* t_last,
+                              uint8_t* status, uint64_t* seq_hash, uint32_t* tie_step,
+                              const rtssa_options* opt, rtssa_stream_t stream_, rtssa_stats* stats)
+{
+    hipStream_t stream = (hipStream_t)stream_;
+    rtssa_options o{};
+    if (opt) o = *opt;
+    uint64_t maxf = o.max_firings ? o.max_firings : 10000000ull;
+    if (maxf > 0xFFFFFFFFull) return rt_fail(RTSSA_E_INVALID, "max_firings must be < 2^32");
+    if (stats) memset(stats, 0, sizeof(*stats));
+    int rc = rt_check_run(net, x0, x0_per_traj, t_end, sample_t, G, traj_offset, R, stream);
     if (rc) return rc;
-    rt_sim_params p{};
-    p.x0 = x0;
-    p.x0_per_traj = x0_per_traj;
-    p.G = G;
-    p.t_end = t_end;
-    p.s = sample_t;
-    p.key0 = (uint32_t)seed;
-    p.key1 = (uint32_t)(seed >> 32);
-    p.net_id = net_id;
-    p.traj_offset = (uint32_t)traj_offset;
-    p.R = R;
-    p.max_firings = (uint32_t)maxf;
-    p.samples = samples;
-    p.ss_r = s_stride_r;
-    p.ss_g = s_stride_g;
-    p.ss_n = s_stride_n;
-    p.n_out = n_out;
-    p.T_out = T_out;
-    p.x_final = x_final;
-    p.t_last = t_last;
-    p.status = status;
-    p.seq_hash = (unsigned long long*)seq_hash;
-    p.tie_step = tie_step;
-    p.ws = ws;
+    if (R == 0) return RTSSA_OK;
+    int mapping = o.mapping == RTSSA_MAP_AUTO ? rt_auto_mapping(net) : o.mapping;
+
+    rt_run_scratch* sc = nullptr;
+    rc = check_hip(hipMallocAsync((void**)&sc, sizeof(rt_run_scratch), stream), "scratch allocation");
+    if (rc) return rc;
+    const rt_item_dev item = rt_make_item(net, x0, x0_per_traj, t_end, sample_t, G, net_id,
+                                          traj_offset, R, samples, s_stride_r, s_stride_g,
+                                          s_stride_n, n_out, T_out, x_final, t_last, status,
+                                          seq_hash, tie_step);
+    rt_class_dev C{};
+    C.items = &sc->item;
+    C.unit_start = sc->unit_start;
+    C.item_next = sc->item_next;
+    C.ws = &sc->ws;
+    C.count = 1;
+    C.exclusive = 0;
+    C.max_N = net->N;
+    C.max_M = net->M;
+    C.max_firings = (uint32_t)maxf;
 
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     if (stats) {
         hipEventCreate(&ev0);
         hipEventCreate(&ev1);
     }
-    rc = rt_launch_zero_ws(ws, &p, stream);
+    rc = rt_launch_setup(&sc->ws, sc->item_next, 2, (uint32_t)seed, (uint32_t)(seed >> 32),
+                         nullptr, &item, &sc->item, sc->unit_start, stream);
     if (!rc && stats) hipEventRecord(ev0, stream);
-    int grid_used = 0, block_used = o.block;
-    if (!rc) {
-        if (mapping == RTSSA_MAP_THREAD) {
-            if (block_used <= 0) block_used = 256;
-            rc = rt_launch_thread(net, p, block_used, o.grid, stream, &grid_used);
-        } else if (mapping == RTSSA_MAP_WAVE || mapping == RTSSA_MAP_WORKGROUP) {
-            if (mapping == RTSSA_MAP_WAVE) block_used = 64;
-            else if (block_used <= 0) block_used = rt_auto_group_size(net->M);
-            if (block_used != 64 && block_used != 256 && block_used != 512 && block_used != 1024)
-                rc = rt_fail(RTSSA_E_INVALID, "group size must be 64, 256, 512 or 1024");
-            else
-                rc = rt_launch_group(net, p, block_used, o.grid, stream, &grid_used);
-        } else {
-            rc = rt_fail(RTSSA_E_INVALID, "unknown mapping");
-        }
-    }
+    int grid_used = 0, block_used = 0;
+    if (!rc)
+        rc = rt_launch_class(mapping, net->M, net->N, net->max_nu, C, o.block, o.grid, R, stream,
+                             &block_used, &grid_used);
     if (!rc && stats) {
         hipEventRecord(ev1, stream);
         rt_ws h{};
-        rc = check_hip(hipMemcpyAsync(&h, ws, sizeof(rt_ws), hipMemcpyDeviceToHost, stream),
+        rc = check_hip(hipMemcpyAsync(&h, &sc->ws, sizeof(rt_ws), hipMemcpyDeviceToHost, stream),
                        "reading stats");
         if (!rc) rc = check_hip(hipStreamSynchronize(stream), "simulation");
         if (!rc) {
             float ms = 0.f;
             hipEventElapsedTime(&ms, ev0, ev1);
-            stats->firings = h.firings;
-            stats->near_ties = h.near_ties;
-            stats->clamps = h.clamps;
-            stats->slow_logs = h.slow_logs;
-            for (int q = 0; q < 4; ++q) stats->status_count[q] = h.status_count[q];
+            rt_fill_stats(stats, h);
             stats->kernel_ms = ms;
             stats->mapping = mapping;
             stats->block = block_used;
@@ -157,7 +228,7 @@ extern "C" int rtssa_simulate(const rtssa_network* net, const int32_t* x0, int32
     }
     if (ev0) hipEventDestroy(ev0);
     if (ev1) hipEventDestroy(ev1);
-    hipFreeAsync(ws, stream);
+    hipFreeAsync(sc, stream);
     return rc;
 }
 

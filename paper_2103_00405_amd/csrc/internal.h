@@ -47,23 +47,17 @@ struct rtssa_network {
 };
 
 
-// Fields the per-firing path reads; passed by value.
-struct rt_hot_params {
-    double t_end;
-    uint32_t key0, key1, net_id, traj_offset;
-    uint32_t max_firings;
-    int32_t pad;
-};
-
-struct rt_sim_params {
+// One network and its run parameters, in device memory: the unit of work
+// description of every kernel (a single run is a batch of one item).
+struct rt_item_dev {
+    rt_net_dev net;
     const int32_t* x0;
     int32_t x0_per_traj;
     int32_t G;
     double t_end;
     const double* s;
-    uint32_t key0, key1, net_id, traj_offset;
+    uint32_t net_id, traj_offset;
     int64_t R;
-    uint32_t max_firings;
     int32_t* samples;
     int64_t ss_r, ss_g, ss_n;
     uint32_t* n_out;
@@ -73,29 +67,62 @@ struct rt_sim_params {
     uint8_t* status;
     unsigned long long* seq_hash;
     uint32_t* tie_step;
-    struct rt_ws* ws;
 };
 
-// Device workspace: counters written by the kernels, the work-queue head of
-// the persistent kernels, and a copy of the launch parameters that rare code
-// paths read through a pointer (keeping them out of scalar registers).
+// Device workspace of one launch (or one class of a batch): counters written
+// by the kernels, the work-queue heads, and the Philox key.
 struct rt_ws {
     unsigned long long firings, near_ties, clamps, slow_logs;
     unsigned long long status_count[4];
-    unsigned long long next_traj;
-    unsigned long long pad[7];
-    rt_sim_params params;
+    unsigned long long next_unit;    // trajectory units or items handed out
+    uint32_t key0, key1;
+    unsigned long long pad[6];
+};
+
+// A class of items run by one persistent kernel: items[0 .. count); the
+// trajectory units of item i are unit_start[i] .. unit_start[i+1]-1.
+// item_next[i] counts the trajectories of item i handed to lanes of the
+// thread mapping.  exclusive = 1: one wavefront takes a whole item (batches,
+// so that a wavefront's lanes share one network); 0: every wavefront works
+// on item 0 (a single run).
+struct rt_class_dev {
+    const rt_item_dev* items;
+    const int64_t* unit_start;
+    unsigned long long* item_next;
+    rt_ws* ws;
+    int32_t count;
+    int32_t exclusive;
+    int32_t max_N;
+    int32_t max_M;
+    uint32_t max_firings;
+    int32_t pad;
 };
 
 // error reporting and mapping choice (api.cpp)
 int rt_fail(int code, const std::string& msg);
 int rt_auto_mapping(const rtssa_network* net);
 int rt_auto_group_size(int M);
+int rt_launch_class(int mapping, int max_M, int max_N, int max_nu, const rt_class_dev& C,
+                    int block, int grid, int64_t lanes, hipStream_t stream, int* block_used,
+                    int* grid_used);
+rt_item_dev rt_make_item(const rtssa_network* net, const int32_t* x0, int32_t x0_per_traj,
+                         double t_end, const double* sample_t, int32_t G, uint32_t net_id,
+                         uint64_t traj_offset, int64_t R, int32_t* samples, int64_t s_stride_r,
+                         int64_t s_stride_g, int64_t s_stride_n, uint32_t* n_out, double* T_out,
+                         int32_t* x_final, double* t_last, uint8_t* status, uint64_t* seq_hash,
+                         uint32_t* tie_step);
+int rt_check_run(const rtssa_network* net, const int32_t* x0, int32_t x0_per_traj, double t_end,
+                 const double* sample_t, int32_t G, uint64_t traj_offset, int64_t R,
+                 hipStream_t stream);
+void rt_fill_stats(rtssa_stats* stats, const rt_ws& h);
+int check_hip(hipError_t e, const char* what);
 
-// kernels.hip
-int rt_launch_thread(const rtssa_network* net, const rt_sim_params& p, int block, int grid,
-                     hipStream_t stream, int* grid_used);
-int rt_launch_zero_ws(rt_ws* ws, const rt_sim_params* params, hipStream_t stream);
+// kernels: launchers take a class descriptor whose pointers are device memory
+int rt_launch_thread(int M, int N, const rt_class_dev& C, int block, int grid,
+                     hipStream_t stream, int* grid_used, int64_t lanes);
+int rt_launch_setup(rt_ws* ws, unsigned long long* extra, int64_t n_extra, uint32_t key0,
+                    uint32_t key1, const uint32_t* key_src, const rt_item_dev* item,
+                    rt_item_dev* item_dst, int64_t* unit_start, hipStream_t stream);
 int rt_launch_score_grad(const double* f, const uint32_t* n, const double* T, int64_t R,
                          int32_t M, int32_t baseline, double* grad, double* se,
                          hipStream_t stream);
@@ -104,7 +131,11 @@ int rt_launch_debug_neglog(const uint64_t* m, double* out, uint8_t* slow, int64_
 int rt_launch_debug_philox(const uint32_t* ctr, uint32_t k0, uint32_t k1, uint32_t* out,
                            int64_t count, hipStream_t stream);
 int rt_thread_supported(int M, int N);
-int rt_launch_group(const rtssa_network* net, const rt_sim_params& p, int L, int grid,
+int rt_launch_group(int M, int max_N, int max_M, const rt_class_dev& C, int L, int grid,
                     hipStream_t stream, int* grid_used);
 int rt_group_slots(int M, int L);
 size_t rt_group_lds_bytes(int N, int M);
+int rt_launch_subwave(int max_M, const rt_class_dev& C, int L, int grid, hipStream_t stream,
+                      int* grid_used);
+int rt_subwave_slots(int M, int L);
+int rt_subwave_lanes(int M);

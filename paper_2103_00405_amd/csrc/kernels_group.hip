@@ -95,21 +95,32 @@ struct rt_group_shared {
     uint32_t log_scratch[16][RT_LOG_SCRATCH];
 };
 
+// Index of the item owning global unit u: unit_start[i] <= u < unit_start[i+1].
+__device__ __forceinline__ int group_find_item(const int64_t* unit_start, int count, int64_t u)
+{
+    int lo = 0, hi = count;
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (unit_start[mid] <= u) lo = mid; else hi = mid;
+    }
+    return lo;
+}
+
 template <int L, int S>
-__global__ __launch_bounds__(L) void rt_group_kernel(rt_hot_params H, rt_ws* __restrict__ ws,
-                                                      rt_net_dev net)
+__global__ __launch_bounds__(L) void rt_group_kernel(rt_class_dev C)
 {
     constexpr int W = L / 64;
     extern __shared__ int32_t dyn_lds[];
     __shared__ rt_group_shared sh;
-    const rt_sim_params& P = ws->params;
-    const int N = net.N, M = net.M;
+    rt_ws* const ws = C.ws;
+    const uint32_t key0 = ws->key0, key1 = ws->key1;
+    const int64_t total = C.unit_start[C.count];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     int32_t* X = dyn_lds;                                   // [N]
     // two bitmaps of channels to refresh, alternating by event parity: one is
     // read (and then cleared) while the next event sets the other
-    const int nflag = (M + 31) >> 5;
-    uint32_t* flag_buf = (uint32_t*)(dyn_lds + ((N + 3) & ~3));   // [2][nflag]
+    const int nflag = (C.max_M + 31) >> 5;
+    uint32_t* flag_buf = (uint32_t*)(dyn_lds + ((C.max_N + 3) & ~3));   // [2][nflag]
     uint32_t* sc = sh.log_scratch[wave];
 
     double T[S], Pk[S], a[S], inv[S];
@@ -118,13 +129,20 @@ __global__ __launch_bounds__(L) void rt_group_kernel(rt_hot_params H, rt_ws* __r
     for (int s = 0; s < S; ++s) { T[s] = 0.0; Pk[s] = 0.0; a[s] = 0.0; inv[s] = 0.0; n[s] = 0; }
 
     for (;;) {
-        // ---- next trajectory
-        if (tid == 0) sh.next_traj = atomicAdd(&ws->next_traj, 1ull);
+        // ---- next trajectory unit
+        if (tid == 0) sh.next_traj = atomicAdd(&ws->next_unit, 1ull);
         __syncthreads();
-        const int64_t r = (int64_t)sh.next_traj;
-        if (r >= P.R) break;
-        const uint32_t traj = H.traj_offset + (uint32_t)r;
-        const int32_t* x0 = P.x0 + (P.x0_per_traj ? r * N : 0);
+        const int64_t u = (int64_t)sh.next_traj;
+        if (u >= total) break;
+        const int item = group_find_item(C.unit_start, C.count, u);
+        const rt_item_dev* it = C.items + item;
+        const rt_net_dev net = it->net;
+        const int N = net.N, M = net.M;
+        const int64_t r = u - C.unit_start[item];
+        const uint32_t traj = it->traj_offset + (uint32_t)r;
+        const uint32_t net_id = it->net_id;
+        const double t_end = it->t_end;
+        const int32_t* x0 = it->x0 + (it->x0_per_traj ? r * N : 0);
         for (int j = tid; j < N; j += L) X[j] = x0[j];
         for (int q = tid; q < 2 * nflag; q += L) flag_buf[q] = 0u;
         __syncthreads();
@@ -136,13 +154,13 @@ __global__ __launch_bounds__(L) void rt_group_kernel(rt_hot_params H, rt_ws* __r
             T[s] = 0.0;
             n[s] = 0;
             if (k < M) {
-                Pk[s] = rt_exp1_wave(H.key0, H.key1, traj, H.net_id, (uint32_t)k, 0u,
+                Pk[s] = rt_exp1_wave(key0, key1, traj, net_id, (uint32_t)k, 0u,
                                      &ws->slow_logs, sc);
                 a[s] = group_propensity(net.react[k], net.c[k], X);
                 inv[s] = 1.0 / a[s];
             }
         }
-        double t = 0.0, s_next = P.G > 0 ? P.s[0] : __builtin_inf();
+        double t = 0.0, s_next = it->G > 0 ? it->s[0] : __builtin_inf();
         int32_t g = 0;
         uint32_t fired = 0, tie = kTieNone;
         unsigned long long hash = kFnvOffset;
@@ -204,7 +222,7 @@ __global__ __launch_bounds__(L) void rt_group_kernel(rt_hot_params H, rt_ws* __r
             const int clamped = __builtin_amdgcn_readfirstlane(__shfl(loc.clamped, 0, 64));
             const double t_new = t + d1;
             if (d1 == __builtin_inf()) { st = RTSSA_TRAJ_ABSORBED; break; }
-            if (t_new > H.t_end) { st = RTSSA_TRAJ_OK; break; }
+            if (t_new > t_end) { st = RTSSA_TRAJ_OK; break; }
             if (d2 - d1 <= 1e-12 * d1) {
                 if (tid == 0) atomicAdd(&ws->near_ties, 1ull);
                 tie = tie == kTieNone ? fired : tie;
@@ -212,12 +230,12 @@ __global__ __launch_bounds__(L) void rt_group_kernel(rt_hot_params H, rt_ws* __r
             if (s_next < t_new) {
                 // sample points before the event see the current X
                 while (s_next < t_new) {
-                    if (P.samples) {
-                        int32_t* dst = P.samples + r * P.ss_r + (int64_t)g * P.ss_g;
-                        for (int j = tid; j < N; j += L) dst[j * P.ss_n] = X[j];
+                    if (it->samples) {
+                        int32_t* dst = it->samples + r * it->ss_r + (int64_t)g * it->ss_g;
+                        for (int j = tid; j < N; j += L) dst[j * it->ss_n] = X[j];
                     }
                     ++g;
-                    s_next = g < P.G ? P.s[g] : __builtin_inf();
+                    s_next = g < it->G ? it->s[g] : __builtin_inf();
                 }
                 __syncthreads();
             }
@@ -245,7 +263,7 @@ __global__ __launch_bounds__(L) void rt_group_kernel(rt_hot_params H, rt_ws* __r
                 uint32_t nm = n[0];
 #pragma unroll
                 for (int s = 1; s < S; ++s) nm = slot == s ? n[s] : nm;
-                E = rt_exp1_wave(H.key0, H.key1, traj, H.net_id, (uint32_t)mu, nm + 1u,
+                E = rt_exp1_wave(key0, key1, traj, net_id, (uint32_t)mu, nm + 1u,
                                  &ws->slow_logs, sc);
             }
             __syncthreads();                               // barrier 2
@@ -259,34 +277,34 @@ __global__ __launch_bounds__(L) void rt_group_kernel(rt_hot_params H, rt_ws* __r
             uint32_t* tmp = flags_rd;
             flags_rd = flags_wr;
             flags_wr = tmp;
-            if (fired >= H.max_firings) st = RTSSA_TRAJ_MAX_FIRINGS;   // apply, then stop
+            if (fired >= C.max_firings) st = RTSSA_TRAJ_MAX_FIRINGS;   // apply, then stop
         }
 
         // ---- end of the trajectory
         const bool good = st == RTSSA_TRAJ_OK || st == RTSSA_TRAJ_ABSORBED;
-        if (P.samples) {
-            for (; g < P.G; ++g) {
-                int32_t* dst = P.samples + r * P.ss_r + (int64_t)g * P.ss_g;
-                for (int j = tid; j < N; j += L) dst[j * P.ss_n] = good ? X[j] : -1;
+        if (it->samples) {
+            for (; g < it->G; ++g) {
+                int32_t* dst = it->samples + r * it->ss_r + (int64_t)g * it->ss_g;
+                for (int j = tid; j < N; j += L) dst[j * it->ss_n] = good ? X[j] : -1;
             }
         }
-        const double dt = H.t_end - t;
+        const double dt = t_end - t;
 #pragma unroll
         for (int s = 0; s < S; ++s) {
             const int k = tid + s * L;
             if (k < M) {
                 if (good) T[s] = fma(a[s], dt, T[s]);
-                if (P.n_out) P.n_out[r * M + k] = n[s];
-                if (P.T_out) P.T_out[r * M + k] = T[s];
+                if (it->n_out) it->n_out[r * M + k] = n[s];
+                if (it->T_out) it->T_out[r * M + k] = T[s];
             }
         }
-        if (P.x_final)
-            for (int j = tid; j < N; j += L) P.x_final[r * N + j] = X[j];
+        if (it->x_final)
+            for (int j = tid; j < N; j += L) it->x_final[r * N + j] = X[j];
         if (tid == 0) {
-            if (P.t_last) P.t_last[r] = t;
-            if (P.status) P.status[r] = (uint8_t)st;
-            if (P.seq_hash) P.seq_hash[r] = hash;
-            if (P.tie_step) P.tie_step[r] = tie;
+            if (it->t_last) it->t_last[r] = t;
+            if (it->status) it->status[r] = (uint8_t)st;
+            if (it->seq_hash) it->seq_hash[r] = hash;
+            if (it->tie_step) it->tie_step[r] = tie;
             atomicAdd(&ws->firings, (unsigned long long)fired);
             atomicAdd(&ws->status_count[st], 1ull);
         }
@@ -294,7 +312,7 @@ __global__ __launch_bounds__(L) void rt_group_kernel(rt_hot_params H, rt_ws* __r
     }
 }
 
-typedef void (*group_kernel_t)(rt_hot_params, rt_ws*, rt_net_dev);
+typedef void (*group_kernel_t)(rt_class_dev);
 
 template <int L, int S>
 group_kernel_t pick_kernel() { return rt_group_kernel<L, S>; }
@@ -303,7 +321,8 @@ group_kernel_t select_group(int L, int S)
 {
 #define RT_CASE(l, s) if (L == l && S == s) return pick_kernel<l, s>();
     RT_CASE(64, 1) RT_CASE(64, 2) RT_CASE(64, 4) RT_CASE(64, 8) RT_CASE(64, 16)
-    RT_CASE(256, 1) RT_CASE(256, 2) RT_CASE(256, 4) RT_CASE(256, 8)
+    RT_CASE(256, 1) RT_CASE(256, 2) RT_CASE(256, 4) RT_CASE(256, 8) RT_CASE(256, 16)
+    RT_CASE(128, 16) RT_CASE(128, 32)
     RT_CASE(512, 1) RT_CASE(512, 2) RT_CASE(512, 4) RT_CASE(512, 8)
     RT_CASE(1024, 1) RT_CASE(1024, 2) RT_CASE(1024, 4) RT_CASE(1024, 8)
 #undef RT_CASE
@@ -325,15 +344,13 @@ int rt_group_slots(int M, int L)
     return p < 1 ? 1 : p;
 }
 
-int rt_launch_group(const rtssa_network* net, const rt_sim_params& p, int L, int grid,
+int rt_launch_group(int M, int max_N, int max_M, const rt_class_dev& C, int L, int grid,
                     hipStream_t stream, int* grid_used)
 {
-    const int S = rt_group_slots(net->M, L);
+    const int S = rt_group_slots(M, L);
     group_kernel_t kfn = select_group(L, S);
     if (!kfn) return rt_fail(RTSSA_E_UNSUPPORTED, "no group kernel for this network size and L");
-    if (net->max_nu > 64)
-        return rt_fail(RTSSA_E_UNSUPPORTED, "a reaction changes more than 64 species");
-    const size_t lds = rt_group_lds_bytes(net->N, net->M);
+    const size_t lds = rt_group_lds_bytes(max_N, max_M);
     if (lds > 96 * 1024) return rt_fail(RTSSA_E_UNSUPPORTED, "network too large for LDS");
     if (lds > 48 * 1024 &&
         hipFuncSetAttribute((const void*)kfn, hipFuncAttributeMaxDynamicSharedMemorySize,
@@ -346,18 +363,10 @@ int rt_launch_group(const rtssa_network* net, const rt_sim_params& p, int L, int
         if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kfn, L, lds) != hipSuccess ||
             per_cu < 1)
             per_cu = 1;
-        const int64_t full = (int64_t)cus * per_cu;
-        grid = (int)std::max<int64_t>(1, std::min<int64_t>(p.R, full));
+        grid = cus * per_cu;
     }
     if (grid_used) *grid_used = grid;
-    rt_hot_params h{};
-    h.t_end = p.t_end;
-    h.key0 = p.key0;
-    h.key1 = p.key1;
-    h.net_id = p.net_id;
-    h.traj_offset = p.traj_offset;
-    h.max_firings = p.max_firings;
-    hipLaunchKernelGGL(kfn, dim3(grid), dim3(L), lds, stream, h, p.ws, net->dev);
+    hipLaunchKernelGGL(kfn, dim3(grid), dim3(L), lds, stream, C);
     return hipGetLastError() == hipSuccess ? RTSSA_OK
                                            : rt_fail(RTSSA_E_HIP, "group kernel launch failed");
 }

@@ -1,0 +1,362 @@
+// kernels_subwave.hip -- L lanes per trajectory (L = 4 .. 64), 64 / L
+// trajectories per wavefront, for mid-size networks.
+//
+// Channel k of a trajectory belongs to lane k mod L of its group, slot k / L;
+// T_k, P_k, a_k, 1/a_k and n_k live in that lane's VGPRs.  Each group has its
+// own species counts X and two dependency bitmaps in LDS.  The groups of a
+// wavefront advance in lockstep, one firing per pass, but each group runs its
+// own trajectory: the expensive per-firing tail (one Philox block and one
+// correctly rounded logarithm for the fired channel, Eq. 26) runs in one lane
+// per group, so a wavefront pays it once for 64 / L firings.  There are no
+// workgroup barriers: a group lives inside one wavefront, whose LDS accesses
+// complete in program order.
+//
+// Work units are trajectories of the class's items, taken from a device
+// counter by one lane per group; every rare event (start or end of a
+// trajectory, a sample point, a near-tie, a clamped gap, an overflow, the
+// firing cap) is handled in a branch entered only when some group needs it.
+#include <hip/hip_runtime.h>
+
+#include "internal.h"
+#include "rt_device.h"
+
+namespace {
+
+constexpr uint32_t kTieNone = 0xFFFFFFFFu;
+constexpr unsigned long long kFnvOffset = 0xcbf29ce484222325ull;
+constexpr unsigned long long kFnvPrime = 0x100000001b3ull;
+constexpr int kBlock = 256;
+
+__device__ __forceinline__ double u64_to_f64(uint64_t h)
+{
+    return fma((double)(uint32_t)(h >> 32), 0x1p32, (double)(uint32_t)h);
+}
+
+// a_k = RN(c_k RN(h_k(X))) with X in LDS (Eq. 1-2).
+__device__ __forceinline__ double sw_propensity(int2 rr, double c, const int32_t* X)
+{
+    const int kind = (int)((uint32_t)rr.x >> 29);
+    const int s0 = rr.x & RT_SPECIES_MASK;
+    uint64_t h;
+    if (kind == RT_H_ZERO) {
+        h = 1;
+    } else if (kind == RT_H_ONE) {
+        h = (uint32_t)X[s0];
+    } else if (kind == RT_H_PAIR) {
+        const uint32_t x = (uint32_t)X[s0];
+        h = ((uint64_t)x * (uint32_t)(x - 1u)) >> 1;
+    } else {
+        h = (uint64_t)(uint32_t)X[s0] * (uint32_t)X[rr.y];
+    }
+    return c * u64_to_f64(h);
+}
+
+// Orders the wavefront's LDS accesses (the hardware completes them in order
+// for one wavefront; this keeps the compiler from reordering them).
+__device__ __forceinline__ void wave_lds_fence()
+{
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+}
+
+// Index of the item owning global unit u: unit_start[i] <= u < unit_start[i+1].
+__device__ __forceinline__ int find_item(const int64_t* unit_start, int count, int64_t u)
+{
+    int lo = 0, hi = count;   // unit_start[lo] <= u < unit_start[hi]
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (unit_start[mid] <= u) lo = mid; else hi = mid;
+    }
+    return lo;
+}
+
+#ifndef RT_SUBWAVE_MIN_WAVES
+#define RT_SUBWAVE_MIN_WAVES 2
+#endif
+
+template <int L, int S>
+__global__ __launch_bounds__(kBlock, RT_SUBWAVE_MIN_WAVES) void rt_subwave_kernel(rt_class_dev C)
+{
+    constexpr unsigned long long kGroupBits = L == 64 ? ~0ull : ((1ull << L) - 1ull);
+    rt_ws* const ws = C.ws;
+    const uint32_t key0 = ws->key0, key1 = ws->key1;
+    const int tid = threadIdx.x, li = tid % L, lane = tid & 63;
+    const unsigned long long gmask = kGroupBits << (lane - li);
+    extern __shared__ int32_t dyn_lds[];
+    __shared__ uint32_t log_scratch[kBlock / 64][RT_LOG_SCRATCH];
+    uint32_t* sc = log_scratch[tid >> 6];
+    const int NP = (C.max_N + 3) & ~3, NF = (C.max_M + 31) >> 5;
+    int32_t* X = dyn_lds + (tid / L) * (NP + 2 * NF);
+    uint32_t* fb = (uint32_t*)(X + NP);                 // [2][NF] dependency bitmaps
+    const int64_t total = C.unit_start[C.count];
+
+    // channel state of this lane's slots
+    double T[S], Pk[S], a[S], inv[S];
+    uint32_t n[S];
+#pragma unroll
+    for (int s = 0; s < S; ++s) { T[s] = 0.0; Pk[s] = 0.0; a[s] = 0.0; inv[s] = 0.0; n[s] = 0; }
+    // trajectory context (identical in every lane of the group)
+    const rt_item_dev* it = C.items;
+    int M = 0, N = 0, rd = 0, mu = 0;
+    int64_t r = 0;
+    uint32_t traj = 0, net_id = 0, fired = 0, tie = kTieNone;
+    double t = 0.0, t_end = 0.0, s_next = 0.0, delta = 0.0, E = 0.0;
+    int32_t g = 0;
+    unsigned long long hash = kFnvOffset;
+    bool active = true, fresh = true, capped = false, pending = false;
+
+    while (__ballot(active) != 0ull) {
+        if (!active) continue;
+        const rt_net_dev& net = it->net;
+        uint32_t* const flags_rd = fb + rd * NF;          // set by the pending event
+        uint32_t* const flags_wr = fb + (rd ^ 1) * NF;    // set by this pass's event
+        // ---- pass over own channels: apply the pending event, refresh, gap
+        double d1 = __builtin_inf(), d2 = __builtin_inf();
+        int kmin = 0x7FFFFFFF, clamped = 0;
+#pragma unroll
+        for (int s = 0; s < S; ++s) {
+            const int k = li + s * L;
+            if (k < M) {
+                if (pending) {
+                    if (k == mu) {
+                        T[s] = Pk[s];
+                        Pk[s] = Pk[s] + E;
+                        n[s] += 1u;
+                    } else {
+                        T[s] = fma(a[s], delta, T[s]);
+                    }
+                    if (flags_rd[k >> 5] & (1u << (k & 31))) {
+                        a[s] = sw_propensity(net.react[k], net.c[k], X);
+                        inv[s] = 1.0 / a[s];
+                    }
+                }
+                const double raw = (Pk[s] - T[s]) * inv[s];
+                double d = raw < 0.0 ? 0.0 : raw;
+                d = a[s] == 0.0 ? __builtin_inf() : d;
+                const bool lt = d < d1;
+                d2 = lt ? d1 : (d < d2 ? d : d2);
+                d1 = lt ? d : d1;
+                kmin = lt ? k : kmin;
+                clamped = lt ? (raw < 0.0) : clamped;
+            }
+        }
+        if (pending) {
+            // the pending event is applied (a repeated pass must not apply it
+            // again) and every lane of the group has read its flags
+            for (int q = li; q < NF; q += L) flags_rd[q] = 0u;
+            pending = false;
+        }
+        // ---- argmin across the group's lanes (lowest k wins ties)
+#pragma unroll
+        for (int off = L >> 1; off > 0; off >>= 1) {
+            const double o1 = __shfl_xor(d1, off, 64), o2 = __shfl_xor(d2, off, 64);
+            const int ok_ = __shfl_xor(kmin, off, 64), oc = __shfl_xor(clamped, off, 64);
+            const bool bw = o1 < d1 || (o1 == d1 && ok_ < kmin);
+            d2 = bw ? fmin(o2, d1) : fmin(d2, o1);
+            d1 = bw ? o1 : d1;
+            kmin = bw ? ok_ : kmin;
+            clamped = bw ? oc : clamped;
+        }
+        const double t_new = t + d1;
+        const bool absorbed = d1 == __builtin_inf();
+        const bool term = absorbed || t_new > t_end;
+        const bool live = !fresh && !capped;
+        const bool event = live && !term;
+        // ---- the jump v_mu, checked against [0, 2^31 - 1] by lanes < |v_mu|
+        int nb = 0, ne = 0;
+        if (event) { nb = net.nu_ptr[kmin]; ne = net.nu_ptr[kmin + 1]; }
+        int32_t xv = 0, xs = 0;
+        bool okl = true;
+        if (li < ne - nb) {
+            xs = net.nu_sp[nb + li];
+            const int64_t v = (int64_t)X[xs] + net.nu_dl[nb + li];
+            okl = v >= 0 && v <= 0x7FFFFFFF;
+            xv = (int32_t)v;
+        }
+        const bool ok = (__ballot(!okl) & gmask) == 0ull;
+        const bool near_tie = event && d2 - d1 <= 1e-12 * d1;
+        const bool rare = !live || term || near_tie || clamped || !ok || s_next < t_new;
+        if (__builtin_expect(__ballot(rare) != 0ull, 0)) {
+            if (event) {
+                if (near_tie) {
+                    if (li == 0) atomicAdd(&ws->near_ties, 1ull);
+                    tie = tie == kTieNone ? fired : tie;
+                }
+                while (s_next < t_new) {
+                    if (it->samples) {
+                        int32_t* dst = it->samples + r * it->ss_r + (int64_t)g * it->ss_g;
+                        for (int j = li; j < N; j += L) dst[j * it->ss_n] = X[j];
+                    }
+                    ++g;
+                    s_next = g < it->G ? it->s[g] : __builtin_inf();
+                }
+                if (ok && clamped && li == 0) atomicAdd(&ws->clamps, 1ull);
+            }
+            const bool stop = !live || term || !ok;
+            if (stop && !fresh) {
+                // ---- end of the trajectory
+                const int st = capped ? RTSSA_TRAJ_MAX_FIRINGS
+                                      : (absorbed ? RTSSA_TRAJ_ABSORBED
+                                                  : (term ? RTSSA_TRAJ_OK : RTSSA_TRAJ_OVERFLOW));
+                const bool good = st == RTSSA_TRAJ_OK || st == RTSSA_TRAJ_ABSORBED;
+                if (it->samples) {
+                    for (; g < it->G; ++g) {
+                        int32_t* dst = it->samples + r * it->ss_r + (int64_t)g * it->ss_g;
+                        for (int j = li; j < N; j += L) dst[j * it->ss_n] = good ? X[j] : -1;
+                    }
+                }
+                const double dt = t_end - t;
+#pragma unroll
+                for (int s = 0; s < S; ++s) {
+                    const int k = li + s * L;
+                    if (k < M) {
+                        if (good) T[s] = fma(a[s], dt, T[s]);
+                        if (it->n_out) it->n_out[r * M + k] = n[s];
+                        if (it->T_out) it->T_out[r * M + k] = T[s];
+                    }
+                }
+                if (it->x_final)
+                    for (int j = li; j < N; j += L) it->x_final[r * N + j] = X[j];
+                if (li == 0) {
+                    if (it->t_last) it->t_last[r] = t;
+                    if (it->status) it->status[r] = (uint8_t)st;
+                    if (it->seq_hash) it->seq_hash[r] = hash;
+                    if (it->tie_step) it->tie_step[r] = tie;
+                    atomicAdd(&ws->firings, (unsigned long long)fired);
+                    atomicAdd(&ws->status_count[st], 1ull);
+                }
+            }
+            if (stop) {
+                // ---- take the next trajectory unit
+                unsigned long long u = 0;
+                if (li == 0) u = atomicAdd(&ws->next_unit, 1ull);
+                u = __shfl(u, lane - li, 64);
+                wave_lds_fence();                          // X and flags are reused
+                fresh = false;
+                capped = false;
+                pending = false;
+                active = (int64_t)u < total;
+                if (active) {
+                    const int item = find_item(C.unit_start, C.count, (int64_t)u);
+                    it = C.items + item;
+                    r = (int64_t)u - C.unit_start[item];
+                    M = it->net.M;
+                    N = it->net.N;
+                    t_end = it->t_end;
+                    net_id = it->net_id;
+                    traj = it->traj_offset + (uint32_t)r;
+                    const int32_t* x0 = it->x0 + (it->x0_per_traj ? r * N : 0);
+                    for (int j = li; j < N; j += L) X[j] = x0[j];
+                    for (int q = li; q < 2 * NF; q += L) fb[q] = 0u;
+                    rd = 0;
+                    t = 0.0;
+                    g = 0;
+                    s_next = it->G > 0 ? it->s[0] : __builtin_inf();
+                    fired = 0;
+                    tie = kTieNone;
+                    hash = kFnvOffset;
+                    wave_lds_fence();
+#pragma unroll
+                    for (int s = 0; s < S; ++s) {
+                        const int k = li + s * L;
+                        T[s] = 0.0;
+                        n[s] = 0;
+                        if (k < M) {
+                            Pk[s] = rt_exp1_wave(key0, key1, traj, net_id, (uint32_t)k, 0u,
+                                                 &ws->slow_logs, sc);
+                            a[s] = sw_propensity(it->net.react[k], it->net.c[k], X);
+                            inv[s] = 1.0 / a[s];
+                        }
+                    }
+                }
+            }
+            if (__ballot(stop) != 0ull) continue;         // started groups compute first gaps
+        }
+        // ---- the event: jump, dependency flags, fresh draw by the owner lane
+        mu = kmin;
+        if (li < ne - nb) X[xs] = xv;
+        {
+            const int db = net.dep_ptr[mu], de = net.dep_ptr[mu + 1];
+            for (int q = db + li; q < de; q += L) {
+                const int kk = net.dep_idx[q];
+                atomicOr(&flags_wr[kk >> 5], 1u << (kk & 31));
+            }
+        }
+        if (li == (mu % L)) {
+            const int slot = mu / L;
+            uint32_t nm = n[0];
+#pragma unroll
+            for (int s = 1; s < S; ++s) nm = slot == s ? n[s] : nm;
+            E = rt_exp1_wave(key0, key1, traj, net_id, (uint32_t)mu, nm + 1u, &ws->slow_logs, sc);
+        }
+        wave_lds_fence();
+        t = t_new;
+        delta = d1;
+        ++fired;
+        hash = (hash ^ (unsigned long long)(uint32_t)mu) * kFnvPrime;
+        pending = true;
+        rd ^= 1;
+        capped = fired >= C.max_firings;
+    }
+}
+
+typedef void (*subwave_kernel_t)(rt_class_dev);
+
+template <int L, int S>
+subwave_kernel_t sw_pick() { return rt_subwave_kernel<L, S>; }
+
+subwave_kernel_t select_subwave(int L, int S)
+{
+#define RT_CASE(l, s) if (L == l && S == s) return sw_pick<l, s>();
+    RT_CASE(4, 2) RT_CASE(4, 4) RT_CASE(4, 8)
+    RT_CASE(8, 4) RT_CASE(8, 8)
+    RT_CASE(16, 4) RT_CASE(16, 8)
+    RT_CASE(32, 4) RT_CASE(32, 8)
+    RT_CASE(64, 4) RT_CASE(64, 8)
+#undef RT_CASE
+    return nullptr;
+}
+
+}  // namespace
+
+// Lanes per trajectory for an M-channel network: the fewest lanes that keep
+// at most 8 channels per lane (at least 4 lanes).
+int rt_subwave_lanes(int M)
+{
+    int L = 4;
+    while (L < 64 && L * 8 < M) L <<= 1;
+    return L;
+}
+
+int rt_subwave_slots(int M, int L)
+{
+    int s = (M + L - 1) / L;
+    int p = 2;
+    while (p < s) p <<= 1;
+    if (L > 4 && p < 4) p = 4;
+    return p;
+}
+
+int rt_launch_subwave(int max_M, const rt_class_dev& C, int L, int grid, hipStream_t stream,
+                      int* grid_used)
+{
+    const int S = rt_subwave_slots(max_M, L);
+    subwave_kernel_t kfn = select_subwave(L, S);
+    if (!kfn) return rt_fail(RTSSA_E_UNSUPPORTED, "no sub-wave kernel for this size");
+    const int NP = (C.max_N + 3) & ~3, NF = (C.max_M + 31) >> 5;
+    const size_t lds = (size_t)(kBlock / L) * (NP + 2 * NF) * 4;
+    if (lds > 64 * 1024) return rt_fail(RTSSA_E_UNSUPPORTED, "sub-wave LDS too large");
+    if (grid <= 0) {
+        int dev = 0, cus = 0, per_cu = 0;
+        hipGetDevice(&dev);
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kfn, kBlock, lds) != hipSuccess ||
+            per_cu < 1)
+            per_cu = 1;
+        grid = cus * per_cu;
+    }
+    if (grid_used) *grid_used = grid;
+    hipLaunchKernelGGL(kfn, dim3(grid), dim3(kBlock), lds, stream, C);
+    return hipGetLastError() == hipSuccess ? RTSSA_OK
+                                           : rt_fail(RTSSA_E_HIP, "sub-wave kernel launch failed");
+}

@@ -54,8 +54,10 @@ def _t_end_for(spec, x0, firings):
 
 @pytest.mark.parametrize("N,M,mapping,block,seed", [
     (6, 12, 2, 0, 1), (10, 40, 2, 0, 2), (30, 100, 2, 0, 3), (80, 300, 2, 0, 4),
-    (64, 513, 2, 0, 5), (40, 200, 3, 256, 6), (200, 900, 3, 256, 7), (300, 1500, 3, 512, 8),
+    (64, 513, 3, 256, 5), (40, 200, 3, 256, 6), (200, 900, 3, 256, 7), (300, 1500, 3, 512, 8),
     (500, 2000, 3, 1024, 9), (1000, 4000, 3, 1024, 10), (8, 8, 3, 1024, 11), (5, 65, 2, 0, 12),
+    (6, 12, 2, 4, 13), (20, 60, 2, 8, 14), (30, 100, 2, 16, 15), (60, 200, 2, 32, 16),
+    (120, 500, 2, 64, 17), (3, 9, 2, 4, 18),
 ])
 def test_random_networks_bit_exact(N, M, mapping, block, seed):
     api = _api()
@@ -91,10 +93,11 @@ def test_mappings_agree_on_the_same_network():
     net2 = api.Network(spec)
     t_end = _t_end_for(spec, x0, 800)
     a = api.simulate(net2, x0, t_end, [t_end], 50, mapping=2, with_hash=True)
-    for block in (256, 512):
-        b = api.simulate(net2, x0, t_end, [t_end], 50, mapping=3, block=block, with_hash=True)
+    for mapping, block in ((3, 256), (3, 512), (2, 8), (2, 16), (2, 32), (2, 64)):
+        b = api.simulate(net2, x0, t_end, [t_end], 50, mapping=mapping, block=block,
+                         with_hash=True)
         for k in KEYS:
-            assert torch.equal(a[k], b[k]), (block, k)
+            assert torch.equal(a[k], b[k]), (mapping, block, k)
 
 
 def test_group_edge_cases():
