@@ -52,7 +52,7 @@ def parse():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--trajectories", type=int, default=1 << 20)
     ap.add_argument("--workload", default="all",
-                    choices=["all", "lv_ensemble", "large_random", "gradient"])
+                    choices=["all", "lv_ensemble", "large_random", "gradient", "batched"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--block", type=int, default=0)
@@ -212,6 +212,56 @@ def bench_gradient(api, W, reps=3):
     return res
 
 
+def bench_batched(api, W, steps=2, n_nets=4096, solo_sample=128):
+    """4096 random networks (M log-uniform in [3, 2048], N = M/4, 64
+    trajectories each, t_end for about 2e4 firings) in one captured launch per
+    size class, against one rtssa_simulate launch per network (timed on a
+    sample of networks and scaled to the whole batch)."""
+    import numpy as np
+    import torch
+    t0 = time.perf_counter()
+    wl = W.batch_networks(n_nets)
+    jobs = [dict(net=api.Network(w.net), x0=w.x0, t_end=w.t_end, sample_t=w.sample_t, R=w.R,
+                 net_id=w.net_id) for w in wl]
+    log("batched: %d networks generated in %.1f s" % (n_nets, time.perf_counter() - t0))
+    b = api.Batch(jobs, want=("samples", "n", "T", "x_final", "status"))
+    st = b.run(seed=1)                                   # captures the graph
+    log("batched warmup: %.1f ms, %d firings" % (st["kernel_ms"], st["firings"]))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    fir, kms = 0, []
+    for i in range(steps):
+        st = b.run(seed=1)
+        fir += st["firings"]
+        kms.append(st["kernel_ms"])
+        log("batched step %d: %.1f ms, %d firings" % (i, st["kernel_ms"], st["firings"]))
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    # one launch per network, on a sample of networks
+    rng = np.random.default_rng(0)
+    idx = sorted(rng.choice(n_nets, size=min(solo_sample, n_nets), replace=False))
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    solo_fir = 0
+    for i in idx:
+        j = jobs[i]
+        o = api.simulate(j["net"], j["x0"], j["t_end"], j["sample_t"], j["R"], seed=1,
+                         net_id=j["net_id"], want=("samples", "n", "T", "x_final", "status"),
+                         stats=False)
+        solo_fir += int(o["n"].to(torch.int64).sum())
+    torch.cuda.synchronize()
+    solo_wall = time.perf_counter() - t1
+    solo_rate = solo_fir / solo_wall
+    per_step = fir / steps
+    return {"workload": "batched_random_networks", "networks": n_nets, "trajectories_each": 64,
+            "value": fir / wall, "unit": "firings/s", "ms_per_step": wall / steps * 1e3,
+            "firings_per_step": per_step, "graph": True, "classes": b.classes(),
+            "per_network_launches": {"value": solo_rate, "unit": "firings/s",
+                                     "networks_timed": len(idx),
+                                     "estimated_ms_for_all": per_step / solo_rate * 1e3},
+            "speedup_vs_per_network": (fir / wall) / solo_rate}
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -223,9 +273,13 @@ def main():
 
     from paper_2103_00405_amd import api, workloads as W
 
-    if args.workload in ("large_random", "gradient"):
-        out = bench_large(api, W, args.steps, args.warmup) if args.workload == "large_random" \
-            else bench_gradient(api, W)
+    if args.workload in ("large_random", "gradient", "batched"):
+        if args.workload == "large_random":
+            out = bench_large(api, W, args.steps, args.warmup)
+        elif args.workload == "gradient":
+            out = bench_gradient(api, W)
+        else:
+            out = bench_batched(api, W, args.steps)
         print(json.dumps(out), flush=True)
         return
 
@@ -270,7 +324,8 @@ def main():
         res["calibration_copy_bytes"] = nb
     if args.workload == "all":
         res["secondary"] = {"large_random": bench_large(api, W, 2, 1),
-                            "gradient": bench_gradient(api, W)}
+                            "gradient": bench_gradient(api, W),
+                            "batched": bench_batched(api, W, 2)}
     if not args.no_cpu_baseline:
         res["cpu_baseline"] = cpu_baseline(w, args.cpu_seconds)
     print(json.dumps(res), flush=True)

@@ -182,6 +182,66 @@ int rtssa_score_grad(const double* f, const uint32_t* n, const double* T, int64_
                      rtssa_stream_t stream);
 
 /* ---------------------------------------------------------------------
+ * Batches: many independent networks in one launch.
+ *
+ * Each item is one rtssa_simulate call's worth of arguments (same meaning,
+ * same validation).  rtssa_batch_create groups the items into classes by
+ * kernel mapping (thread, sub-wavefront lanes per trajectory, workgroup
+ * size; taken from the plan file written by rtssa_autotune when plan_path
+ * names one, else from the network size), copies their descriptors to the
+ * device and owns them; the caller keeps every input and output buffer alive
+ * and unchanged in address until rtssa_batch_destroy.  rtssa_batch_run runs
+ * every item: with use_graph = 1 the first run captures a hipGraph (one
+ * persistent kernel per class on parallel branches) and later runs replay
+ * it; with 0 the kernels are enqueued directly.  The results equal those of
+ * one rtssa_simulate per item with the same seed (and each item's net_id).
+ * stats as in rtssa_simulate (the call then waits for the stream).
+ */
+typedef struct {
+    const rtssa_network* net;
+    const int32_t* x0;
+    int32_t x0_per_traj;
+    int32_t G;
+    double t_end;
+    const double* sample_t;
+    uint32_t net_id;
+    int32_t reserved;
+    uint64_t traj_offset;
+    int64_t R;
+    int32_t* samples;
+    int64_t s_stride_r, s_stride_g, s_stride_n;
+    uint32_t* n_out;
+    double* T_out;
+    int32_t* x_final;
+    double* t_last;
+    uint8_t* status;
+    uint64_t* seq_hash;
+    uint32_t* tie_step;
+} rtssa_batch_item;
+
+typedef struct rtssa_batch rtssa_batch;
+
+int rtssa_batch_create(const rtssa_batch_item* items, int32_t count, const rtssa_options* opt,
+                       const char* plan_path, rtssa_batch** out);
+int rtssa_batch_run(rtssa_batch* batch, uint64_t seed, int32_t use_graph, rtssa_stream_t stream,
+                    rtssa_stats* stats);
+/* cls < 0: *n_items receives the number of classes; else the class's
+ * mapping, lanes per trajectory (1 for the thread mapping), items,
+ * trajectories and largest channel count. */
+int rtssa_batch_info(const rtssa_batch* batch, int32_t cls, int32_t* mapping, int32_t* lanes,
+                     int32_t* n_items, int64_t* trajectories, int32_t* max_M);
+int rtssa_batch_destroy(rtssa_batch* batch);
+
+/* Autotuner: for every size class among the items (networks beyond the
+ * thread mapping), time each feasible lane count / workgroup size on up to
+ * `samples` items of the class (short runs, results discarded) and write the
+ * fastest to the plan file plan_path (text: "wave|workgroup M_lo M_hi L").
+ * Returns the number of classes tuned (>= 0) or a negative error code.
+ * Synchronous. */
+int rtssa_autotune(const rtssa_batch_item* items, int32_t count, int32_t samples,
+                   const char* plan_path, rtssa_stream_t stream);
+
+/* ---------------------------------------------------------------------
  * Test hooks: the library's own Philox and -ln(u), for checking its
  * arithmetic element by element.  The *_host variants run the same source
  * compiled for the CPU; the device variants launch a kernel.

@@ -34,6 +34,14 @@ class Options(C.Structure):
                 ("reserved", i32)]
 
 
+class BatchItem(C.Structure):
+    _fields_ = [("net", vp), ("x0", vp), ("x0_per_traj", i32), ("G", i32), ("t_end", f64),
+                ("sample_t", vp), ("net_id", u32), ("reserved", i32), ("traj_offset", u64),
+                ("R", i64), ("samples", vp), ("s_stride_r", i64), ("s_stride_g", i64),
+                ("s_stride_n", i64), ("n_out", vp), ("T_out", vp), ("x_final", vp),
+                ("t_last", vp), ("status", vp), ("seq_hash", vp), ("tie_step", vp)]
+
+
 SIGNATURES = {
     "rtssa_last_error": (C.c_char_p, []),
     "rtssa_version": (C.c_char_p, []),
@@ -45,6 +53,12 @@ SIGNATURES = {
                                  i64, vp, vp, vp, vp, vp, vp, vp, C.POINTER(Options), vp,
                                  C.POINTER(Stats)]),
     "rtssa_score_grad": (C.c_int, [vp, vp, vp, i64, i32, i32, vp, vp, vp]),
+    "rtssa_batch_create": (C.c_int, [C.POINTER(BatchItem), i32, C.POINTER(Options), C.c_char_p,
+                                     C.POINTER(vp)]),
+    "rtssa_batch_run": (C.c_int, [vp, u64, i32, vp, C.POINTER(Stats)]),
+    "rtssa_batch_info": (C.c_int, [vp, i32, vp, vp, vp, vp, vp]),
+    "rtssa_batch_destroy": (C.c_int, [vp]),
+    "rtssa_autotune": (C.c_int, [C.POINTER(BatchItem), i32, i32, C.c_char_p, vp]),
     "rtssa_debug_neglog": (C.c_int, [vp, vp, vp, i64, i32, vp]),
     "rtssa_debug_neglog_host": (f64, [u64, i32, C.POINTER(i32)]),
     "rtssa_debug_neglog_fast_host": (None, [u64, C.POINTER(f64), C.POINTER(f64)]),

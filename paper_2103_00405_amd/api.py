@@ -178,3 +178,105 @@ def expectation(log_c: torch.Tensor, net: Network, f: Callable, x0, t_end: float
     """Monte-Carlo E[f(X(t_end))] over R trajectories; differentiable in log_c
     through the score n_k - T_k(t_end) of each path."""
     return _Expectation.apply(log_c, net, f, x0, t_end, R, seed, baseline)
+
+
+class Batch:
+    """Many independent networks run by one persistent launch per size class
+    (captured once into a hipGraph and replayed).  ``jobs`` is a list of dicts
+    with keys net (Network), x0, t_end, sample_t, R and optionally net_id,
+    traj_offset; outputs are allocated here (per job: samples, n, T, x_final,
+    t_last, status, seq_hash, tie_step) and returned by ``run``."""
+
+    def __init__(self, jobs, max_firings=10_000_000, mapping=MAP_AUTO, plan_path=None,
+                 want=("samples", "n", "T", "x_final", "t_last", "status", "tie_step"),
+                 with_hash=False, device="cuda"):
+        from ._lib import BatchItem
+        self.device = _require_gpu(device)
+        dev = self.device
+        self.jobs, self.outputs, self._keep = [], [], []
+        items = (BatchItem * len(jobs))()
+        for i, j in enumerate(jobs):
+            net = j["net"]
+            R = int(j["R"])
+            x0 = torch.as_tensor(np.asarray(j["x0"]), dtype=torch.int32).to(dev).contiguous()
+            s = torch.as_tensor(np.asarray(j["sample_t"], dtype=np.float64),
+                                dtype=torch.float64).to(dev).contiguous()
+            G = int(s.numel())
+            o = {}
+            shapes = dict(samples=((R, G, net.N), torch.int32), n=((R, net.M), torch.int32),
+                          T=((R, net.M), torch.float64), x_final=((R, net.N), torch.int32),
+                          t_last=((R,), torch.float64), status=((R,), torch.uint8),
+                          tie_step=((R,), torch.int32), seq_hash=((R,), torch.int64))
+            for k in set(want) | ({"seq_hash"} if with_hash else set()):
+                shape, dt = shapes[k]
+                o[k] = torch.empty(shape, dtype=dt, device=dev)
+            smp = o.get("samples")
+            st = smp.stride() if smp is not None else (0, 0, 0)
+            it = items[i]
+            it.net = net.handle
+            it.x0 = x0.data_ptr() if x0.numel() else None
+            it.x0_per_traj = 1 if x0.dim() == 2 else 0
+            it.G = G
+            it.t_end = float(j["t_end"])
+            it.sample_t = s.data_ptr() if G else None
+            it.net_id = int(j.get("net_id", i))
+            it.traj_offset = int(j.get("traj_offset", 0))
+            it.R = R
+            it.samples = smp.data_ptr() if smp is not None and smp.numel() else None
+            it.s_stride_r, it.s_stride_g, it.s_stride_n = st
+            for k, f in (("n", "n_out"), ("T", "T_out"), ("x_final", "x_final"),
+                         ("t_last", "t_last"), ("status", "status"), ("seq_hash", "seq_hash"),
+                         ("tie_step", "tie_step")):
+                t = o.get(k)
+                setattr(it, f, t.data_ptr() if t is not None and t.numel() else None)
+            self._keep += [x0, s, net]
+            self.outputs.append(o)
+            self.jobs.append(j)
+        self._items = items
+        self._h = C.c_void_p()
+        opt = Options(int(max_firings), int(mapping), 0, 0, 0)
+        with torch.cuda.device(dev):
+            check(lib().rtssa_batch_create(items, len(jobs), C.byref(opt),
+                                           plan_path.encode() if plan_path else None,
+                                           C.byref(self._h)))
+
+    def run(self, seed=1, use_graph=True, stats=True):
+        st = Stats()
+        with torch.cuda.device(self.device):
+            check(lib().rtssa_batch_run(self._h, int(seed) & (2**64 - 1), 1 if use_graph else 0,
+                                        _stream(self.device), C.byref(st) if stats else None))
+        return st.as_dict() if stats else None
+
+    def classes(self):
+        n = C.c_int32()
+        check(lib().rtssa_batch_info(self._h, -1, None, None, C.byref(n), None, None))
+        out = []
+        for c in range(n.value):
+            m, l, k, mm = C.c_int32(), C.c_int32(), C.c_int32(), C.c_int32()
+            r = C.c_int64()
+            check(lib().rtssa_batch_info(self._h, c, C.byref(m), C.byref(l), C.byref(k),
+                                         C.byref(r), C.byref(mm)))
+            out.append(dict(mapping=m.value, lanes=l.value, items=k.value,
+                            trajectories=r.value, max_M=mm.value))
+        return out
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        try:
+            if h and _lib._lib is not None:
+                _lib._lib.rtssa_batch_destroy(h)
+        except Exception:
+            pass
+        self._h = None
+
+
+def autotune(batch_jobs_items, plan_path, samples=4):
+    """Write a plan file choosing lanes per trajectory / workgroup size per
+    size class by timing short runs (see rtssa_autotune)."""
+    b = batch_jobs_items
+    with torch.cuda.device(b.device):
+        n = lib().rtssa_autotune(b._items, len(b.jobs), int(samples), plan_path.encode(),
+                                 _stream(b.device))
+    if n < 0:
+        check(n)
+    return n

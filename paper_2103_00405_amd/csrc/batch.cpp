@@ -1,0 +1,425 @@
+// batch.cpp -- many independent networks in one captured launch, and the
+// autotuner that picks each size class's mapping parameters.
+//
+// rtssa_batch_create sorts the items into classes -- one per kernel
+// instantiation (thread mapping by padded (M, N); sub-wavefront mapping by
+// lanes per trajectory; workgroup mapping by group size) -- and uploads, per
+// class, the item descriptors, the prefix sums of trajectory counts and a
+// workspace.  The first rtssa_batch_run captures a hipGraph: one setup kernel
+// per class, then one persistent kernel per class on its own stream (parallel
+// branches of the graph, joined at the end).  Later runs copy the new seed
+// into device memory and replay the graph.  Because every draw is keyed by
+// (seed, trajectory, net_id, channel, firing index), the outputs equal those
+// of one rtssa_simulate per item with the same seed and net_id.
+#include <math.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <map>
+#include <string>
+#include <vector>
+
+#include "internal.h"
+
+namespace {
+
+struct class_key {
+    int mapping;    // RTSSA_MAP_*
+    int a, b;       // thread: padded (M, N); wave / workgroup: lanes per trajectory, 0
+    bool operator<(const class_key& o) const
+    {
+        return mapping != o.mapping ? mapping < o.mapping : (a != o.a ? a < o.a : b < o.b);
+    }
+};
+
+int pad_thread_m(int M) { return M <= 1 ? 1 : (M <= 4 ? M : (M <= 6 ? 6 : 8)); }
+int pad_thread_n(int N) { return N <= 1 ? 1 : (N <= 2 ? 2 : (N <= 4 ? 4 : 8)); }
+
+// plan cache: lines "wave <M_lo> <M_hi> <L>" or "workgroup <M_lo> <M_hi> <L>"
+struct plan_entry { int mapping, lo, hi, L; };
+
+std::vector<plan_entry> read_plan(const char* path)
+{
+    std::vector<plan_entry> out;
+    if (!path || !*path) return out;
+    FILE* f = fopen(path, "r");
+    if (!f) return out;
+    char kind[32];
+    int lo, hi, L;
+    while (fscanf(f, "%31s %d %d %d", kind, &lo, &hi, &L) == 4) {
+        int m = strcmp(kind, "wave") == 0 ? RTSSA_MAP_WAVE
+                                          : (strcmp(kind, "workgroup") == 0 ? RTSSA_MAP_WORKGROUP : 0);
+        if (m) out.push_back({m, lo, hi, L});
+    }
+    fclose(f);
+    return out;
+}
+
+int plan_lookup(const std::vector<plan_entry>& plan, int mapping, int M)
+{
+    for (const auto& e : plan)
+        if (e.mapping == mapping && M >= e.lo && M <= e.hi) return e.L;
+    return 0;
+}
+
+class_key classify(const rtssa_network* net, const std::vector<plan_entry>& plan,
+                   const rtssa_options& o)
+{
+    int mapping = o.mapping ? o.mapping : rt_auto_mapping(net);
+    if (mapping == RTSSA_MAP_THREAD && rt_thread_supported(net->M, net->N))
+        return {RTSSA_MAP_THREAD, pad_thread_m(net->M), pad_thread_n(net->N)};
+    if (mapping == RTSSA_MAP_THREAD) mapping = RTSSA_MAP_WAVE;
+    if (mapping == RTSSA_MAP_WAVE && (net->M > 512 || net->max_nu > 64))
+        mapping = RTSSA_MAP_WORKGROUP;
+    if (mapping == RTSSA_MAP_WAVE) {
+        int L = plan_lookup(plan, RTSSA_MAP_WAVE, net->M);
+        if (L <= 0) L = rt_subwave_lanes(net->M);
+        while (L < 64 && (L < net->max_nu || L * 8 < net->M)) L <<= 1;
+        return {RTSSA_MAP_WAVE, L, 0};
+    }
+    int L = plan_lookup(plan, RTSSA_MAP_WORKGROUP, net->M);
+    if (L <= 0) L = rt_auto_group_size(net->M);
+    return {RTSSA_MAP_WORKGROUP, L, 0};
+}
+
+}  // namespace
+
+struct rtssa_batch_class {
+    class_key key;
+    std::vector<int> members;   // item indices, heaviest first
+    int max_M = 0, max_N = 0, max_nu = 0;
+    int64_t units = 0;
+    rt_class_dev dev{};
+    hipStream_t side = nullptr;
+    int block_used = 0, grid_used = 0;
+};
+
+struct rtssa_batch {
+    std::vector<rtssa_batch_item> items;
+    std::vector<rtssa_batch_class> classes;
+    rtssa_options opt{};
+    void* dev_block = nullptr;     // descriptors, prefix sums, counters, workspaces, key
+    uint32_t* key_dev = nullptr;
+    rt_ws* ws_dev = nullptr;       // one per class, contiguous
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    hipEvent_t fork = nullptr;
+    std::vector<hipEvent_t> joins;
+    int device = -1;
+};
+
+extern "C" int rtssa_batch_create(const rtssa_batch_item* items, int32_t count,
+                                  const rtssa_options* opt, const char* plan_path,
+                                  rtssa_batch** out)
+{
+    if (!out) return rt_fail(RTSSA_E_INVALID, "out is NULL");
+    *out = nullptr;
+    if (count < 1 || !items) return rt_fail(RTSSA_E_INVALID, "a batch needs at least one item");
+    rtssa_options o{};
+    if (opt) o = *opt;
+    uint64_t maxf = o.max_firings ? o.max_firings : 10000000ull;
+    if (maxf > 0xFFFFFFFFull) return rt_fail(RTSSA_E_INVALID, "max_firings must be < 2^32");
+    // validate every item (reads each sample grid once)
+    for (int i = 0; i < count; ++i) {
+        const rtssa_batch_item& b = items[i];
+        int rc = rt_check_run(b.net, b.x0, b.x0_per_traj, b.t_end, b.sample_t, b.G,
+                              b.traj_offset, b.R, nullptr);
+        if (rc) return rt_fail(rc, "item " + std::to_string(i) + ": " + rtssa_last_error());
+    }
+    const std::vector<plan_entry> plan = read_plan(plan_path);
+    std::map<class_key, std::vector<int>> groups;
+    for (int i = 0; i < count; ++i)
+        if (items[i].R > 0) groups[classify(items[i].net, plan, o)].push_back(i);
+
+    rtssa_batch* B = new rtssa_batch();
+    B->items.assign(items, items + count);
+    B->opt = o;
+    hipGetDevice(&B->device);
+    for (auto& kv : groups) {
+        rtssa_batch_class c;
+        c.key = kv.first;
+        c.members = kv.second;
+        // heaviest items first so the tail of the queue holds short work
+        std::stable_sort(c.members.begin(), c.members.end(), [&](int x, int y) {
+            return (double)items[x].net->M * items[x].R > (double)items[y].net->M * items[y].R;
+        });
+        for (int i : c.members) {
+            c.max_M = std::max(c.max_M, items[i].net->M);
+            c.max_N = std::max(c.max_N, items[i].net->N);
+            c.max_nu = std::max(c.max_nu, items[i].net->max_nu);
+            c.units += items[i].R;
+        }
+        B->classes.push_back(c);
+    }
+    // one device block: per class items, unit_start, item_next; then the
+    // workspaces; then the key
+    size_t off = 0;
+    std::vector<size_t> o_items, o_start, o_next;
+    auto align = [](size_t v) { return (v + 255) / 256 * 256; };
+    for (auto& c : B->classes) {
+        o_items.push_back(off);
+        off = align(off + sizeof(rt_item_dev) * c.members.size());
+        o_start.push_back(off);
+        off = align(off + sizeof(int64_t) * (c.members.size() + 1));
+        o_next.push_back(off);
+        off = align(off + sizeof(unsigned long long) * c.members.size());
+    }
+    const size_t o_ws = off;
+    off = align(off + sizeof(rt_ws) * std::max<size_t>(1, B->classes.size()));
+    const size_t o_key = off;
+    off = align(off + 16);
+    if (hipMalloc(&B->dev_block, off) != hipSuccess) {
+        delete B;
+        return rt_fail(RTSSA_E_NOMEM, "batch tables allocation failed");
+    }
+    char* base = (char*)B->dev_block;
+    B->ws_dev = (rt_ws*)(base + o_ws);
+    B->key_dev = (uint32_t*)(base + o_key);
+    int rc = RTSSA_OK;
+    for (size_t ci = 0; ci < B->classes.size() && !rc; ++ci) {
+        auto& c = B->classes[ci];
+        std::vector<rt_item_dev> dv;
+        std::vector<int64_t> starts(1, 0);
+        for (int i : c.members) {
+            const rtssa_batch_item& b = items[i];
+            dv.push_back(rt_make_item(b.net, b.x0, b.x0_per_traj, b.t_end, b.sample_t, b.G,
+                                      b.net_id, b.traj_offset, b.R, b.samples, b.s_stride_r,
+                                      b.s_stride_g, b.s_stride_n, b.n_out, b.T_out, b.x_final,
+                                      b.t_last, b.status, b.seq_hash, b.tie_step));
+            starts.push_back(starts.back() + b.R);
+        }
+        rc = check_hip(hipMemcpy(base + o_items[ci], dv.data(), sizeof(rt_item_dev) * dv.size(),
+                                 hipMemcpyHostToDevice), "batch upload");
+        if (!rc)
+            rc = check_hip(hipMemcpy(base + o_start[ci], starts.data(),
+                                     sizeof(int64_t) * starts.size(), hipMemcpyHostToDevice),
+                           "batch upload");
+        c.dev.items = (const rt_item_dev*)(base + o_items[ci]);
+        c.dev.unit_start = (const int64_t*)(base + o_start[ci]);
+        c.dev.item_next = (unsigned long long*)(base + o_next[ci]);
+        c.dev.ws = B->ws_dev + ci;
+        c.dev.count = (int32_t)c.members.size();
+        c.dev.exclusive = 1;
+        c.dev.max_N = c.max_N;
+        c.dev.max_M = c.max_M;
+        c.dev.max_firings = (uint32_t)maxf;
+        if (!rc && ci > 0)
+            rc = check_hip(hipStreamCreateWithFlags(&c.side, hipStreamNonBlocking), "stream");
+    }
+    if (!rc) rc = check_hip(hipEventCreateWithFlags(&B->fork, hipEventDisableTiming), "event");
+    for (size_t ci = 0; ci < B->classes.size() && !rc; ++ci) {
+        hipEvent_t e = nullptr;
+        rc = check_hip(hipEventCreateWithFlags(&e, hipEventDisableTiming), "event");
+        B->joins.push_back(e);
+    }
+    if (rc) {
+        rtssa_batch_destroy(B);
+        return rc;
+    }
+    *out = B;
+    return RTSSA_OK;
+}
+
+static int batch_enqueue(rtssa_batch* B, hipStream_t stream)
+{
+    // setup kernels (counters, queues, key) then one persistent kernel per
+    // class, each class on its own stream, joined back into `stream`
+    int rc = RTSSA_OK;
+    for (size_t ci = 0; ci < B->classes.size() && !rc; ++ci) {
+        auto& c = B->classes[ci];
+        rc = rt_launch_setup(c.dev.ws, c.dev.item_next, c.dev.count, 0u, 0u, B->key_dev, nullptr,
+                             nullptr, nullptr, stream);
+    }
+    if (!rc) rc = check_hip(hipEventRecord(B->fork, stream), "fork");
+    for (size_t ci = 1; ci < B->classes.size() && !rc; ++ci)
+        rc = check_hip(hipStreamWaitEvent(B->classes[ci].side, B->fork, 0), "fork");
+    for (size_t ci = 0; ci < B->classes.size() && !rc; ++ci) {
+        auto& c = B->classes[ci];
+        hipStream_t s = ci == 0 ? stream : c.side;
+        const int block = c.key.mapping == RTSSA_MAP_THREAD ? B->opt.block : c.key.a;
+        rc = rt_launch_class(c.key.mapping, c.key.mapping == RTSSA_MAP_THREAD ? c.key.a : c.max_M,
+                             c.key.mapping == RTSSA_MAP_THREAD ? c.key.b : c.max_N, c.max_nu,
+                             c.dev, block, B->opt.grid, c.units, s, &c.block_used, &c.grid_used);
+        if (!rc && ci > 0) rc = check_hip(hipEventRecord(B->joins[ci], s), "join");
+    }
+    for (size_t ci = 1; ci < B->classes.size() && !rc; ++ci)
+        rc = check_hip(hipStreamWaitEvent(stream, B->joins[ci], 0), "join");
+    return rc;
+}
+
+extern "C" int rtssa_batch_run(rtssa_batch* B, uint64_t seed, int32_t use_graph,
+                               rtssa_stream_t stream_, rtssa_stats* stats)
+{
+    if (!B) return rt_fail(RTSSA_E_INVALID, "batch is NULL");
+    hipStream_t stream = (hipStream_t)stream_;
+    if (stats) memset(stats, 0, sizeof(*stats));
+    uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
+    int rc = check_hip(hipMemcpyAsync(B->key_dev, key, sizeof(key), hipMemcpyHostToDevice, stream),
+                       "seed upload");
+    if (rc) return rc;
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    if (stats) {
+        hipEventCreate(&ev0);
+        hipEventCreate(&ev1);
+        hipEventRecord(ev0, stream);
+    }
+    if (use_graph) {
+        if (!B->exec) {
+            // capture once; the key is read from device memory at run time
+            hipStream_t cap = nullptr;
+            rc = check_hip(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking), "stream");
+            if (!rc) rc = check_hip(hipStreamBeginCapture(cap, hipStreamCaptureModeGlobal), "capture");
+            if (!rc) {
+                int rc2 = batch_enqueue(B, cap);
+                hipGraph_t g = nullptr;
+                rc = check_hip(hipStreamEndCapture(cap, &g), "end capture");
+                if (!rc) rc = rc2;
+                if (!rc) {
+                    B->graph = g;
+                    rc = check_hip(hipGraphInstantiate(&B->exec, g, nullptr, nullptr, 0),
+                                   "graph instantiate");
+                } else if (g) {
+                    hipGraphDestroy(g);
+                }
+            }
+            if (cap) hipStreamDestroy(cap);
+        }
+        if (!rc) rc = check_hip(hipGraphLaunch(B->exec, stream), "graph launch");
+    } else {
+        rc = batch_enqueue(B, stream);
+    }
+    if (!rc && stats) {
+        hipEventRecord(ev1, stream);
+        std::vector<rt_ws> h(B->classes.size());
+        rc = check_hip(hipMemcpyAsync(h.data(), B->ws_dev, sizeof(rt_ws) * h.size(),
+                                      hipMemcpyDeviceToHost, stream), "reading stats");
+        if (!rc) rc = check_hip(hipStreamSynchronize(stream), "batch");
+        if (!rc) {
+            float ms = 0.f;
+            hipEventElapsedTime(&ms, ev0, ev1);
+            for (const auto& w : h) rt_fill_stats(stats, w);
+            stats->kernel_ms = ms;
+            stats->mapping = 0;
+            stats->grid = (int32_t)B->classes.size();
+        }
+    }
+    if (ev0) hipEventDestroy(ev0);
+    if (ev1) hipEventDestroy(ev1);
+    return rc;
+}
+
+extern "C" int rtssa_batch_info(const rtssa_batch* B, int32_t cls, int32_t* mapping, int32_t* lanes,
+                                int32_t* n_items, int64_t* trajectories, int32_t* max_M)
+{
+    if (!B) return rt_fail(RTSSA_E_INVALID, "batch is NULL");
+    if (cls < 0) {
+        if (n_items) *n_items = (int32_t)B->classes.size();
+        return RTSSA_OK;
+    }
+    if (cls >= (int)B->classes.size()) return rt_fail(RTSSA_E_INVALID, "no such class");
+    const auto& c = B->classes[cls];
+    if (mapping) *mapping = c.key.mapping;
+    if (lanes) *lanes = c.key.mapping == RTSSA_MAP_THREAD ? 1 : c.key.a;
+    if (n_items) *n_items = (int32_t)c.members.size();
+    if (trajectories) *trajectories = c.units;
+    if (max_M) *max_M = c.max_M;
+    return RTSSA_OK;
+}
+
+extern "C" int rtssa_batch_destroy(rtssa_batch* B)
+{
+    if (!B) return RTSSA_OK;
+    if (B->exec) hipGraphExecDestroy(B->exec);
+    if (B->graph) hipGraphDestroy(B->graph);
+    for (auto& c : B->classes)
+        if (c.side) hipStreamDestroy(c.side);
+    for (auto e : B->joins)
+        if (e) hipEventDestroy(e);
+    if (B->fork) hipEventDestroy(B->fork);
+    if (B->dev_block) hipFree(B->dev_block);
+    delete B;
+    return RTSSA_OK;
+}
+
+// ---------------------------------------------------------------- autotuner
+// For each size class present in the items (sub-wave: channel counts in
+// (8L/2, 8L]; workgroup: powers of two), time every feasible lane count on up
+// to `samples` items of the class (a short run of each, the same seed) and
+// record the fastest in the plan file.  Returns the number of classes tuned.
+extern "C" int rtssa_autotune(const rtssa_batch_item* items, int32_t count, int32_t samples,
+                              const char* plan_path, rtssa_stream_t stream_)
+{
+    if (!items || count < 1 || !plan_path) return rt_fail(RTSSA_E_INVALID, "bad arguments");
+    hipStream_t stream = (hipStream_t)stream_;
+    struct bucket { int mapping, lo, hi; std::vector<int> members; };
+    std::map<std::pair<int, int>, bucket> buckets;
+    for (int i = 0; i < count; ++i) {
+        const rtssa_network* n = items[i].net;
+        int m = rt_auto_mapping(n);
+        if (m == RTSSA_MAP_THREAD) continue;
+        int lo, hi;
+        if (m == RTSSA_MAP_WAVE) {
+            int L = rt_subwave_lanes(n->M);
+            lo = L == 4 ? 0 : 4 * L + 1;
+            hi = 8 * L;
+        } else {
+            hi = 1024;
+            while (hi < n->M) hi <<= 1;
+            lo = hi / 2 + 1;
+        }
+        auto& b = buckets[{m, hi}];
+        b.mapping = m;
+        b.lo = lo;
+        b.hi = hi;
+        if ((int)b.members.size() < std::max(1, samples)) b.members.push_back(i);
+    }
+    FILE* f = fopen(plan_path, "w");
+    if (!f) return rt_fail(RTSSA_E_INVALID, std::string("cannot write ") + plan_path);
+    int tuned = 0;
+    for (auto& kv : buckets) {
+        bucket& b = kv.second;
+        std::vector<int> cands;
+        if (b.mapping == RTSSA_MAP_WAVE) {
+            for (int L = 4; L <= 64; L <<= 1)
+                if (8 * L >= b.hi) cands.push_back(L);
+        } else {
+            for (int L = 128; L <= 1024; L <<= 1) cands.push_back(L);
+        }
+        double best = -1.0;
+        int bestL = cands.empty() ? 0 : cands[0];
+        for (int L : cands) {
+            double fired = 0, ms = 0;
+            bool ok = true;
+            for (int i : b.members) {
+                const rtssa_batch_item& it = items[i];
+                if (b.mapping == RTSSA_MAP_WAVE && (L < it.net->max_nu || 8 * L < it.net->M)) {
+                    ok = false;
+                    break;
+                }
+                rtssa_options o{};
+                o.mapping = b.mapping;
+                o.block = L;
+                o.max_firings = 20000;
+                rtssa_stats st{};
+                int rc = rtssa_simulate(it.net, it.x0, it.x0_per_traj, it.t_end, nullptr, 0, 7,
+                                        it.net_id, it.traj_offset, it.R, nullptr, 0, 0, 0, nullptr,
+                                        nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, &o,
+                                        (rtssa_stream_t)stream, &st);
+                if (rc) { ok = false; break; }
+                fired += (double)st.firings;
+                ms += st.kernel_ms;
+            }
+            if (!ok || ms <= 0) continue;
+            const double rate = fired / ms;
+            if (rate > best) { best = rate; bestL = L; }
+        }
+        if (best > 0) {
+            fprintf(f, "%s %d %d %d\n", b.mapping == RTSSA_MAP_WAVE ? "wave" : "workgroup", b.lo,
+                    b.hi, bestL);
+            ++tuned;
+        }
+    }
+    fclose(f);
+    return tuned;
+}

@@ -1,0 +1,109 @@
+"""Batched form: many networks of uneven size in one captured launch.
+
+Every item of a batch must equal, bit for bit, the same network run alone by
+rtssa_simulate with the same seed and net_id (and a few items are checked
+against the CPU oracle directly); graph replays with new seeds, direct
+enqueue, and plans chosen by the autotuner must not change any bit."""
+import math
+import os
+import tempfile
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2103_00405_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+KEYS = ("samples", "n", "T", "x_final", "t_last", "status", "seq_hash", "tie_step")
+
+
+def _api():
+    from paper_2103_00405_amd import api
+    return api
+
+
+def _jobs(api, n_nets=40, seed=5, target=600, R=12):
+    rng = np.random.default_rng(seed)
+    jobs = []
+    sizes = [2, 3, 5, 8, 12, 30, 70, 150, 300, 520, 900]
+    for i in range(n_nets):
+        M = sizes[i % len(sizes)] if i < len(sizes) else int(round(math.exp(rng.uniform(
+            math.log(3), math.log(1200)))))
+        N = max(2, M // 4)
+        spec = W.random_network(N, M, rng, logc=(-1.0, 1.0), bimol_scale=0.05)
+        x0 = rng.integers(0, 80, size=N).astype(np.int32)
+        a0 = W.initial_total_rate(spec, x0)
+        t_end = float(target / a0) if a0 > 0 else 1.0
+        jobs.append(dict(spec=spec, net=api.Network(spec), x0=x0, t_end=t_end,
+                         sample_t=W.uniform_grid(t_end, 7), R=R, net_id=i))
+    return jobs
+
+
+def _solo(api, j, seed):
+    return api.simulate(j["net"], j["x0"], j["t_end"], j["sample_t"], j["R"], seed=seed,
+                        net_id=j["net_id"], with_hash=True)
+
+
+def test_batch_equals_per_network_launches():
+    api = _api()
+    jobs = _jobs(api)
+    b = api.Batch(jobs, with_hash=True)
+    cls = b.classes()
+    kinds = {c["mapping"] for c in cls}
+    assert kinds == {api.MAP_THREAD, api.MAP_WAVE, api.MAP_WORKGROUP}, cls
+    st = b.run(seed=11)
+    torch.cuda.synchronize()
+    total = 0
+    for j, o in zip(jobs, b.outputs):
+        ref = _solo(api, j, 11)
+        total += ref["stats"]["firings"]
+        for k in KEYS:
+            assert torch.equal(o[k], ref[k]), (j["net_id"], k)
+    assert st["firings"] == total
+    # three items straight against the oracle
+    for i in (0, 7, 9):
+        j = jobs[i]
+        ref = oracle.simulate(j["spec"], j["x0"], j["t_end"], j["sample_t"], 11, j["R"],
+                              net_id=j["net_id"])
+        o = b.outputs[i]
+        assert np.array_equal(o["n"].cpu().numpy().view(np.uint32), ref["n"])
+        assert np.array_equal(o["T"].cpu().numpy().view(np.uint64), ref["T"].view(np.uint64))
+        assert np.array_equal(o["samples"].cpu().numpy(), ref["samples"])
+
+
+def test_graph_replay_new_seed_and_direct_enqueue():
+    api = _api()
+    jobs = _jobs(api, n_nets=25, seed=6)
+    b = api.Batch(jobs, with_hash=True)
+    b.run(seed=3)
+    first = [{k: v.clone() for k, v in o.items()} for o in b.outputs]
+    b.run(seed=4)                                    # replay with another seed
+    for j, o in zip(jobs, b.outputs):
+        ref = _solo(api, j, 4)
+        for k in ("n", "T", "seq_hash", "samples"):
+            assert torch.equal(o[k], ref[k]), (j["net_id"], k)
+    b.run(seed=3, use_graph=False)                   # direct enqueue, first seed again
+    for f, o in zip(first, b.outputs):
+        for k in KEYS:
+            assert torch.equal(f[k], o[k]), k
+
+
+def test_autotuned_plan_keeps_bits():
+    api = _api()
+    jobs = _jobs(api, n_nets=20, seed=7)
+    b0 = api.Batch(jobs, with_hash=True)
+    b0.run(seed=9)
+    with tempfile.TemporaryDirectory() as d:
+        plan = os.path.join(d, "plan.txt")
+        n = api.autotune(b0, plan, samples=2)
+        assert n >= 1
+        lines = open(plan).read().split()
+        assert lines and lines[0] in ("wave", "workgroup")
+        b1 = api.Batch(jobs, with_hash=True, plan_path=plan)
+        b1.run(seed=9)
+    for o0, o1 in zip(b0.outputs, b1.outputs):
+        for k in KEYS:
+            assert torch.equal(o0[k], o1[k]), k
