@@ -212,11 +212,20 @@ def bench_gradient(api, W, reps=3):
     return res
 
 
-def bench_batched(api, W, steps=2, n_nets=4096, solo_sample=128):
+BATCH_MAX_FIRINGS = 100_000     # per trajectory; 5x the 2e4 the t_end is set for
+
+
+def bench_batched(api, W, steps=2, n_nets=4096, solo_sample=32, tune_samples=16):
     """4096 random networks (M log-uniform in [3, 2048], N = M/4, 64
     trajectories each, t_end for about 2e4 firings) in one captured launch per
-    size class, against one rtssa_simulate launch per network (timed on a
-    sample of networks and scaled to the whole batch)."""
+    size class, lane counts chosen by the autotuner, against one rtssa_simulate
+    launch per network.  Networks whose rates grow with the state can run far
+    past 2e4 firings; every trajectory is capped at 1e5 firings (status
+    MAX_FIRINGS, counted), in the batch and in the per-network launches alike.
+    The per-network time is measured on a stratified sample (every
+    n_nets/solo_sample-th network in order of M) and scaled to the batch."""
+    import tempfile
+
     import numpy as np
     import torch
     t0 = time.perf_counter()
@@ -224,7 +233,17 @@ def bench_batched(api, W, steps=2, n_nets=4096, solo_sample=128):
     jobs = [dict(net=api.Network(w.net), x0=w.x0, t_end=w.t_end, sample_t=w.sample_t, R=w.R,
                  net_id=w.net_id) for w in wl]
     log("batched: %d networks generated in %.1f s" % (n_nets, time.perf_counter() - t0))
-    b = api.Batch(jobs, want=("samples", "n", "T", "x_final", "status"))
+    want = ("samples", "n", "T", "x_final", "status")
+    b0 = api.Batch(jobs, want=want, max_firings=BATCH_MAX_FIRINGS)
+    with tempfile.TemporaryDirectory() as d:
+        plan = os.path.join(d, "plan.txt")
+        t0 = time.perf_counter()
+        api.autotune(b0, plan, samples=tune_samples)
+        tune_s = time.perf_counter() - t0
+        plan_text = open(plan).read().strip().splitlines()
+        del b0
+        b = api.Batch(jobs, want=want, max_firings=BATCH_MAX_FIRINGS, plan_path=plan)
+    log("batched: autotuned in %.1f s: %s" % (tune_s, "; ".join(plan_text)))
     st = b.run(seed=1)                                   # captures the graph
     log("batched warmup: %.1f ms, %d firings" % (st["kernel_ms"], st["firings"]))
     torch.cuda.synchronize()
@@ -237,29 +256,38 @@ def bench_batched(api, W, steps=2, n_nets=4096, solo_sample=128):
         log("batched step %d: %.1f ms, %d firings" % (i, st["kernel_ms"], st["firings"]))
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    # one launch per network, on a sample of networks
-    rng = np.random.default_rng(0)
-    idx = sorted(rng.choice(n_nets, size=min(solo_sample, n_nets), replace=False))
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    solo_fir = 0
+    capped = int((torch.cat([o["status"] for o in b.outputs]) == api.TRAJ_MAX_FIRINGS).sum())
+    # one launch per network, on a stratified sample of networks
+    order = sorted(range(n_nets), key=lambda i: wl[i].net.M)
+    stride = max(1, n_nets // solo_sample)
+    idx = order[stride // 2::stride][:solo_sample]
+    solo_ms, solo_fir = 0.0, 0
     for i in idx:
         j = jobs[i]
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
         o = api.simulate(j["net"], j["x0"], j["t_end"], j["sample_t"], j["R"], seed=1,
-                         net_id=j["net_id"], want=("samples", "n", "T", "x_final", "status"),
-                         stats=False)
+                         net_id=j["net_id"], want=want, stats=False,
+                         max_firings=BATCH_MAX_FIRINGS)
+        torch.cuda.synchronize()
+        solo_ms += (time.perf_counter() - t1) * 1e3
         solo_fir += int(o["n"].to(torch.int64).sum())
-    torch.cuda.synchronize()
-    solo_wall = time.perf_counter() - t1
-    solo_rate = solo_fir / solo_wall
+    est_ms = solo_ms * n_nets / len(idx)
     per_step = fir / steps
+    ms_step = wall / steps * 1e3
+    log("batched: per-network launches, %d sampled: %.1f ms -> %.0f ms for all" %
+        (len(idx), solo_ms, est_ms))
     return {"workload": "batched_random_networks", "networks": n_nets, "trajectories_each": 64,
-            "value": fir / wall, "unit": "firings/s", "ms_per_step": wall / steps * 1e3,
-            "firings_per_step": per_step, "graph": True, "classes": b.classes(),
-            "per_network_launches": {"value": solo_rate, "unit": "firings/s",
-                                     "networks_timed": len(idx),
-                                     "estimated_ms_for_all": per_step / solo_rate * 1e3},
-            "speedup_vs_per_network": (fir / wall) / solo_rate}
+            "value": fir / wall, "unit": "firings/s", "ms_per_step": ms_step,
+            "firings_per_step": per_step, "graph": True,
+            "max_firings_per_trajectory": BATCH_MAX_FIRINGS,
+            "trajectories_capped": capped, "autotune_s": tune_s, "plan": plan_text,
+            "classes": b.classes(),
+            "per_network_launches": {"networks_timed": len(idx), "sample_ms": solo_ms,
+                                     "sample_firings": solo_fir,
+                                     "estimated_ms_for_all": est_ms,
+                                     "value": per_step / (est_ms / 1e3), "unit": "firings/s"},
+            "speedup_vs_per_network": est_ms / ms_step}
 
 
 def main():

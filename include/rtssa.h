@@ -233,11 +233,16 @@ int rtssa_batch_info(const rtssa_batch* batch, int32_t cls, int32_t* mapping, in
 int rtssa_batch_destroy(rtssa_batch* batch);
 
 /* Autotuner: for every size class among the items (networks beyond the
- * thread mapping), time each feasible lane count / workgroup size on up to
- * `samples` items of the class (short runs, results discarded) and write the
- * fastest to the plan file plan_path (text: "wave|workgroup M_lo M_hi L").
- * Returns the number of classes tuned (>= 0) or a negative error code.
- * Synchronous. */
+ * thread mapping: sub-wavefront classes by lanes per trajectory, workgroup
+ * classes by power-of-two channel ranges), time each feasible lane count /
+ * workgroup size on a sub-batch of up to `samples` items of the class, run
+ * as the batch runs it (one shared persistent grid; outputs not written; at
+ * most 1000 firings per trajectory; items with a shared x0 run with more
+ * trajectories so that the sub-batch fills the device), and write the
+ * fastest, in firings per second, to the plan file plan_path (text lines
+ * "wave|workgroup M_lo M_hi L").  Returns the number of classes tuned (>= 0)
+ * or a negative error code.  Synchronous; allocates and frees device memory.
+ */
 int rtssa_autotune(const rtssa_batch_item* items, int32_t count, int32_t samples,
                    const char* plan_path, rtssa_stream_t stream);
 

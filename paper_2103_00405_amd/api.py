@@ -270,7 +270,7 @@ class Batch:
         self._h = None
 
 
-def autotune(batch_jobs_items, plan_path, samples=4):
+def autotune(batch_jobs_items, plan_path, samples=16):
     """Write a plan file choosing lanes per trajectory / workgroup size per
     size class by timing short runs (see rtssa_autotune)."""
     b = batch_jobs_items

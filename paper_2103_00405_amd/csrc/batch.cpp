@@ -109,9 +109,18 @@ struct rtssa_batch {
     int device = -1;
 };
 
+static int batch_create(const rtssa_batch_item* items, int32_t count, const rtssa_options* opt,
+                        const std::vector<plan_entry>& plan, rtssa_batch** out);
+
 extern "C" int rtssa_batch_create(const rtssa_batch_item* items, int32_t count,
                                   const rtssa_options* opt, const char* plan_path,
                                   rtssa_batch** out)
+{
+    return batch_create(items, count, opt, read_plan(plan_path), out);
+}
+
+static int batch_create(const rtssa_batch_item* items, int32_t count, const rtssa_options* opt,
+                        const std::vector<plan_entry>& plan, rtssa_batch** out)
 {
     if (!out) return rt_fail(RTSSA_E_INVALID, "out is NULL");
     *out = nullptr;
@@ -127,7 +136,6 @@ extern "C" int rtssa_batch_create(const rtssa_batch_item* items, int32_t count,
                               b.traj_offset, b.R, nullptr);
         if (rc) return rt_fail(rc, "item " + std::to_string(i) + ": " + rtssa_last_error());
     }
-    const std::vector<plan_entry> plan = read_plan(plan_path);
     std::map<class_key, std::vector<int>> groups;
     for (int i = 0; i < count; ++i)
         if (items[i].R > 0) groups[classify(items[i].net, plan, o)].push_back(i);
@@ -343,10 +351,16 @@ extern "C" int rtssa_batch_destroy(rtssa_batch* B)
 }
 
 // ---------------------------------------------------------------- autotuner
-// For each size class present in the items (sub-wave: channel counts in
-// (8L/2, 8L]; workgroup: powers of two), time every feasible lane count on up
-// to `samples` items of the class (a short run of each, the same seed) and
-// record the fastest in the plan file.  Returns the number of classes tuned.
+// Size classes present in the items: sub-wave channel counts in (8L/2, 8L]
+// (all counts up to 32 for L = 4); workgroup counts in power-of-two ranges
+// from (512, 1024] up.  For each class, every feasible lane count is timed on
+// a sub-batch of up to `samples` of its items, launched the way the batch
+// launches the class (one persistent grid shared by the items, outputs
+// dropped, firings capped at 1000 per trajectory); items with a shared x0
+// get more trajectories so that the sub-batch fills the device (32768
+// trajectories for sub-wavefront classes, 4096 for workgroup classes).  The
+// fastest in firings per second goes to the plan file.  Returns the number
+// of classes tuned.
 extern "C" int rtssa_autotune(const rtssa_batch_item* items, int32_t count, int32_t samples,
                               const char* plan_path, rtssa_stream_t stream_)
 {
@@ -356,17 +370,19 @@ extern "C" int rtssa_autotune(const rtssa_batch_item* items, int32_t count, int3
     std::map<std::pair<int, int>, bucket> buckets;
     for (int i = 0; i < count; ++i) {
         const rtssa_network* n = items[i].net;
+        if (items[i].R < 1) continue;
         int m = rt_auto_mapping(n);
         if (m == RTSSA_MAP_THREAD) continue;
+        if (m == RTSSA_MAP_WAVE && n->M > 512) m = RTSSA_MAP_WORKGROUP;
         int lo, hi;
         if (m == RTSSA_MAP_WAVE) {
             int L = rt_subwave_lanes(n->M);
-            lo = L == 4 ? 0 : 4 * L + 1;
+            lo = L == 4 ? 1 : 4 * L + 1;
             hi = 8 * L;
         } else {
             hi = 1024;
             while (hi < n->M) hi <<= 1;
-            lo = hi / 2 + 1;
+            lo = hi == 1024 ? 1 : hi / 2 + 1;
         }
         auto& b = buckets[{m, hi}];
         b.mapping = m;
@@ -374,52 +390,64 @@ extern "C" int rtssa_autotune(const rtssa_batch_item* items, int32_t count, int3
         b.hi = hi;
         if ((int)b.members.size() < std::max(1, samples)) b.members.push_back(i);
     }
-    FILE* f = fopen(plan_path, "w");
-    if (!f) return rt_fail(RTSSA_E_INVALID, std::string("cannot write ") + plan_path);
-    int tuned = 0;
+    std::vector<plan_entry> chosen;
     for (auto& kv : buckets) {
         bucket& b = kv.second;
+        int max_nu = 0, max_M = 0;
+        std::vector<rtssa_batch_item> sub;
+        // enough trajectories to fill the device at every candidate (a
+        // too-small sub-batch measures latency, not throughput)
+        const int64_t fill = b.mapping == RTSSA_MAP_WAVE ? 32768 : 4096;
+        const int64_t per_item = (fill + (int64_t)b.members.size() - 1) / (int64_t)b.members.size();
+        for (int i : b.members) {
+            rtssa_batch_item it = items[i];
+            if (!it.x0_per_traj) it.R = std::max<int64_t>(it.R, per_item);
+            // outputs dropped: the tuning runs leave the caller's buffers alone
+            it.samples = nullptr;
+            it.G = 0;
+            it.sample_t = nullptr;
+            it.n_out = nullptr;
+            it.T_out = nullptr;
+            it.x_final = nullptr;
+            it.t_last = nullptr;
+            it.status = nullptr;
+            it.seq_hash = nullptr;
+            it.tie_step = nullptr;
+            sub.push_back(it);
+            max_nu = std::max(max_nu, it.net->max_nu);
+            max_M = std::max(max_M, it.net->M);
+        }
         std::vector<int> cands;
         if (b.mapping == RTSSA_MAP_WAVE) {
             for (int L = 4; L <= 64; L <<= 1)
-                if (8 * L >= b.hi) cands.push_back(L);
+                if (8 * L >= max_M && L >= max_nu) cands.push_back(L);
         } else {
-            for (int L = 128; L <= 1024; L <<= 1) cands.push_back(L);
+            for (int L = 64; L <= 1024; L <<= 1)
+                if (rt_group_supported(max_M, L)) cands.push_back(L);
         }
         double best = -1.0;
-        int bestL = cands.empty() ? 0 : cands[0];
+        int bestL = 0;
         for (int L : cands) {
-            double fired = 0, ms = 0;
-            bool ok = true;
-            for (int i : b.members) {
-                const rtssa_batch_item& it = items[i];
-                if (b.mapping == RTSSA_MAP_WAVE && (L < it.net->max_nu || 8 * L < it.net->M)) {
-                    ok = false;
-                    break;
-                }
-                rtssa_options o{};
-                o.mapping = b.mapping;
-                o.block = L;
-                o.max_firings = 20000;
-                rtssa_stats st{};
-                int rc = rtssa_simulate(it.net, it.x0, it.x0_per_traj, it.t_end, nullptr, 0, 7,
-                                        it.net_id, it.traj_offset, it.R, nullptr, 0, 0, 0, nullptr,
-                                        nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, &o,
-                                        (rtssa_stream_t)stream, &st);
-                if (rc) { ok = false; break; }
-                fired += (double)st.firings;
-                ms += st.kernel_ms;
-            }
-            if (!ok || ms <= 0) continue;
-            const double rate = fired / ms;
+            rtssa_options o{};
+            o.mapping = b.mapping;
+            o.max_firings = 1000;
+            std::vector<plan_entry> p = {{b.mapping, 1, 1 << 30, L}};
+            rtssa_batch* tb = nullptr;
+            if (batch_create(sub.data(), (int32_t)sub.size(), &o, p, &tb)) continue;
+            rtssa_stats st{};
+            const int rc = rtssa_batch_run(tb, 7, 0, (rtssa_stream_t)stream, &st);
+            rtssa_batch_destroy(tb);
+            if (rc || st.kernel_ms <= 0) continue;
+            const double rate = (double)st.firings / st.kernel_ms;
             if (rate > best) { best = rate; bestL = L; }
         }
-        if (best > 0) {
-            fprintf(f, "%s %d %d %d\n", b.mapping == RTSSA_MAP_WAVE ? "wave" : "workgroup", b.lo,
-                    b.hi, bestL);
-            ++tuned;
-        }
+        if (bestL > 0) chosen.push_back({b.mapping, b.lo, b.hi, bestL});
     }
+    FILE* f = fopen(plan_path, "w");
+    if (!f) return rt_fail(RTSSA_E_INVALID, std::string("cannot write ") + plan_path);
+    for (const auto& e : chosen)
+        fprintf(f, "%s %d %d %d\n", e.mapping == RTSSA_MAP_WAVE ? "wave" : "workgroup", e.lo, e.hi,
+                e.L);
     fclose(f);
-    return tuned;
+    return (int)chosen.size();
 }

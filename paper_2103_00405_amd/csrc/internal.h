@@ -134,7 +134,9 @@ int rt_thread_supported(int M, int N);
 int rt_launch_group(int M, int max_N, int max_M, const rt_class_dev& C, int L, int grid,
                     hipStream_t stream, int* grid_used);
 int rt_group_slots(int M, int L);
-size_t rt_group_lds_bytes(int N, int M);
+// true when a workgroup kernel with L threads exists for M channels
+bool rt_group_supported(int M, int L);
+size_t rt_group_lds_bytes(int N, int M, int L);
 int rt_launch_subwave(int max_M, const rt_class_dev& C, int L, int grid, hipStream_t stream,
                       int* grid_used);
 int rt_subwave_slots(int M, int L);

@@ -1,29 +1,31 @@
 // kernels_group.hip -- wavefront- and workgroup-per-trajectory mappings.
 //
-// One workgroup of L threads (L = 64: one wavefront; L = 256..1024: several)
+// One workgroup of L threads (L = 64: one wavefront; L = 128..1024: several)
 // simulates one trajectory at a time; the grid is persistent and takes
 // trajectory indices from a device work queue.  Channel k belongs to thread
-// k mod L, slot k / L; each thread keeps its channels' T_k, P_k, a_k, 1/a_k
-// and n_k in registers.  The species counts X and a bitmap of channels whose
-// propensity must be recomputed live in LDS.
+// k mod L, slot k / L; each thread keeps its channels' T_k, P_k, a_k and
+// 1/a_k in registers (slots past M are frozen channels that never win).  The
+// species counts X, the firing counts n_k and one stale word per thread (bit
+// s: slot s must recompute its propensity) live in LDS.
 //
 // One firing (section 4, Table 2, in the internal-time form of Eq. 14-16):
-//   pass   every thread, for its channels: apply the previous event
-//          (T_k += a_k Delta, or T_mu = P_mu and P_mu += E for the fired
-//          channel), recompute a_k and 1/a_k if the channel reads a species
-//          the previous event changed, then the gap (P_k - T_k)/a_k and a
-//          local argmin with second minimum;
-//   argmin across the wavefront by shuffles, across wavefronts through LDS
-//          (barrier 1); lowest k wins ties (Eq. 25);
+//   pass   every thread: T_k += a_k Delta for all its channels (Eq. 15); the
+//          owner of the previous event's channel sets T_mu = P_mu and adds
+//          the fresh Exp(1) to P_mu (Eq. 26); stale slots recompute a_k and
+//          1/a_k; then the gaps (P_k - T_k)/a_k and a local argmin with
+//          second minimum, branch-free;
+//   argmin across the wavefront by DPP and permlane exchanges, across
+//          wavefronts through LDS (barrier 1); lowest k wins ties (Eq. 25);
 //   event  wavefront 0 applies the jump v_mu to X; the threads of the
 //          dependency list D(mu) (the channels reading a changed species,
-//          Gibson & Bruck's dependency graph cited in section 5) flag their
-//          channels; the owner of mu draws the fresh Exp(1) (Eq. 26)
-//          (barrier 2).
+//          Gibson & Bruck's dependency graph cited in section 5) set stale
+//          bits; the owner of mu draws the fresh Exp(1) (barrier 2) and
+//          counts the firing in n_mu.
 #include <hip/hip_runtime.h>
 
 #include "internal.h"
 #include "rt_device.h"
+#include "rt_wave.h"
 
 namespace {
 
@@ -55,39 +57,6 @@ __device__ __forceinline__ double group_propensity(int2 rr, double c, const int3
     return c * u64_to_f64(h);
 }
 
-// (d1, d2, k, clamped): smallest gap, second smallest gap (order statistic
-// with multiplicity), its channel, and whether its raw gap was negative.
-struct rt_min2 {
-    double d1, d2;
-    int k;
-    int clamped;
-};
-
-__device__ __forceinline__ void min2_merge(rt_min2& a, const rt_min2& b)
-{
-    const bool bw = b.d1 < a.d1 || (b.d1 == a.d1 && b.k < a.k);
-    const double d2 = bw ? fmin(b.d2, a.d1) : fmin(a.d2, b.d1);
-    a.d1 = bw ? b.d1 : a.d1;
-    a.k = bw ? b.k : a.k;
-    a.clamped = bw ? b.clamped : a.clamped;
-    a.d2 = d2;
-}
-
-__device__ __forceinline__ rt_min2 min2_shfl_xor(const rt_min2& v, int off)
-{
-    rt_min2 o;
-    o.d1 = __shfl_xor(v.d1, off, 64);
-    o.d2 = __shfl_xor(v.d2, off, 64);
-    o.k = __shfl_xor(v.k, off, 64);
-    o.clamped = __shfl_xor(v.clamped, off, 64);
-    return o;
-}
-
-__device__ __forceinline__ void min2_wave(rt_min2& v, int width)
-{
-    for (int off = width >> 1; off > 0; off >>= 1) min2_merge(v, min2_shfl_xor(v, off));
-}
-
 struct rt_group_shared {
     rt_min2 wave_min[16];
     unsigned long long next_traj;
@@ -96,7 +65,7 @@ struct rt_group_shared {
 };
 
 // Index of the item owning global unit u: unit_start[i] <= u < unit_start[i+1].
-__device__ __forceinline__ int group_find_item(const int64_t* unit_start, int count, int64_t u)
+__device__ __forceinline__ int group_find_item(rt_cptr<int64_t> unit_start, int count, int64_t u)
 {
     int lo = 0, hi = count;
     while (hi - lo > 1) {
@@ -106,61 +75,87 @@ __device__ __forceinline__ int group_find_item(const int64_t* unit_start, int co
     return lo;
 }
 
+// Waves per SIMD the register allocation aims at: 16 slots of channel state
+// fit 2, 8 fit 3, fewer fit 4.
+constexpr int group_min_waves(int S) { return S >= 16 ? 2 : (S >= 8 ? 3 : 4); }
+
 template <int L, int S>
-__global__ __launch_bounds__(L) void rt_group_kernel(rt_class_dev C)
+__global__ __launch_bounds__(L, group_min_waves(S)) void rt_group_kernel(rt_class_dev C)
 {
     constexpr int W = L / 64;
+    constexpr int LOG2L = __builtin_ctz(L);
     extern __shared__ int32_t dyn_lds[];
     __shared__ rt_group_shared sh;
     rt_ws* const ws = C.ws;
     const uint32_t key0 = ws->key0, key1 = ws->key1;
-    const int64_t total = C.unit_start[C.count];
+    const rt_cptr<int64_t> unit_start = rt_const(C.unit_start);
+    const int64_t total = unit_start[C.count];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    int32_t* X = dyn_lds;                                   // [N]
-    // two bitmaps of channels to refresh, alternating by event parity: one is
-    // read (and then cleared) while the next event sets the other
-    const int nflag = (C.max_M + 31) >> 5;
-    uint32_t* flag_buf = (uint32_t*)(dyn_lds + ((C.max_N + 3) & ~3));   // [2][nflag]
+    int32_t* X = dyn_lds;                                            // [N] species counts
+    uint32_t* nk = (uint32_t*)(dyn_lds + ((C.max_N + 3) & ~3));      // [M] firing counts n_k
+    // stale words: bit s of word t marks channel t + s L, so each thread
+    // reads (and clears) its whole stale set at once.  The event of one firing
+    // sets bits between barriers 1 and 2; every thread reads and clears its
+    // own word in the next pass, before the next barrier 1.
+    uint32_t* stale_w = nk + ((C.max_M + 3) & ~3);                   // [L]
     uint32_t* sc = sh.log_scratch[wave];
 
+    // channel state: slot s of thread tid is channel tid + s L; slots past M
+    // are frozen channels (a = 0) and never win
     double T[S], Pk[S], a[S], inv[S];
-    uint32_t n[S];
 #pragma unroll
-    for (int s = 0; s < S; ++s) { T[s] = 0.0; Pk[s] = 0.0; a[s] = 0.0; inv[s] = 0.0; n[s] = 0; }
+    for (int s = 0; s < S; ++s) { T[s] = 0.0; Pk[s] = 0.0; a[s] = 0.0; inv[s] = __builtin_inf(); }
 
     for (;;) {
         // ---- next trajectory unit
         if (tid == 0) sh.next_traj = atomicAdd(&ws->next_unit, 1ull);
         __syncthreads();
-        const int64_t u = (int64_t)sh.next_traj;
+        // the unit is the same for the whole workgroup: keep it (and with it
+        // the item descriptor and the network's table pointers) in SGPRs
+        const unsigned long long u_lds = sh.next_traj;
+        const int64_t u = (int64_t)(((unsigned long long)(uint32_t)__builtin_amdgcn_readfirstlane(
+                                         (int)(u_lds >> 32)) << 32) |
+                                     (uint32_t)__builtin_amdgcn_readfirstlane((int)u_lds));
         if (u >= total) break;
-        const int item = group_find_item(C.unit_start, C.count, u);
-        const rt_item_dev* it = C.items + item;
+        const int item = __builtin_amdgcn_readfirstlane(group_find_item(unit_start, C.count, u));
+        const rt_cptr<rt_item_dev> it = rt_const(C.items) + item;
         const rt_net_dev net = it->net;
         const int N = net.N, M = net.M;
-        const int64_t r = u - C.unit_start[item];
+        const rt_cptr<int2> react = rt_const(net.react);
+        const rt_cptr<double> cc = rt_const(net.c);
+        const rt_cptr<int32_t> nu_ptr = rt_const(net.nu_ptr), nu_sp = rt_const(net.nu_sp);
+        const rt_cptr<int32_t> nu_dl = rt_const(net.nu_dl), dep_ptr = rt_const(net.dep_ptr);
+        const rt_cptr<int32_t> dep_idx = rt_const(net.dep_idx);
+        const rt_cptr<double> grid_s = rt_const(it->s);
+        const int64_t r = u - unit_start[item];
         const uint32_t traj = it->traj_offset + (uint32_t)r;
         const uint32_t net_id = it->net_id;
         const double t_end = it->t_end;
         const int32_t* x0 = it->x0 + (it->x0_per_traj ? r * N : 0);
         for (int j = tid; j < N; j += L) X[j] = x0[j];
-        for (int q = tid; q < 2 * nflag; q += L) flag_buf[q] = 0u;
+        for (int k = tid; k < M; k += L) nk[k] = 0u;
+        stale_w[tid] = 0u;
         __syncthreads();
-        uint32_t* flags_rd = flag_buf;            // set by the pending event
-        uint32_t* flags_wr = flag_buf + nflag;    // set by the next event
 #pragma unroll
-        for (int s = 0; s < S; ++s) {
-            const int k = tid + s * L;
-            T[s] = 0.0;
-            n[s] = 0;
+        for (int s = 0; s < S; ++s) { T[s] = 0.0; Pk[s] = 0.0; a[s] = 0.0; inv[s] = __builtin_inf(); }
+        // first internal firing times and propensities, one slot at a time
+#pragma unroll 1
+        for (int s1 = 0; s1 < S; ++s1) {
+            const int k = tid + s1 * L;
             if (k < M) {
-                Pk[s] = rt_exp1_wave(key0, key1, traj, net_id, (uint32_t)k, 0u,
-                                     &ws->slow_logs, sc);
-                a[s] = group_propensity(net.react[k], net.c[k], X);
-                inv[s] = 1.0 / a[s];
+                const double p0 = rt_exp1_wave(key0, key1, traj, net_id, (uint32_t)k, 0u,
+                                               &ws->slow_logs, sc);
+                const double an = group_propensity(react[k], cc[k], X);
+                const double in = 1.0 / an;
+#pragma unroll
+                for (int s = 0; s < S; ++s) {
+                    Pk[s] = s == s1 ? p0 : Pk[s];
+                    a[s] = s == s1 ? an : a[s];
+                    inv[s] = s == s1 ? in : inv[s];
+                }
             }
         }
-        double t = 0.0, s_next = it->G > 0 ? it->s[0] : __builtin_inf();
+        double t = 0.0, s_next = it->G > 0 ? grid_s[0] : __builtin_inf();
         int32_t g = 0;
         uint32_t fired = 0, tie = kTieNone;
         unsigned long long hash = kFnvOffset;
@@ -172,54 +167,62 @@ __global__ __launch_bounds__(L) void rt_group_kernel(rt_class_dev C)
 
         for (;;) {
             // ---- pass over own channels: apply the pending event, refresh, gap
-            rt_min2 loc = {__builtin_inf(), __builtin_inf(), 0x7FFFFFFF, 0};
+            if (pending) {
+                // every internal clock advances by a_k delta (Eq. 15) ...
 #pragma unroll
-            for (int s = 0; s < S; ++s) {
-                const int k = tid + s * L;
-                if (k < M) {
-                    if (pending) {
-                        if (k == mu) {
+                for (int s = 0; s < S; ++s) T[s] = fma(a[s], delta, T[s]);
+                // ... except the fired one, which is set to its firing time and
+                // gets its next one (Eq. 26)
+                if (tid == (mu & (L - 1))) {
+                    const int sm = mu >> LOG2L;
+#pragma unroll
+                    for (int s = 0; s < S; ++s) {
+                        if (s == sm) {
                             T[s] = Pk[s];
                             Pk[s] = Pk[s] + E;
-                            n[s] += 1u;
-                        } else {
-                            T[s] = fma(a[s], delta, T[s]);
-                        }
-                        const uint32_t bit = 1u << (k & 31);
-                        if (flags_rd[k >> 5] & bit) {
-                            a[s] = group_propensity(net.react[k], net.c[k], X);
-                            inv[s] = 1.0 / a[s];
                         }
                     }
-                    const double raw = (Pk[s] - T[s]) * inv[s];
-                    double d = raw < 0.0 ? 0.0 : raw;
-                    d = a[s] == 0.0 ? __builtin_inf() : d;
-                    const bool lt = d < loc.d1;
-                    loc.d2 = lt ? loc.d1 : (d < loc.d2 ? d : loc.d2);
-                    loc.d1 = lt ? d : loc.d1;
-                    loc.k = lt ? k : loc.k;
-                    loc.clamped = lt ? (raw < 0.0) : loc.clamped;
+                }
+                // refresh the slots whose propensity reads a changed species,
+                // one at a time (keeps the propensity code out of the
+                // unrolled pass)
+                unsigned int stale = stale_w[tid];
+                stale_w[tid] = 0u;
+                while (stale) {
+                    const int s1 = __builtin_ctz(stale);
+                    stale &= stale - 1u;
+                    const int k = tid + s1 * L;
+                    const double an = group_propensity(react[k], cc[k], X);
+                    const double in = 1.0 / an;
+#pragma unroll
+                    for (int s = 0; s < S; ++s) {
+                        a[s] = s == s1 ? an : a[s];
+                        inv[s] = s == s1 ? in : inv[s];
+                    }
                 }
             }
             if (st == RTSSA_TRAJ_MAX_FIRINGS) break;       // the capped event is now applied
+            rt_min2 loc = rt_min2_empty();
+#pragma unroll
+            for (int s = 0; s < S; ++s) {
+                const double raw = (Pk[s] - T[s]) * inv[s];
+                const double d = a[s] == 0.0 ? __builtin_inf() : fmax(raw, 0.0);
+                rt_min2_push(loc, d, s);                   // slot now, channel below
+            }
+            loc.k = loc.k == 0x7FFFFFFF ? loc.k : tid + (loc.k << LOG2L);
             // ---- argmin over the workgroup
-            min2_wave(loc, 64);
-            if (W > 1) {
+            loc = rt_min2_allreduce<64>(loc);
+            if constexpr (W > 1) {
                 if (lane == 0) sh.wave_min[wave] = loc;
             }
             __syncthreads();                               // barrier 1
-            if (pending) {
-                // every thread has read the pending event's flags: clear them
-                for (int q = tid; q < nflag; q += L) flags_rd[q] = 0u;
+            if constexpr (W > 1) {
+                // every lane reads partial (lane mod W): the groups of W lanes
+                // all reduce the same W values
+                loc = rt_min2_allreduce<W>(sh.wave_min[lane & (W - 1)]);
             }
-            if (W > 1) {
-                rt_min2 v = lane < W ? sh.wave_min[lane] : rt_min2{__builtin_inf(), __builtin_inf(), 0x7FFFFFFF, 0};
-                min2_wave(v, W < 2 ? 2 : W);
-                loc = v;
-            }
-            const double d1 = __shfl(loc.d1, 0, 64), d2 = __shfl(loc.d2, 0, 64);
-            mu = __builtin_amdgcn_readfirstlane(__shfl(loc.k, 0, 64));
-            const int clamped = __builtin_amdgcn_readfirstlane(__shfl(loc.clamped, 0, 64));
+            const double d1 = loc.d1, d2 = loc.d2;
+            mu = __builtin_amdgcn_readfirstlane(loc.k);
             const double t_new = t + d1;
             if (d1 == __builtin_inf()) { st = RTSSA_TRAJ_ABSORBED; break; }
             if (t_new > t_end) { st = RTSSA_TRAJ_OK; break; }
@@ -235,48 +238,55 @@ __global__ __launch_bounds__(L) void rt_group_kernel(rt_class_dev C)
                         for (int j = tid; j < N; j += L) dst[j * it->ss_n] = X[j];
                     }
                     ++g;
-                    s_next = g < it->G ? it->s[g] : __builtin_inf();
+                    s_next = g < it->G ? grid_s[g] : __builtin_inf();
                 }
                 __syncthreads();
             }
             // ---- the event: jump (wave 0), dependency flags, fresh draw (owner)
-            const int nb = net.nu_ptr[mu], ne = net.nu_ptr[mu + 1];
+            const int nb = nu_ptr[mu], ne = nu_ptr[mu + 1];
             if (wave == 0) {
                 int32_t v = 0;
                 bool okl = true;
                 if (lane < ne - nb) {
-                    const int64_t nv = (int64_t)X[net.nu_sp[nb + lane]] + net.nu_dl[nb + lane];
+                    const int64_t nv = (int64_t)X[nu_sp[nb + lane]] + nu_dl[nb + lane];
                     okl = nv >= 0 && nv <= 0x7FFFFFFF;
                     v = (int32_t)nv;
                 }
                 const bool ok = __ballot(!okl) == 0ull;
-                if (ok && lane < ne - nb) X[net.nu_sp[nb + lane]] = v;
+                if (ok && lane < ne - nb) X[nu_sp[nb + lane]] = v;
                 if (lane == 0) sh.ok = ok;
             }
-            const int db = net.dep_ptr[mu], de = net.dep_ptr[mu + 1];
+            const int db = dep_ptr[mu], de = dep_ptr[mu + 1];
             for (int q = db + tid; q < de; q += L) {
-                const int kk = net.dep_idx[q];
-                atomicOr(&flags_wr[kk >> 5], 1u << (kk & 31));
+                const int kk = dep_idx[q];
+                atomicOr(&stale_w[kk & (L - 1)], 1u << (kk >> LOG2L));
             }
-            if (tid == (mu % L)) {
-                const int slot = mu / L;
-                uint32_t nm = n[0];
-#pragma unroll
-                for (int s = 1; s < S; ++s) nm = slot == s ? n[s] : nm;
+            const bool owner = tid == (mu & (L - 1));
+            uint32_t nm = 0;
+            bool clamped = false;
+            if (owner) {
+                nm = nk[mu];
                 E = rt_exp1_wave(key0, key1, traj, net_id, (uint32_t)mu, nm + 1u,
                                  &ws->slow_logs, sc);
+                if (d1 == 0.0) {
+                    // a zero gap: was it clamped from a negative raw gap?
+                    const int sm = mu >> LOG2L;
+#pragma unroll
+                    for (int s = 0; s < S; ++s)
+                        if (s == sm) clamped = (Pk[s] - T[s]) * inv[s] < 0.0;
+                }
             }
             __syncthreads();                               // barrier 2
             if (!sh.ok) { st = RTSSA_TRAJ_OVERFLOW; break; }
-            if (clamped && tid == 0) atomicAdd(&ws->clamps, 1ull);
+            if (owner) {
+                nk[mu] = nm + 1u;
+                if (clamped) atomicAdd(&ws->clamps, 1ull);
+            }
             t = t_new;
             delta = d1;
             ++fired;
             hash = (hash ^ (unsigned long long)(uint32_t)mu) * kFnvPrime;
             pending = true;
-            uint32_t* tmp = flags_rd;
-            flags_rd = flags_wr;
-            flags_wr = tmp;
             if (fired >= C.max_firings) st = RTSSA_TRAJ_MAX_FIRINGS;   // apply, then stop
         }
 
@@ -294,7 +304,7 @@ __global__ __launch_bounds__(L) void rt_group_kernel(rt_class_dev C)
             const int k = tid + s * L;
             if (k < M) {
                 if (good) T[s] = fma(a[s], dt, T[s]);
-                if (it->n_out) it->n_out[r * M + k] = n[s];
+                if (it->n_out) it->n_out[r * M + k] = nk[k];
                 if (it->T_out) it->T_out[r * M + k] = T[s];
             }
         }
@@ -308,7 +318,7 @@ __global__ __launch_bounds__(L) void rt_group_kernel(rt_class_dev C)
             atomicAdd(&ws->firings, (unsigned long long)fired);
             atomicAdd(&ws->status_count[st], 1ull);
         }
-        __syncthreads();                                   // X is reused next
+        __syncthreads();                                   // X and nk are reused next
     }
 }
 
@@ -322,7 +332,7 @@ group_kernel_t select_group(int L, int S)
 #define RT_CASE(l, s) if (L == l && S == s) return pick_kernel<l, s>();
     RT_CASE(64, 1) RT_CASE(64, 2) RT_CASE(64, 4) RT_CASE(64, 8) RT_CASE(64, 16)
     RT_CASE(256, 1) RT_CASE(256, 2) RT_CASE(256, 4) RT_CASE(256, 8) RT_CASE(256, 16)
-    RT_CASE(128, 16) RT_CASE(128, 32)
+    RT_CASE(128, 4) RT_CASE(128, 8) RT_CASE(128, 16)
     RT_CASE(512, 1) RT_CASE(512, 2) RT_CASE(512, 4) RT_CASE(512, 8)
     RT_CASE(1024, 1) RT_CASE(1024, 2) RT_CASE(1024, 4) RT_CASE(1024, 8)
 #undef RT_CASE
@@ -331,9 +341,9 @@ group_kernel_t select_group(int L, int S)
 
 }  // namespace
 
-size_t rt_group_lds_bytes(int N, int M)
+size_t rt_group_lds_bytes(int N, int M, int L)
 {
-    return (size_t)((N + 3) & ~3) * 4 + (size_t)((M + 31) >> 5) * 8 + 16;
+    return (size_t)((N + 3) & ~3) * 4 + (size_t)((M + 3) & ~3) * 4 + (size_t)L * 4;
 }
 
 int rt_group_slots(int M, int L)
@@ -344,13 +354,18 @@ int rt_group_slots(int M, int L)
     return p < 1 ? 1 : p;
 }
 
+bool rt_group_supported(int M, int L)
+{
+    return M >= 1 && select_group(L, rt_group_slots(M, L)) != nullptr;
+}
+
 int rt_launch_group(int M, int max_N, int max_M, const rt_class_dev& C, int L, int grid,
                     hipStream_t stream, int* grid_used)
 {
     const int S = rt_group_slots(M, L);
     group_kernel_t kfn = select_group(L, S);
     if (!kfn) return rt_fail(RTSSA_E_UNSUPPORTED, "no group kernel for this network size and L");
-    const size_t lds = rt_group_lds_bytes(max_N, max_M);
+    const size_t lds = rt_group_lds_bytes(max_N, max_M, L);
     if (lds > 96 * 1024) return rt_fail(RTSSA_E_UNSUPPORTED, "network too large for LDS");
     if (lds > 48 * 1024 &&
         hipFuncSetAttribute((const void*)kfn, hipFuncAttributeMaxDynamicSharedMemorySize,

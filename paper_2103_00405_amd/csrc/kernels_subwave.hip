@@ -2,8 +2,10 @@
 // trajectories per wavefront, for mid-size networks.
 //
 // Channel k of a trajectory belongs to lane k mod L of its group, slot k / L;
-// T_k, P_k, a_k, 1/a_k and n_k live in that lane's VGPRs.  Each group has its
-// own species counts X and two dependency bitmaps in LDS.  The groups of a
+// T_k, P_k, a_k and 1/a_k live in that lane's VGPRs (slots past the
+// network's M are frozen channels that never win).  Each group has its own
+// species counts X, firing counts n_k and one stale word per lane (bit s:
+// slot s must recompute its propensity) in LDS.  The groups of a
 // wavefront advance in lockstep, one firing per pass, but each group runs its
 // own trajectory: the expensive per-firing tail (one Philox block and one
 // correctly rounded logarithm for the fired channel, Eq. 26) runs in one lane
@@ -19,6 +21,7 @@
 
 #include "internal.h"
 #include "rt_device.h"
+#include "rt_wave.h"
 
 namespace {
 
@@ -60,7 +63,7 @@ __device__ __forceinline__ void wave_lds_fence()
 }
 
 // Index of the item owning global unit u: unit_start[i] <= u < unit_start[i+1].
-__device__ __forceinline__ int find_item(const int64_t* unit_start, int count, int64_t u)
+__device__ __forceinline__ int find_item(rt_cptr<int64_t> unit_start, int count, int64_t u)
 {
     int lo = 0, hi = count;   // unit_start[lo] <= u < unit_start[hi]
     while (hi - lo > 1) {
@@ -70,12 +73,12 @@ __device__ __forceinline__ int find_item(const int64_t* unit_start, int count, i
     return lo;
 }
 
-#ifndef RT_SUBWAVE_MIN_WAVES
-#define RT_SUBWAVE_MIN_WAVES 2
-#endif
+// Waves per SIMD the register allocation aims at: 8 slots of channel state
+// fit 3, fewer fit 4.
+constexpr int subwave_min_waves(int S) { return S >= 8 ? 3 : 4; }
 
 template <int L, int S>
-__global__ __launch_bounds__(kBlock, RT_SUBWAVE_MIN_WAVES) void rt_subwave_kernel(rt_class_dev C)
+__global__ __launch_bounds__(kBlock, subwave_min_waves(S)) void rt_subwave_kernel(rt_class_dev C)
 {
     constexpr unsigned long long kGroupBits = L == 64 ? ~0ull : ((1ull << L) - 1ull);
     rt_ws* const ws = C.ws;
@@ -85,19 +88,21 @@ __global__ __launch_bounds__(kBlock, RT_SUBWAVE_MIN_WAVES) void rt_subwave_kerne
     extern __shared__ int32_t dyn_lds[];
     __shared__ uint32_t log_scratch[kBlock / 64][RT_LOG_SCRATCH];
     uint32_t* sc = log_scratch[tid >> 6];
-    const int NP = (C.max_N + 3) & ~3, NF = (C.max_M + 31) >> 5;
-    int32_t* X = dyn_lds + (tid / L) * (NP + 2 * NF);
-    uint32_t* fb = (uint32_t*)(X + NP);                 // [2][NF] dependency bitmaps
-    const int64_t total = C.unit_start[C.count];
+    constexpr int LOG2L = __builtin_ctz(L);
+    const int NP = (C.max_N + 3) & ~3, MP = (C.max_M + 3) & ~3;
+    int32_t* X = dyn_lds + (tid / L) * (NP + L + MP);   // [N] species counts
+    uint32_t* stale_w = (uint32_t*)(X + NP);            // [L] stale words
+    uint32_t* nk = stale_w + L;                         // [M] firing counts
+    const rt_cptr<int64_t> unit_start = rt_const(C.unit_start);
+    const int64_t total = unit_start[C.count];
 
     // channel state of this lane's slots
     double T[S], Pk[S], a[S], inv[S];
-    uint32_t n[S];
 #pragma unroll
-    for (int s = 0; s < S; ++s) { T[s] = 0.0; Pk[s] = 0.0; a[s] = 0.0; inv[s] = 0.0; n[s] = 0; }
+    for (int s = 0; s < S; ++s) { T[s] = 0.0; Pk[s] = 0.0; a[s] = 0.0; inv[s] = __builtin_inf(); }
     // trajectory context (identical in every lane of the group)
-    const rt_item_dev* it = C.items;
-    int M = 0, N = 0, rd = 0, mu = 0;
+    rt_cptr<rt_item_dev> it = rt_const(C.items);
+    int M = 0, N = 0, mu = 0;
     int64_t r = 0;
     uint32_t traj = 0, net_id = 0, fired = 0, tie = kTieNone;
     double t = 0.0, t_end = 0.0, s_next = 0.0, delta = 0.0, E = 0.0;
@@ -107,56 +112,54 @@ __global__ __launch_bounds__(kBlock, RT_SUBWAVE_MIN_WAVES) void rt_subwave_kerne
 
     while (__ballot(active) != 0ull) {
         if (!active) continue;
-        const rt_net_dev& net = it->net;
-        uint32_t* const flags_rd = fb + rd * NF;          // set by the pending event
-        uint32_t* const flags_wr = fb + (rd ^ 1) * NF;    // set by this pass's event
+        const rt_cptr<rt_net_dev> net = &it->net;
         // ---- pass over own channels: apply the pending event, refresh, gap
-        double d1 = __builtin_inf(), d2 = __builtin_inf();
-        int kmin = 0x7FFFFFFF, clamped = 0;
+        if (pending) {
+            // every internal clock advances by a_k delta (Eq. 15) ...
 #pragma unroll
-        for (int s = 0; s < S; ++s) {
-            const int k = li + s * L;
-            if (k < M) {
-                if (pending) {
-                    if (k == mu) {
-                        T[s] = Pk[s];
-                        Pk[s] = Pk[s] + E;
-                        n[s] += 1u;
-                    } else {
-                        T[s] = fma(a[s], delta, T[s]);
-                    }
-                    if (flags_rd[k >> 5] & (1u << (k & 31))) {
-                        a[s] = sw_propensity(net.react[k], net.c[k], X);
-                        inv[s] = 1.0 / a[s];
-                    }
+            for (int s = 0; s < S; ++s) T[s] = fma(a[s], delta, T[s]);
+            // ... except the fired one: its firing time, then the next (Eq. 26)
+            if (li == (mu & (L - 1))) {
+                const int sm = mu >> LOG2L;
+#pragma unroll
+                for (int s = 0; s < S; ++s) {
+                    const bool f = s == sm;
+                    T[s] = f ? Pk[s] : T[s];
+                    Pk[s] = f ? Pk[s] + E : Pk[s];
                 }
-                const double raw = (Pk[s] - T[s]) * inv[s];
-                double d = raw < 0.0 ? 0.0 : raw;
-                d = a[s] == 0.0 ? __builtin_inf() : d;
-                const bool lt = d < d1;
-                d2 = lt ? d1 : (d < d2 ? d : d2);
-                d1 = lt ? d : d1;
-                kmin = lt ? k : kmin;
-                clamped = lt ? (raw < 0.0) : clamped;
+            }
+            // the pending event's stale bits for this lane (read and cleared;
+            // the pass then runs with pending = false if it is repeated)
+            unsigned int stale = stale_w[li];
+            stale_w[li] = 0u;
+            pending = false;
+            // refresh one stale slot at a time (rare; keeps the code and the
+            // register footprint of the propensity out of the unrolled pass)
+            while (stale) {
+                const int s1 = __builtin_ctz(stale);
+                stale &= stale - 1u;
+                const int k = li + s1 * L;
+                const double an = sw_propensity(rt_const(net->react)[k], rt_const(net->c)[k], X);
+                const double in = 1.0 / an;
+#pragma unroll
+                for (int s = 0; s < S; ++s) {
+                    a[s] = s == s1 ? an : a[s];
+                    inv[s] = s == s1 ? in : inv[s];
+                }
             }
         }
-        if (pending) {
-            // the pending event is applied (a repeated pass must not apply it
-            // again) and every lane of the group has read its flags
-            for (int q = li; q < NF; q += L) flags_rd[q] = 0u;
-            pending = false;
-        }
-        // ---- argmin across the group's lanes (lowest k wins ties)
+        rt_min2 loc = rt_min2_empty();
 #pragma unroll
-        for (int off = L >> 1; off > 0; off >>= 1) {
-            const double o1 = __shfl_xor(d1, off, 64), o2 = __shfl_xor(d2, off, 64);
-            const int ok_ = __shfl_xor(kmin, off, 64), oc = __shfl_xor(clamped, off, 64);
-            const bool bw = o1 < d1 || (o1 == d1 && ok_ < kmin);
-            d2 = bw ? fmin(o2, d1) : fmin(d2, o1);
-            d1 = bw ? o1 : d1;
-            kmin = bw ? ok_ : kmin;
-            clamped = bw ? oc : clamped;
+        for (int s = 0; s < S; ++s) {
+            const double raw = (Pk[s] - T[s]) * inv[s];
+            const double d = a[s] == 0.0 ? __builtin_inf() : fmax(raw, 0.0);
+            rt_min2_push(loc, d, s);                       // slot now, channel below
         }
+        loc.k = loc.k == 0x7FFFFFFF ? loc.k : li + (loc.k << LOG2L);
+        // ---- argmin across the group's lanes (lowest k wins ties)
+        loc = rt_min2_allreduce<L>(loc);
+        const double d1 = loc.d1, d2 = loc.d2;
+        const int kmin = loc.k;
         const double t_new = t + d1;
         const bool absorbed = d1 == __builtin_inf();
         const bool term = absorbed || t_new > t_end;
@@ -164,18 +167,23 @@ __global__ __launch_bounds__(kBlock, RT_SUBWAVE_MIN_WAVES) void rt_subwave_kerne
         const bool event = live && !term;
         // ---- the jump v_mu, checked against [0, 2^31 - 1] by lanes < |v_mu|
         int nb = 0, ne = 0;
-        if (event) { nb = net.nu_ptr[kmin]; ne = net.nu_ptr[kmin + 1]; }
+        if (event) {
+            const rt_cptr<int32_t> nu_ptr = rt_const(net->nu_ptr);
+            nb = nu_ptr[kmin];
+            ne = nu_ptr[kmin + 1];
+        }
         int32_t xv = 0, xs = 0;
         bool okl = true;
         if (li < ne - nb) {
-            xs = net.nu_sp[nb + li];
-            const int64_t v = (int64_t)X[xs] + net.nu_dl[nb + li];
+            xs = rt_const(net->nu_sp)[nb + li];
+            const int64_t v = (int64_t)X[xs] + rt_const(net->nu_dl)[nb + li];
             okl = v >= 0 && v <= 0x7FFFFFFF;
             xv = (int32_t)v;
         }
         const bool ok = (__ballot(!okl) & gmask) == 0ull;
         const bool near_tie = event && d2 - d1 <= 1e-12 * d1;
-        const bool rare = !live || term || near_tie || clamped || !ok || s_next < t_new;
+        // a zero gap may have been clamped from a negative raw gap
+        const bool rare = !live || term || near_tie || d1 == 0.0 || !ok || s_next < t_new;
         if (__builtin_expect(__ballot(rare) != 0ull, 0)) {
             if (event) {
                 if (near_tie) {
@@ -188,9 +196,16 @@ __global__ __launch_bounds__(kBlock, RT_SUBWAVE_MIN_WAVES) void rt_subwave_kerne
                         for (int j = li; j < N; j += L) dst[j * it->ss_n] = X[j];
                     }
                     ++g;
-                    s_next = g < it->G ? it->s[g] : __builtin_inf();
+                    s_next = g < it->G ? rt_const(it->s)[g] : __builtin_inf();
                 }
-                if (ok && clamped && li == 0) atomicAdd(&ws->clamps, 1ull);
+                if (ok && d1 == 0.0 && li == (kmin & (L - 1))) {
+                    const int sm = kmin >> LOG2L;
+                    bool clamped = false;
+#pragma unroll
+                    for (int s = 0; s < S; ++s)
+                        clamped = s == sm ? (Pk[s] - T[s]) * inv[s] < 0.0 : clamped;
+                    if (clamped) atomicAdd(&ws->clamps, 1ull);
+                }
             }
             const bool stop = !live || term || !ok;
             if (stop && !fresh) {
@@ -211,7 +226,7 @@ __global__ __launch_bounds__(kBlock, RT_SUBWAVE_MIN_WAVES) void rt_subwave_kerne
                     const int k = li + s * L;
                     if (k < M) {
                         if (good) T[s] = fma(a[s], dt, T[s]);
-                        if (it->n_out) it->n_out[r * M + k] = n[s];
+                        if (it->n_out) it->n_out[r * M + k] = nk[k];
                         if (it->T_out) it->T_out[r * M + k] = T[s];
                     }
                 }
@@ -237,9 +252,9 @@ __global__ __launch_bounds__(kBlock, RT_SUBWAVE_MIN_WAVES) void rt_subwave_kerne
                 pending = false;
                 active = (int64_t)u < total;
                 if (active) {
-                    const int item = find_item(C.unit_start, C.count, (int64_t)u);
-                    it = C.items + item;
-                    r = (int64_t)u - C.unit_start[item];
+                    const int item = find_item(unit_start, C.count, (int64_t)u);
+                    it = rt_const(C.items) + item;
+                    r = (int64_t)u - unit_start[item];
                     M = it->net.M;
                     N = it->net.N;
                     t_end = it->t_end;
@@ -247,25 +262,38 @@ __global__ __launch_bounds__(kBlock, RT_SUBWAVE_MIN_WAVES) void rt_subwave_kerne
                     traj = it->traj_offset + (uint32_t)r;
                     const int32_t* x0 = it->x0 + (it->x0_per_traj ? r * N : 0);
                     for (int j = li; j < N; j += L) X[j] = x0[j];
-                    for (int q = li; q < 2 * NF; q += L) fb[q] = 0u;
-                    rd = 0;
+                    for (int k = li; k < M; k += L) nk[k] = 0u;
+                    stale_w[li] = 0u;
                     t = 0.0;
                     g = 0;
-                    s_next = it->G > 0 ? it->s[0] : __builtin_inf();
+                    s_next = it->G > 0 ? rt_const(it->s)[0] : __builtin_inf();
                     fired = 0;
                     tie = kTieNone;
                     hash = kFnvOffset;
                     wave_lds_fence();
 #pragma unroll
                     for (int s = 0; s < S; ++s) {
-                        const int k = li + s * L;
                         T[s] = 0.0;
-                        n[s] = 0;
+                        Pk[s] = 0.0;
+                        a[s] = 0.0;
+                        inv[s] = __builtin_inf();
+                    }
+                    // first internal firing times and propensities, one slot at a time
+#pragma unroll 1
+                    for (int s1 = 0; s1 < S; ++s1) {
+                        const int k = li + s1 * L;
                         if (k < M) {
-                            Pk[s] = rt_exp1_wave(key0, key1, traj, net_id, (uint32_t)k, 0u,
-                                                 &ws->slow_logs, sc);
-                            a[s] = sw_propensity(it->net.react[k], it->net.c[k], X);
-                            inv[s] = 1.0 / a[s];
+                            const double p0 = rt_exp1_wave(key0, key1, traj, net_id, (uint32_t)k,
+                                                           0u, &ws->slow_logs, sc);
+                            const double an = sw_propensity(rt_const(it->net.react)[k],
+                                                            rt_const(it->net.c)[k], X);
+                            const double in = 1.0 / an;
+#pragma unroll
+                            for (int s = 0; s < S; ++s) {
+                                Pk[s] = s == s1 ? p0 : Pk[s];
+                                a[s] = s == s1 ? an : a[s];
+                                inv[s] = s == s1 ? in : inv[s];
+                            }
                         }
                     }
                 }
@@ -276,17 +304,16 @@ __global__ __launch_bounds__(kBlock, RT_SUBWAVE_MIN_WAVES) void rt_subwave_kerne
         mu = kmin;
         if (li < ne - nb) X[xs] = xv;
         {
-            const int db = net.dep_ptr[mu], de = net.dep_ptr[mu + 1];
+            const rt_cptr<int32_t> dep_ptr = rt_const(net->dep_ptr);
+            const int db = dep_ptr[mu], de = dep_ptr[mu + 1];
             for (int q = db + li; q < de; q += L) {
-                const int kk = net.dep_idx[q];
-                atomicOr(&flags_wr[kk >> 5], 1u << (kk & 31));
+                const int kk = rt_const(net->dep_idx)[q];
+                atomicOr(&stale_w[kk & (L - 1)], 1u << (kk >> LOG2L));
             }
         }
-        if (li == (mu % L)) {
-            const int slot = mu / L;
-            uint32_t nm = n[0];
-#pragma unroll
-            for (int s = 1; s < S; ++s) nm = slot == s ? n[s] : nm;
+        if (li == (mu & (L - 1))) {
+            const uint32_t nm = nk[mu];
+            nk[mu] = nm + 1u;
             E = rt_exp1_wave(key0, key1, traj, net_id, (uint32_t)mu, nm + 1u, &ws->slow_logs, sc);
         }
         wave_lds_fence();
@@ -295,7 +322,6 @@ __global__ __launch_bounds__(kBlock, RT_SUBWAVE_MIN_WAVES) void rt_subwave_kerne
         ++fired;
         hash = (hash ^ (unsigned long long)(uint32_t)mu) * kFnvPrime;
         pending = true;
-        rd ^= 1;
         capped = fired >= C.max_firings;
     }
 }
@@ -343,8 +369,8 @@ int rt_launch_subwave(int max_M, const rt_class_dev& C, int L, int grid, hipStre
     const int S = rt_subwave_slots(max_M, L);
     subwave_kernel_t kfn = select_subwave(L, S);
     if (!kfn) return rt_fail(RTSSA_E_UNSUPPORTED, "no sub-wave kernel for this size");
-    const int NP = (C.max_N + 3) & ~3, NF = (C.max_M + 31) >> 5;
-    const size_t lds = (size_t)(kBlock / L) * (NP + 2 * NF) * 4;
+    const int NP = (C.max_N + 3) & ~3, MP = (C.max_M + 3) & ~3;
+    const size_t lds = (size_t)(kBlock / L) * (NP + L + MP) * 4;
     if (lds > 64 * 1024) return rt_fail(RTSSA_E_UNSUPPORTED, "sub-wave LDS too large");
     if (grid <= 0) {
         int dev = 0, cus = 0, per_cu = 0;

@@ -139,17 +139,14 @@ __global__ __launch_bounds__(256, RT_THREAD_MIN_WAVES) void rt_thread_kernel(rt_
             // gaps and argmin (lowest k wins ties; d2 = second smallest gap)
             double d1 = __builtin_inf(), d2 = __builtin_inf();
             int mu = 0;
-            bool clamped = false;
 #pragma unroll
             for (int k = 0; k < MT; ++k) {
                 const double raw = (Pk[k] - T[k]) * inv[k];
-                double d = raw < 0.0 ? 0.0 : raw;
-                d = a[k] == 0.0 ? __builtin_inf() : d;
+                const double d = a[k] == 0.0 ? __builtin_inf() : fmax(raw, 0.0);
                 const bool lt = d < d1;
-                d2 = lt ? d1 : (d < d2 ? d : d2);
-                d1 = lt ? d : d1;
+                d2 = fmin(d2, fmax(d1, d));                // the two smallest of {d1, d2, d}
+                d1 = fmin(d1, d);
                 mu = lt ? k : mu;
-                clamped = lt ? (raw < 0.0) : clamped;
             }
             const double t_new = t + d1;
             const bool absorbed = d1 == __builtin_inf();
@@ -169,7 +166,8 @@ __global__ __launch_bounds__(256, RT_THREAD_MIN_WAVES) void rt_thread_kernel(rt_
             const bool live = !fresh && !capped;          // a trajectory is in progress
             const bool event = live && !term;             // this pass may apply an event
             const bool near_tie = event && d2 - d1 <= 1e-12 * d1;
-            const bool rare = !live || term || near_tie || clamped || !ok || s_next < t_new;
+            // a zero gap may have been clamped from a negative raw gap
+            const bool rare = !live || term || near_tie || d1 == 0.0 || !ok || s_next < t_new;
             if (__builtin_expect(__ballot(rare) != 0ull, 0)) {
                 if (event) {
                     if (near_tie) {
@@ -181,7 +179,13 @@ __global__ __launch_bounds__(256, RT_THREAD_MIN_WAVES) void rt_thread_kernel(rt_
                         ++g;
                         s_next = g < it->G ? it->s[g] : __builtin_inf();
                     }
-                    if (ok && clamped) atomicAdd(&ws->clamps, 1ull);
+                    if (ok && d1 == 0.0) {
+                        bool clamped = false;
+#pragma unroll
+                        for (int k = 0; k < MT; ++k)
+                            clamped = mu == k ? (Pk[k] - T[k]) * inv[k] < 0.0 : clamped;
+                        if (clamped) atomicAdd(&ws->clamps, 1ull);
+                    }
                 }
                 const bool stop = !live || term || !ok;
                 if (stop && !fresh) {

@@ -6,6 +6,26 @@
 
 #include "rt_math.h"
 
+// Read-only launch data (network tables, item descriptors, prefix sums, the
+// sample grid) read through the constant address space: the compiler may
+// then treat the loads as invariant and, where the address is uniform, issue
+// them as scalar loads into SGPRs.  Only for memory that no kernel of the
+// launch writes.  (The host pass of this single-source file only parses the
+// kernels; it sees plain pointers.)
+#if defined(__HIP_DEVICE_COMPILE__)
+template <typename T>
+using rt_cptr = const __attribute__((address_space(4))) T*;
+#else
+template <typename T>
+using rt_cptr = const T*;
+#endif
+
+template <typename T>
+__device__ __forceinline__ rt_cptr<T> rt_const(const T* p)
+{
+    return (rt_cptr<T>)p;
+}
+
 // RN(-ln u) for the wave's active lanes.  The fast phase runs in every lane;
 // lanes whose rounding it cannot certify (about one draw in 2^17) take turns
 // on the wave's LDS slice sc (RT_LOG_SCRATCH words) for the accurate phase

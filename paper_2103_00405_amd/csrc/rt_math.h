@@ -78,6 +78,7 @@ RT_HD void rt_twosum(double a, double b, double& s, double& e)
 RT_HD void rt_fix_rsub_const(uint32_t* p, const uint32_t* c)
 {
     uint64_t borrow = 0;
+    #pragma unroll 1
     for (int i = 0; i < RT_LOG_LIMBS; ++i) {
         uint64_t d = (uint64_t)c[i] - p[i] - borrow;
         p[i] = (uint32_t)d;
@@ -89,6 +90,7 @@ RT_HD void rt_fix_rsub_const(uint32_t* p, const uint32_t* c)
 RT_HD void rt_fix_add_mul_const(uint32_t* p, const uint32_t* c, uint32_t s)
 {
     uint64_t carry = 0;
+    #pragma unroll 1
     for (int i = 0; i < RT_LOG_LIMBS; ++i) {
         uint64_t t = (uint64_t)c[i] * s + p[i] + carry;
         p[i] = (uint32_t)t;
@@ -99,6 +101,7 @@ RT_HD void rt_fix_add_mul_const(uint32_t* p, const uint32_t* c, uint32_t s)
 RT_HD void rt_fix_neg(uint32_t* p)
 {
     uint64_t carry = 1;
+    #pragma unroll 1
     for (int i = 0; i < RT_LOG_LIMBS; ++i) {
         uint64_t t = (uint64_t)(~p[i]) + carry;
         p[i] = (uint32_t)t;
@@ -114,10 +117,13 @@ RT_HD void rt_fix_mul_z(uint32_t* p, int64_t Z, uint32_t* tmp)
     const bool neg = pneg != (Z < 0);
     if (pneg) rt_fix_neg(p);
     const uint64_t az = Z < 0 ? (uint64_t)(-Z) : (uint64_t)Z;
+    #pragma unroll 1
     for (int i = 0; i < RT_LOG_LIMBS + 2; ++i) tmp[i] = 0;
+    #pragma unroll 1
     for (int j = 0; j < 2; ++j) {
         const uint32_t zj = (uint32_t)(az >> (32 * j));
         uint64_t carry = 0;
+        #pragma unroll 1
         for (int i = 0; i < RT_LOG_LIMBS; ++i) {
             uint64_t t = (uint64_t)p[i] * zj + tmp[i + j] + carry;
             tmp[i + j] = (uint32_t)t;
@@ -126,6 +132,7 @@ RT_HD void rt_fix_mul_z(uint32_t* p, int64_t Z, uint32_t* tmp)
         tmp[RT_LOG_LIMBS + j] += (uint32_t)carry;
     }
     // shift right by 61 = 32 + 29 bits
+    #pragma unroll 1
     for (int i = 0; i < RT_LOG_LIMBS; ++i) p[i] = (tmp[i + 1] >> 29) | (tmp[i + 2] << 3);
     if (neg) rt_fix_neg(p);
 }
@@ -134,10 +141,12 @@ RT_HD void rt_fix_mul_z(uint32_t* p, int64_t Z, uint32_t* tmp)
 RT_HD double rt_fix_to_double(const uint32_t* a)
 {
     int top = -1;
+    #pragma unroll 1
     for (int i = RT_LOG_LIMBS - 1; i >= 0 && top < 0; --i)
         if (a[i]) top = 32 * i + (31 - __builtin_clz(a[i]));
     if (top < 0) return 0.0;
     uint64_t mant = 0;
+    #pragma unroll 1
     for (int b = top; b > top - 53; --b) {
         uint32_t bit = b >= 0 ? (a[b >> 5] >> (b & 31)) & 1u : 0u;
         mant = (mant << 1) | bit;
@@ -145,6 +154,7 @@ RT_HD double rt_fix_to_double(const uint32_t* a)
     const int rb = top - 53;                        // rounding bit position
     const uint32_t round_bit = rb >= 0 ? (a[rb >> 5] >> (rb & 31)) & 1u : 0u;
     bool sticky = false;
+    #pragma unroll 1
     for (int b = rb - 1; b >= 0 && !sticky; --b) sticky = ((a[b >> 5] >> (b & 31)) & 1u) != 0;
     if (round_bit && (sticky || (mant & 1u))) mant += 1;
     int expo = top - 52 - RT_LOG_FRAC;              // value = mant * 2^expo
@@ -162,7 +172,9 @@ RT_HD double rt_neglog_accurate(int e, int i, double z, uint32_t* sc)
     // z = Z 2^-61 exactly (|z| <= 2^-8 is a multiple of 2^-61)
     const int64_t Z = (int64_t)(z * 0x1p61);
     // Horner: p = sum_{j=0..KMAX} (-z)^j / (j + 1);  ln(1 + z) = z p
+    #pragma unroll 1
     for (int q = 0; q < RT_LOG_LIMBS; ++q) p[q] = RT_INVK_FIX[RT_LOG_KMAX][q];
+    #pragma unroll 1
     for (int j = RT_LOG_KMAX - 1; j >= 0; --j) {
         rt_fix_mul_z(p, Z, tmp);
         rt_fix_rsub_const(p, RT_INVK_FIX[j]);

@@ -1,0 +1,127 @@
+// rt_wave.h -- argmin with second minimum across the lanes of a wavefront,
+// by VALU lane exchanges only (no LDS crossbar).
+//
+// The selection of Eq. 25 (smallest internal-time gap, lowest channel on
+// ties) runs as an all-reduce over groups of W = 2..64 aligned lanes:
+//   W >= 2   DPP quad_perm [1,0,3,2]     (partner lane ^ 1)
+//   W >= 4   DPP quad_perm [2,3,0,1]     (partner lane ^ 2)
+//   W >= 8   DPP row_half_mirror         (lane i <-> 7 - i in each half row)
+//   W >= 16  DPP row_mirror              (lane i <-> 15 - i in each row)
+//   W >= 32  v_permlane16_swap           (rows 0 <-> 1 and 2 <-> 3)
+//   W == 64  v_permlane32_swap           (lanes 0..31 <-> 32..63)
+// After the first two steps a quad holds one value, after the mirrors a row;
+// the swaps leave every lane with one value from each side of the pair.  The
+// merge is commutative, so every lane of the group ends with the same
+// result.  Every lane of a group must be active.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+// (d1, d2, k): smallest gap, second smallest gap (order statistic with
+// multiplicity) and the channel k of the smallest gap (lowest k on ties).
+// Gaps are never NaN.
+struct rt_min2 {
+    double d1, d2;
+    int32_t k;
+};
+
+__device__ __forceinline__ rt_min2 rt_min2_empty()
+{
+    return rt_min2{__builtin_inf(), __builtin_inf(), 0x7FFFFFFF};
+}
+
+// Adds channel k with gap d to a lane-local minimum; channels must come in
+// increasing k so that the first of equal gaps is kept.
+__device__ __forceinline__ void rt_min2_push(rt_min2& v, double d, int k)
+{
+    const bool lt = d < v.d1;
+    v.d2 = fmin(v.d2, fmax(v.d1, d));
+    v.d1 = fmin(v.d1, d);
+    v.k = lt ? k : v.k;
+}
+
+// The two smallest gaps of the union of two disjoint channel sets.
+__device__ __forceinline__ rt_min2 rt_min2_merge(const rt_min2& a, const rt_min2& b)
+{
+    rt_min2 r;
+    r.d1 = fmin(a.d1, b.d1);
+    r.d2 = fmin(fmin(a.d2, b.d2), fmax(a.d1, b.d1));
+    r.k = a.d1 < b.d1 ? a.k : (b.d1 < a.d1 ? b.k : min(a.k, b.k));
+    return r;
+}
+
+template <int CTRL>
+__device__ __forceinline__ int32_t rt_dpp(int32_t x)
+{
+    return __builtin_amdgcn_mov_dpp(x, CTRL, 0xF, 0xF, false);
+}
+
+template <int CTRL>
+__device__ __forceinline__ double rt_dpp_f64(double x)
+{
+    const int32_t lo = rt_dpp<CTRL>(__double2loint(x));
+    const int32_t hi = rt_dpp<CTRL>(__double2hiint(x));
+    return __hiloint2double(hi, lo);
+}
+
+template <int CTRL>
+__device__ __forceinline__ rt_min2 rt_min2_dpp_step(const rt_min2& v)
+{
+    rt_min2 o;
+    o.d1 = rt_dpp_f64<CTRL>(v.d1);
+    o.d2 = rt_dpp_f64<CTRL>(v.d2);
+    o.k = rt_dpp<CTRL>(v.k);
+    return rt_min2_merge(v, o);
+}
+
+// One swap step: x from both sides of the lane pair.
+template <int ROWS>
+__device__ __forceinline__ void rt_swap(uint32_t x, uint32_t& p, uint32_t& q)
+{
+    if (ROWS == 16) {
+        const auto r = __builtin_amdgcn_permlane16_swap(x, x, false, false);
+        p = r[0];
+        q = r[1];
+    } else {
+        const auto r = __builtin_amdgcn_permlane32_swap(x, x, false, false);
+        p = r[0];
+        q = r[1];
+    }
+}
+
+template <int ROWS>
+__device__ __forceinline__ double rt_swap_f64(double x, double& other)
+{
+    uint32_t plo, qlo, phi, qhi;
+    rt_swap<ROWS>((uint32_t)__double2loint(x), plo, qlo);
+    rt_swap<ROWS>((uint32_t)__double2hiint(x), phi, qhi);
+    other = __hiloint2double((int)qhi, (int)qlo);
+    return __hiloint2double((int)phi, (int)plo);
+}
+
+template <int ROWS>
+__device__ __forceinline__ rt_min2 rt_min2_swap_step(const rt_min2& v)
+{
+    rt_min2 p, q;
+    p.d1 = rt_swap_f64<ROWS>(v.d1, q.d1);
+    p.d2 = rt_swap_f64<ROWS>(v.d2, q.d2);
+    uint32_t pk, qk;
+    rt_swap<ROWS>((uint32_t)v.k, pk, qk);
+    p.k = (int32_t)pk;
+    q.k = (int32_t)qk;
+    return rt_min2_merge(p, q);
+}
+
+// All-reduce over aligned groups of W lanes (W a power of two, 1..64).
+template <int W>
+__device__ __forceinline__ rt_min2 rt_min2_allreduce(rt_min2 v)
+{
+    if (W >= 2) v = rt_min2_dpp_step<0xB1>(v);     // quad_perm [1,0,3,2]
+    if (W >= 4) v = rt_min2_dpp_step<0x4E>(v);     // quad_perm [2,3,0,1]
+    if (W >= 8) v = rt_min2_dpp_step<0x141>(v);    // row_half_mirror
+    if (W >= 16) v = rt_min2_dpp_step<0x140>(v);   // row_mirror
+    if (W >= 32) v = rt_min2_swap_step<16>(v);
+    if (W >= 64) v = rt_min2_swap_step<32>(v);
+    return v;
+}
