@@ -237,7 +237,7 @@ int rtssa_batch_destroy(rtssa_batch* batch);
  * classes by power-of-two channel ranges), time each feasible lane count /
  * workgroup size on a sub-batch of up to `samples` items of the class, run
  * as the batch runs it (one shared persistent grid; outputs not written; at
- * most 1000 firings per trajectory; items with a shared x0 run with more
+ * most 4000 firings per trajectory; items with a shared x0 run with more
  * trajectories so that the sub-batch fills the device), and write the
  * fastest, in firings per second, to the plan file plan_path (text lines
  * "wave|workgroup M_lo M_hi L").  Returns the number of classes tuned (>= 0)

@@ -356,9 +356,9 @@ extern "C" int rtssa_batch_destroy(rtssa_batch* B)
 // from (512, 1024] up.  For each class, every feasible lane count is timed on
 // a sub-batch of up to `samples` of its items, launched the way the batch
 // launches the class (one persistent grid shared by the items, outputs
-// dropped, firings capped at 1000 per trajectory); items with a shared x0
-// get more trajectories so that the sub-batch fills the device (32768
-// trajectories for sub-wavefront classes, 4096 for workgroup classes).  The
+// dropped, firings capped at 4000 per trajectory); items with a shared x0
+// get more trajectories so that the sub-batch fills the device (65536
+// trajectories for sub-wavefront classes, 8192 for workgroup classes).  The
 // fastest in firings per second goes to the plan file.  Returns the number
 // of classes tuned.
 extern "C" int rtssa_autotune(const rtssa_batch_item* items, int32_t count, int32_t samples,
@@ -397,7 +397,7 @@ extern "C" int rtssa_autotune(const rtssa_batch_item* items, int32_t count, int3
         std::vector<rtssa_batch_item> sub;
         // enough trajectories to fill the device at every candidate (a
         // too-small sub-batch measures latency, not throughput)
-        const int64_t fill = b.mapping == RTSSA_MAP_WAVE ? 32768 : 4096;
+        const int64_t fill = b.mapping == RTSSA_MAP_WAVE ? 65536 : 8192;
         const int64_t per_item = (fill + (int64_t)b.members.size() - 1) / (int64_t)b.members.size();
         for (int i : b.members) {
             rtssa_batch_item it = items[i];
@@ -430,7 +430,7 @@ extern "C" int rtssa_autotune(const rtssa_batch_item* items, int32_t count, int3
         for (int L : cands) {
             rtssa_options o{};
             o.mapping = b.mapping;
-            o.max_firings = 1000;
+            o.max_firings = 4000;
             std::vector<plan_entry> p = {{b.mapping, 1, 1 << 30, L}};
             rtssa_batch* tb = nullptr;
             if (batch_create(sub.data(), (int32_t)sub.size(), &o, p, &tb)) continue;

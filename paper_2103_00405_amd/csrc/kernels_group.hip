@@ -242,33 +242,37 @@ __global__ __launch_bounds__(L, group_min_waves(S)) void rt_group_kernel(rt_clas
                 }
                 __syncthreads();
             }
-            // ---- the event: jump (wave 0), dependency flags, fresh draw (owner)
+            // ---- the event: wavefront 0 applies the jump and sets the stale
+            // bits of D(mu); the owner's wavefront draws the fresh Exp(1), all
+            // its lanes alike (a uniform branch, not a one-lane one)
             const int nb = nu_ptr[mu], ne = nu_ptr[mu + 1];
+            const int db = dep_ptr[mu], de = dep_ptr[mu + 1];
+            const int owner_lane = mu & (L - 1);
             if (wave == 0) {
-                int32_t v = 0;
-                bool okl = true;
-                if (lane < ne - nb) {
-                    const int64_t nv = (int64_t)X[nu_sp[nb + lane]] + nu_dl[nb + lane];
-                    okl = nv >= 0 && nv <= 0x7FFFFFFF;
-                    v = (int32_t)nv;
-                }
+                const int cnt = ne - nb, dcnt = de - db;
+                // every lane loads a valid entry (lists have a padding entry),
+                // so all loads issue before the first use
+                const int qs = nb + max(0, min(lane, cnt - 1));
+                const int qd = db + max(0, min(lane, dcnt - 1));
+                const int sp = nu_sp[qs], dl = nu_dl[qs], kk = dep_idx[qd];
+                const int64_t nv = (int64_t)X[sp] + dl;
+                const bool okl = lane >= cnt || (nv >= 0 && nv <= 0x7FFFFFFF);
                 const bool ok = __ballot(!okl) == 0ull;
-                if (ok && lane < ne - nb) X[nu_sp[nb + lane]] = v;
+                if (ok && lane < cnt) X[sp] = (int32_t)nv;
+                if (lane < dcnt) atomicOr(&stale_w[kk & (L - 1)], 1u << (kk >> LOG2L));
+                for (int q = db + 64 + lane; q < de; q += 64) {   // beyond 64 dependents
+                    const int k2 = dep_idx[q];
+                    atomicOr(&stale_w[k2 & (L - 1)], 1u << (k2 >> LOG2L));
+                }
                 if (lane == 0) sh.ok = ok;
             }
-            const int db = dep_ptr[mu], de = dep_ptr[mu + 1];
-            for (int q = db + tid; q < de; q += L) {
-                const int kk = dep_idx[q];
-                atomicOr(&stale_w[kk & (L - 1)], 1u << (kk >> LOG2L));
-            }
-            const bool owner = tid == (mu & (L - 1));
             uint32_t nm = 0;
             bool clamped = false;
-            if (owner) {
+            if (wave == (owner_lane >> 6)) {
                 nm = nk[mu];
-                E = rt_exp1_wave(key0, key1, traj, net_id, (uint32_t)mu, nm + 1u,
-                                 &ws->slow_logs, sc);
-                if (d1 == 0.0) {
+                E = rt_exp1_uniform(key0, key1, traj, net_id, (uint32_t)mu, nm + 1u,
+                                    &ws->slow_logs, sc);
+                if (d1 == 0.0 && tid == owner_lane) {
                     // a zero gap: was it clamped from a negative raw gap?
                     const int sm = mu >> LOG2L;
 #pragma unroll
@@ -278,7 +282,7 @@ __global__ __launch_bounds__(L, group_min_waves(S)) void rt_group_kernel(rt_clas
             }
             __syncthreads();                               // barrier 2
             if (!sh.ok) { st = RTSSA_TRAJ_OVERFLOW; break; }
-            if (owner) {
+            if (tid == owner_lane) {
                 nk[mu] = nm + 1u;
                 if (clamped) atomicAdd(&ws->clamps, 1ull);
             }

@@ -73,9 +73,9 @@ __device__ __forceinline__ int find_item(rt_cptr<int64_t> unit_start, int count,
     return lo;
 }
 
-// Waves per SIMD the register allocation aims at: 8 slots of channel state
-// fit 3, fewer fit 4.
-constexpr int subwave_min_waves(int S) { return S >= 8 ? 3 : 4; }
+// Waves per SIMD the register allocation must allow: 8 slots of channel
+// state fit 3; fewer slots are left to the compiler (they land at 3).
+constexpr int subwave_min_waves(int S) { return S >= 8 ? 3 : 2; }
 
 template <int L, int S>
 __global__ __launch_bounds__(kBlock, subwave_min_waves(S)) void rt_subwave_kernel(rt_class_dev C)

@@ -149,7 +149,10 @@ extern "C" int rtssa_network_create(int32_t N, int32_t M, const int32_t* react_p
         n->max_nu = std::max<int32_t>(n->max_nu, (int32_t)nu[k].size());
     }
     n->nu_ptr[M] = (int)n->nu_sp.size();
-    if (n->nu_sp.empty()) { n->nu_sp.push_back(0); n->nu_dl.push_back(0); }
+    // one padding entry: kernels may load entry nu_ptr[k] (clamped) for a
+    // reaction with an empty list, including the last one
+    n->nu_sp.push_back(0);
+    n->nu_dl.push_back(0);
     // dependency graph
     n->dep_ptr.assign(M + 1, 0);
     for (int k = 0; k < M; ++k) {
@@ -161,7 +164,7 @@ extern "C" int rtssa_network_create(int32_t N, int32_t M, const int32_t* react_p
         n->max_dep = std::max<int32_t>(n->max_dep, (int32_t)d.size());
     }
     n->dep_ptr[M] = (int)n->dep_idx.size();
-    if (n->dep_idx.empty()) n->dep_idx.push_back(0);
+    n->dep_idx.push_back(0);                 // padding entry, as for nu_sp
     // dense net change for small networks
     if (M <= RT_THREAD_MAX_M && N <= RT_THREAD_MAX_N && M > 0 && N > 0) {
         n->nu_dense.assign((size_t)M * N, 0);

@@ -59,9 +59,47 @@ __device__ __forceinline__ double rt_neglog_wave(uint64_t m, bool force_accurate
     return y;
 }
 
+// RN(-ln u) when every active lane holds the same m (a draw computed by a
+// whole wavefront for one channel): the accurate phase, when needed, runs
+// once in the first active lane and its result is broadcast; *slow counts
+// one per draw.
+__device__ __forceinline__ double rt_neglog_uniform(uint64_t m, unsigned long long* slow,
+                                                    uint32_t* sc)
+{
+    int e, i;
+    double z;
+    rt_neglog_reduce(m, e, i, z);
+    double y = 0.0;
+    bool need = m != 0x1FFFFFFFFFFFFFull;                     // u = 1 gives +0
+    if (need) {
+        double yh, yl;
+        rt_neglog_fast(e, i, z, yh, yl);
+        y = yh;
+        need = !rt_rounding_certain(yh, yl);
+    }
+    if (__builtin_expect(__ballot(need) != 0ull, 0)) {
+        const unsigned long long active = __ballot(true);
+        const int first = __ffsll((long long)active) - 1;
+        if ((int)(threadIdx.x & 63u) == first) {
+            y = rt_neglog_accurate(e, i, z, sc);
+            atomicAdd(slow, 1ull);
+        }
+        y = __shfl(y, first, 64);
+    }
+    return y;
+}
+
 __device__ __forceinline__ double rt_exp1_wave(uint32_t k0, uint32_t k1, uint32_t traj,
                                                uint32_t net, uint32_t k, uint32_t n,
                                                unsigned long long* slow, uint32_t* sc)
 {
     return rt_neglog_wave(rt_draw_m53(k0, k1, traj, net, k, n), false, slow, sc);
+}
+
+// E for channel k at firing index n, computed by every active lane alike.
+__device__ __forceinline__ double rt_exp1_uniform(uint32_t k0, uint32_t k1, uint32_t traj,
+                                                  uint32_t net, uint32_t k, uint32_t n,
+                                                  unsigned long long* slow, uint32_t* sc)
+{
+    return rt_neglog_uniform(rt_draw_m53(k0, k1, traj, net, k, n), slow, sc);
 }

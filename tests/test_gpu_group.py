@@ -58,6 +58,13 @@ def _t_end_for(spec, x0, firings):
     (500, 2000, 3, 1024, 9), (1000, 4000, 3, 1024, 10), (8, 8, 3, 1024, 11), (5, 65, 2, 0, 12),
     (6, 12, 2, 4, 13), (20, 60, 2, 8, 14), (30, 100, 2, 16, 15), (60, 200, 2, 32, 16),
     (120, 500, 2, 64, 17), (3, 9, 2, 4, 18),
+    # every workgroup instantiation the autotuner can choose
+    (30, 200, 3, 64, 19), (60, 500, 3, 64, 20), (100, 1000, 3, 64, 21),
+    (200, 900, 3, 128, 22), (250, 1900, 3, 128, 23), (400, 2040, 3, 256, 24),
+    (800, 3500, 3, 256, 25), (700, 3000, 3, 512, 26), (1200, 5000, 3, 1024, 27),
+    # sub-wavefront with 2 and 4 slots per lane
+    (4, 7, 2, 4, 28), (10, 30, 2, 8, 29), (20, 60, 2, 16, 30), (40, 120, 2, 32, 31),
+    (60, 250, 2, 64, 32),
 ])
 def test_random_networks_bit_exact(N, M, mapping, block, seed):
     api = _api()
