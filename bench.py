@@ -44,6 +44,12 @@ def alg_slots_group(M, deps=20):
 
 PEAK_LANE_SLOTS = 256 * 4 * 16 * 2.4e9   # CUs x SIMDs x lanes x clock = 3.93e13 /s
 
+# HBM bytes per launch of rt_thread_kernel<3,2> on the Lotka-Volterra ensemble,
+# from two rocprofv3 counter passes (FETCH_SIZE, WRITE_SIZE) scaled by the same
+# counters on a 1 GiB copy (factors 2.0 and 1.0).  Valid for the kernel as
+# profiled; set to None when the kernel changes until it is measured again.
+LV_TRAFFIC_BYTES_PER_LAUNCH = 5.399e9
+
 
 def parse():
     ap = argparse.ArgumentParser()
@@ -336,7 +342,8 @@ def main():
                    "grid": st["grid"], "parallelism": "trajectories"},
         "roofline": {"bound": "alu", "achieved": achieved / 1e12,
                      "peak": PEAK_LANE_SLOTS / 1e12, "unit": "Tslot/s",
-                     "frac": achieved / PEAK_LANE_SLOTS, "traffic": None,
+                     "frac": achieved / PEAK_LANE_SLOTS, "traffic": LV_TRAFFIC_BYTES_PER_LAUNCH,
+                     "traffic_unit": "B per launch",
                      "kernel": "rt_thread_kernel<3,2>", "kernel_ms": r["kernel_s"] * 1e3,
                      "slots_per_firing": ALG_SLOTS_PER_FIRING_LV},
         "firings_per_step": r["firings_per_step"],

@@ -140,7 +140,8 @@ int rtssa_network_info(const rtssa_network* net, int32_t* N, int32_t* M,
  * Simulate trajectories traj_offset .. traj_offset + R - 1 of the network on
  * the GPU (the whole hot path of section 4, Table 2, in one launch).
  *   x0        device int32 [N] (x0_per_traj = 0) or [R][N] (x0_per_traj = 1);
- *             counts must be >= 0.
+ *             counts must be >= 0 (not checked here: the values stay in
+ *             device memory; negative counts give meaningless propensities).
  *   t_end     finite, >= 0.
  *   sample_t  device float64 [G], non-decreasing, within [0, t_end]
  *             (read once by the host for validation; may be NULL when G = 0).

@@ -98,7 +98,9 @@ def simulate(net: Network, x0, t_end: float, sample_t, R: int, seed: int = 1, ne
     dev = net.device
     N, M, R = net.N, net.M, int(R)
     x0 = torch.as_tensor(np.asarray(x0) if not torch.is_tensor(x0) else x0, dtype=torch.int32)
-    if x0.numel() and int(x0.min()) < 0:
+    if x0.device.type == "cpu" and x0.numel() and int(x0.min()) < 0:
+        # host input is checked before upload; device input is the caller's
+        # (no device reduction or synchronisation per call)
         raise ValueError("initial counts must be >= 0")
     x0 = x0.to(dev).contiguous()
     per_traj = 1 if x0.dim() == 2 else 0
