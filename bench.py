@@ -127,12 +127,57 @@ def run_ensemble(api, w, steps, warmup, block=0, grid=0, mapping=0):
                 firings_per_step=firings / steps)
 
 
-def bench_large(api, W, steps, warmup):
+def oracle_rate(jobs, threads, target_s):
+    """Oracle firings/s on a bounded sample: jobs = [(net, x0, t_end, grid, R,
+    net_id, max_firings)], run in order until about target_s seconds."""
+    import oracle
+    fir, dt, runs = 0, 0.0, 0
+    for net, x0, t_end, grid, R, net_id, maxf in jobs:
+        t0 = time.perf_counter()
+        o = oracle.simulate(net, x0, t_end, grid, 1, R, net_id=net_id, max_firings=maxf,
+                            threads=threads)
+        dt += time.perf_counter() - t0
+        fir += int(o["stats"]["firings"])
+        runs += 1
+        if dt > target_s:
+            break
+    return fir, dt, runs
+
+
+def bench_lv_small(api, W, reps=5):
+    """The small parity case (256 trajectories, about 1.5e6 firings): too few
+    trajectories to fill the device, so it is reported as time per launch."""
+    import torch
+    w = W.lv_small()
+    net = api.Network(w.net)
+    x0 = torch.tensor(w.x0, dtype=torch.int32, device="cuda")
+    s = torch.tensor(w.sample_t, dtype=torch.float64, device="cuda")
+    api.simulate(net, x0, w.t_end, s, w.R, seed=w.seed)
+    kms, fir = [], 0
+    for _ in range(reps):
+        st = api.simulate(net, x0, w.t_end, s, w.R, seed=w.seed)["stats"]
+        kms.append(st["kernel_ms"])
+        fir = st["firings"]
+    return {"workload": "lotka_volterra_small", "trajectories": w.R, "t_end": w.t_end,
+            "grid_points": len(w.sample_t), "firings_per_launch": fir,
+            "kernel_ms": min(kms), "mapping": "thread"}
+
+
+def bench_large(api, W, steps, warmup, cpu_s=0.0):
     w = W.large_random()
     r = run_ensemble(api, w, steps, warmup)
     slots = alg_slots_group(w.net.M)
     ach = slots * r["firings_per_step"] / r["kernel_s"]
+    cpu = None
+    if cpu_s > 0:
+        threads = max(1, min(16, os.cpu_count() or 1))
+        fir, dt, _ = oracle_rate([(w.net, w.x0, w.t_end, w.sample_t, threads, 0, 20000)],
+                                 threads, cpu_s)
+        cpu = {"value": fir / dt, "unit": "firings/s", "cores": threads, "kind": "oracle",
+               "sample": "%d trajectories, first 20000 firings each (%d firings, %.1f s)" % (
+                   threads, fir, dt)}
     return {"workload": "large_random_network", "N": w.net.N, "M": w.net.M, "trajectories": w.R,
+            "cpu_baseline": cpu,
             "t_end": w.t_end, "value": r["firings"] / r["wall"], "unit": "firings/s",
             "ms_per_step": r["wall"] / steps * 1e3, "firings_per_step": r["firings_per_step"],
             "mapping": "workgroup", "block": r["stats"]["block"], "grid": r["stats"]["grid"],
@@ -221,7 +266,7 @@ def bench_gradient(api, W, reps=3):
 BATCH_MAX_FIRINGS = 100_000     # per trajectory; 5x the 2e4 the t_end is set for
 
 
-def bench_batched(api, W, steps=2, n_nets=4096, solo_sample=32, tune_samples=16):
+def bench_batched(api, W, steps=2, n_nets=4096, solo_sample=32, tune_samples=16, cpu_s=0.0):
     """4096 random networks (M log-uniform in [3, 2048], N = M/4, 64
     trajectories each, t_end for about 2e4 firings) in one captured launch per
     size class, lane counts chosen by the autotuner, against one rtssa_simulate
@@ -280,6 +325,16 @@ def bench_batched(api, W, steps=2, n_nets=4096, solo_sample=32, tune_samples=16)
         solo_fir += int(o["n"].to(torch.int64).sum())
     est_ms = solo_ms * n_nets / len(idx)
     per_step = fir / steps
+    cpu = None
+    if cpu_s > 0:
+        threads = max(1, min(16, os.cpu_count() or 1))
+        mix = [idx[q] for q in np.random.default_rng(1).permutation(len(idx))]
+        cfir, cdt, cruns = oracle_rate(
+            [(wl[i].net, wl[i].x0, wl[i].t_end, wl[i].sample_t, threads, wl[i].net_id,
+              BATCH_MAX_FIRINGS) for i in mix], threads, cpu_s)
+        cpu = {"value": cfir / cdt, "unit": "firings/s", "cores": threads, "kind": "oracle",
+               "sample": "%d of the sampled networks, %d trajectories each (%d firings, %.1f s)"
+               % (cruns, threads, cfir, cdt)}
     ms_step = wall / steps * 1e3
     log("batched: per-network launches, %d sampled: %.1f ms -> %.0f ms for all" %
         (len(idx), solo_ms, est_ms))
@@ -293,7 +348,7 @@ def bench_batched(api, W, steps=2, n_nets=4096, solo_sample=32, tune_samples=16)
                                      "sample_firings": solo_fir,
                                      "estimated_ms_for_all": est_ms,
                                      "value": per_step / (est_ms / 1e3), "unit": "firings/s"},
-            "speedup_vs_per_network": est_ms / ms_step}
+            "speedup_vs_per_network": est_ms / ms_step, "cpu_baseline": cpu}
 
 
 def main():
@@ -358,9 +413,11 @@ def main():
         torch.cuda.synchronize()
         res["calibration_copy_bytes"] = nb
     if args.workload == "all":
-        res["secondary"] = {"large_random": bench_large(api, W, 2, 1),
+        cs = 0.0 if args.no_cpu_baseline else 5.0
+        res["secondary"] = {"lv_small": bench_lv_small(api, W),
+                            "large_random": bench_large(api, W, 2, 1, cpu_s=cs),
                             "gradient": bench_gradient(api, W),
-                            "batched": bench_batched(api, W, 2)}
+                            "batched": bench_batched(api, W, 2, cpu_s=cs)}
     if not args.no_cpu_baseline:
         res["cpu_baseline"] = cpu_baseline(w, args.cpu_seconds)
     print(json.dumps(res), flush=True)

@@ -65,6 +65,13 @@ def _configure(L):
                                C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
                                C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
                                C.c_int32, C.POINTER(_Stats)]
+    L.rto_direct_simulate.restype = C.c_int
+    L.rto_direct_simulate.argtypes = [C.POINTER(_Net), C.c_void_p, C.c_int32, C.c_double,
+                                      C.c_void_p, C.c_int32, C.c_uint64, C.c_uint32,
+                                      C.c_uint64, C.c_int64, C.c_uint64,
+                                      C.c_void_p, C.c_void_p, C.c_void_p,
+                                      C.c_void_p, C.c_void_p, C.c_void_p,
+                                      C.c_int32, C.POINTER(_Stats)]
     L.rto_dm_simulate.restype = C.c_int
     L.rto_dm_simulate.argtypes = [C.POINTER(_Net), C.c_void_p, C.c_double, C.c_void_p,
                                   C.c_int32, C.c_uint64, C.c_int64, C.c_uint64,
@@ -147,6 +154,41 @@ def simulate(net, x0, t_end, sample_t, seed, R, net_id=0, traj_offset=0,
                            % (rc, st.hard_cases))
     out["stats"] = dict(firings=st.firings, near_ties=st.near_ties, clamps=st.clamps,
                         status_count=list(st.status_count))
+    return out
+
+
+def direct_simulate(net, x0, t_end, sample_t, seed, R, net_id=0, traj_offset=0,
+                    max_firings=10_000_000, threads=0, _lib=None):
+    """Run R trajectories of Gillespie's direct method with keyed draws (one
+    Philox block per firing); returns a dict of arrays like simulate, without
+    T and tie_step."""
+    N, M = int(net.N), int(net.M)
+    x0 = np.ascontiguousarray(x0, dtype=np.int32)
+    per_traj = 1 if x0.ndim == 2 else 0
+    s = np.ascontiguousarray(sample_t, dtype=np.float64)
+    G = int(s.size)
+    R = int(R)
+    out = dict(
+        samples=np.zeros((R, G, N), dtype=np.int32),
+        n=np.zeros((R, M), dtype=np.uint32),
+        x_final=np.zeros((R, N), dtype=np.int32),
+        t_last=np.zeros(R, dtype=np.float64),
+        status=np.zeros(R, dtype=np.uint8),
+        seq_hash=np.zeros(R, dtype=np.uint64),
+    )
+    ns, keep = _net_struct(net)
+    st = _Stats()
+    rc = (_lib or lib()).rto_direct_simulate(C.byref(ns), _ptr(x0), per_traj, float(t_end),
+                                             _ptr(s), G,
+                                   int(seed), int(net_id), int(traj_offset), R,
+                                   int(max_firings), _ptr(out["samples"]), _ptr(out["n"]),
+                                   _ptr(out["x_final"]), _ptr(out["t_last"]),
+                                   _ptr(out["status"]), _ptr(out["seq_hash"]), int(threads),
+                                   C.byref(st))
+    if rc not in (0,):
+        raise RuntimeError("oracle rto_direct_simulate failed with code %d (hard cases %d)"
+                           % (rc, st.hard_cases))
+    out["stats"] = dict(firings=st.firings, status_count=list(st.status_count))
     return out
 
 

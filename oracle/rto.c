@@ -154,6 +154,7 @@ typedef struct {
     uint8_t* status;
     uint64_t* seq_hash;
     int64_t r_begin, r_end;
+    int32_t method;             /* 0: random time (Table 2), 1: direct method */
     rto_stats stats;
 } job_t;
 
@@ -266,6 +267,85 @@ static void simulate_path(job_t* jb, int64_t r, int32_t* X, double* T, double* P
     jb->stats.status_count[st]++;
 }
 
+/* ------------------------------------------------ the direct method */
+/* Gillespie's direct method, the comparison method of section 3 and of the
+ * discussion (Eq. 17-22): with the total rate a_0 = sum_k a_k (summed in
+ * channel order), the waiting time is an Exp(1) draw divided by a_0 (the
+ * 1/a_0 that Eq. 22 leaves out), and the firing channel is found by searching
+ * the running sums for the first to reach a uniform fraction of a_0.  Both
+ * numbers come from one Philox4x32-10 block per firing, at counter
+ * (firing index, 0xFFFFFFFF, trajectory, net_id): words 1:0 give the waiting
+ * time's u, words 3:2 the search's u, each u = (m + 1) 2^-53 with m the top
+ * 53 bits.  The second counter word is never a channel index of the random
+ * time draws, so the two methods' streams do not overlap. */
+static void simulate_path_direct(job_t* jb, int64_t r, int32_t* X, double* a, uint32_t* n)
+{
+    const rto_network* net = jb->net;
+    const int N = net->N, M = net->M;
+    const uint32_t traj = (uint32_t)(jb->traj_offset + (uint64_t)r);
+    const uint32_t key[2] = { (uint32_t)jb->seed, (uint32_t)(jb->seed >> 32) };
+
+    const int32_t* x0 = jb->x0 + (jb->x0_per_traj ? (size_t)r * N : 0);
+    for (int j = 0; j < N; j++) X[j] = x0[j];
+    for (int k = 0; k < M; k++) n[k] = 0;
+    double t = 0.0;
+    int32_t g = 0;
+    uint64_t fired = 0;
+    uint8_t st = RTO_OK;
+    uint64_t hash = 0xcbf29ce484222325ull;
+
+    for (;;) {
+        double a0 = 0.0;
+        for (int k = 0; k < M; k++) {
+            a[k] = propensity(net, X, k);
+            a0 += a[k];
+        }
+        if (a0 == 0.0) { st = RTO_ABSORBED; break; }
+        uint32_t ctr[4] = { (uint32_t)fired, 0xFFFFFFFFu, traj, jb->net_id };
+        uint32_t w[4];
+        rto_philox4x32_10(ctr, key, w);
+        uint64_t m1 = ((((uint64_t)w[1] << 32) | w[0]) >> 11);
+        uint64_t m2 = ((((uint64_t)w[3] << 32) | w[2]) >> 11);
+        double E = rto_neglog_u53(m1);
+        if (E < 0) jb->stats.hard_cases++;
+        double tau = E / a0;
+        double t_new = t + tau;
+        if (t_new > jb->t_end) break;
+        while (g < jb->G && jb->s[g] < t_new) { write_sample(jb, r, g, X, 0); g++; }
+        /* the first channel whose running sum reaches u a_0 */
+        double target = (double)(m2 + 1) * 0x1p-53 * a0;
+        int mu = M - 1;
+        double run = 0.0;
+        for (int k = 0; k < M; k++) {
+            run += a[k];
+            if (run >= target) { mu = k; break; }
+        }
+        int ok = 1;
+        for (int e = jb->nu_ptr[mu]; e < jb->nu_ptr[mu + 1]; e++) {
+            int64_t v = (int64_t)X[jb->nu_species[e]] + jb->nu_delta[e];
+            if (v < 0 || v > INT32_MAX) ok = 0;
+        }
+        if (!ok) { st = RTO_OVERFLOW; break; }
+        t = t_new;
+        for (int e = jb->nu_ptr[mu]; e < jb->nu_ptr[mu + 1]; e++)
+            X[jb->nu_species[e]] += jb->nu_delta[e];
+        n[mu] += 1;
+        fired += 1;
+        hash = (hash ^ (uint64_t)(uint32_t)mu) * 0x100000001b3ull;
+        if (fired >= jb->max_firings) { st = RTO_MAX_FIRINGS; break; }
+    }
+
+    int bad = !(st == RTO_OK || st == RTO_ABSORBED);
+    while (g < jb->G) { write_sample(jb, r, g, X, bad); g++; }
+    for (int k = 0; k < M; k++) jb->n_out[(size_t)r * M + k] = n[k];
+    for (int j = 0; j < N; j++) jb->x_final[(size_t)r * N + j] = X[j];
+    jb->t_last[r] = t;
+    jb->status[r] = st;
+    jb->seq_hash[r] = hash;
+    jb->stats.firings += fired;
+    jb->stats.status_count[st]++;
+}
+
 static void* run_job(void* arg)
 {
     job_t* jb = (job_t*)arg;
@@ -276,7 +356,10 @@ static void* run_job(void* arg)
     double* a = (double*)malloc(sizeof(double) * (M > 0 ? M : 1));
     double* inv = (double*)malloc(sizeof(double) * (M > 0 ? M : 1));
     uint32_t* n = (uint32_t*)malloc(sizeof(uint32_t) * (M > 0 ? M : 1));
-    for (int64_t r = jb->r_begin; r < jb->r_end; r++) simulate_path(jb, r, X, T, P, a, inv, n);
+    for (int64_t r = jb->r_begin; r < jb->r_end; r++) {
+        if (jb->method == 1) simulate_path_direct(jb, r, X, a, n);
+        else simulate_path(jb, r, X, T, P, a, inv, n);
+    }
     free(X); free(T); free(P); free(a); free(inv); free(n);
     return NULL;
 }
@@ -316,13 +399,13 @@ static int n_threads(int32_t req, int64_t R)
     return (int)nt;
 }
 
-int rto_simulate(const rto_network* net, const int32_t* x0, int32_t x0_per_traj,
-                 double t_end, const double* sample_t, int32_t G,
-                 uint64_t seed, uint32_t net_id, uint64_t traj_offset, int64_t R,
-                 uint64_t max_firings,
-                 int32_t* samples, uint32_t* n_out, double* T_out, int32_t* x_final,
-                 double* t_last, uint8_t* status, uint64_t* seq_hash, uint32_t* tie_step,
-                 int32_t nthreads, rto_stats* stats)
+static int run_all(const rto_network* net, const int32_t* x0, int32_t x0_per_traj,
+                   double t_end, const double* sample_t, int32_t G,
+                   uint64_t seed, uint32_t net_id, uint64_t traj_offset, int64_t R,
+                   uint64_t max_firings,
+                   int32_t* samples, uint32_t* n_out, double* T_out, int32_t* x_final,
+                   double* t_last, uint8_t* status, uint64_t* seq_hash, uint32_t* tie_step,
+                   int32_t nthreads, rto_stats* stats, int32_t method)
 {
     if (!net || net->N < 0 || net->M < 0 || R < 0 || G < 0) return RTO_E_INVALID;
     if (R == 0) { if (stats) memset(stats, 0, sizeof(*stats)); return RTO_SUCCESS; }
@@ -344,6 +427,7 @@ int rto_simulate(const rto_network* net, const int32_t* x0, int32_t x0_per_traj,
         jb->n_out = n_out; jb->tie_step = tie_step; jb->T_out = T_out; jb->t_last = t_last;
         jb->status = status; jb->seq_hash = seq_hash;
         jb->r_begin = R * i / nt; jb->r_end = R * (i + 1) / nt;
+        jb->method = method;
         pthread_create(&th[i], NULL, run_job, jb);
     }
     rto_stats tot;
@@ -359,4 +443,30 @@ int rto_simulate(const rto_network* net, const int32_t* x0, int32_t x0_per_traj,
     if (stats) *stats = tot;
     free(jobs); free(th); free(nu_ptr); free(nu_sp); free(nu_dl);
     return tot.hard_cases ? RTO_E_HARDCASE : RTO_SUCCESS;
+}
+
+int rto_simulate(const rto_network* net, const int32_t* x0, int32_t x0_per_traj,
+                 double t_end, const double* sample_t, int32_t G,
+                 uint64_t seed, uint32_t net_id, uint64_t traj_offset, int64_t R,
+                 uint64_t max_firings,
+                 int32_t* samples, uint32_t* n_out, double* T_out, int32_t* x_final,
+                 double* t_last, uint8_t* status, uint64_t* seq_hash, uint32_t* tie_step,
+                 int32_t nthreads, rto_stats* stats)
+{
+    return run_all(net, x0, x0_per_traj, t_end, sample_t, G, seed, net_id, traj_offset, R,
+                   max_firings, samples, n_out, T_out, x_final, t_last, status, seq_hash,
+                   tie_step, nthreads, stats, 0);
+}
+
+int rto_direct_simulate(const rto_network* net, const int32_t* x0, int32_t x0_per_traj,
+                        double t_end, const double* sample_t, int32_t G,
+                        uint64_t seed, uint32_t net_id, uint64_t traj_offset, int64_t R,
+                        uint64_t max_firings,
+                        int32_t* samples, uint32_t* n_out, int32_t* x_final,
+                        double* t_last, uint8_t* status, uint64_t* seq_hash,
+                        int32_t nthreads, rto_stats* stats)
+{
+    return run_all(net, x0, x0_per_traj, t_end, sample_t, G, seed, net_id, traj_offset, R,
+                   max_firings, samples, n_out, NULL, x_final, t_last, status, seq_hash,
+                   NULL, nthreads, stats, 1);
 }

@@ -63,6 +63,18 @@ int rto_simulate(const rto_network* net, const int32_t* x0, int32_t x0_per_traj,
                  double* t_last, uint8_t* status, uint64_t* seq_hash, uint32_t* tie_step,
                  int32_t nthreads, rto_stats* stats);
 
+/* Gillespie's direct method (section 3, Eq. 17-22) with draws keyed like the
+ * GPU library's direct method: one Philox4x32-10 block per firing at counter
+ * (firing index, 0xFFFFFFFF, traj, net_id).  Same arrays as rto_simulate
+ * without T_out and tie_step (the method has neither). */
+int rto_direct_simulate(const rto_network* net, const int32_t* x0, int32_t x0_per_traj,
+                        double t_end, const double* sample_t, int32_t G,
+                        uint64_t seed, uint32_t net_id, uint64_t traj_offset, int64_t R,
+                        uint64_t max_firings,
+                        int32_t* samples, uint32_t* n_out, int32_t* x_final,
+                        double* t_last, uint8_t* status, uint64_t* seq_hash,
+                        int32_t nthreads, rto_stats* stats);
+
 /* Gillespie direct method with its own SplitMix64 stream: an independent
  * sampler of the same Markov jump law, used only for two-sample law tests. */
 int rto_dm_simulate(const rto_network* net, const int32_t* x0, double t_end,

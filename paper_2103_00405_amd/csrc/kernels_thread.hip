@@ -55,12 +55,19 @@ __device__ __forceinline__ double propensity(int kind, int s0, int s1, double c,
     return c * u64_to_f64(h);
 }
 
-#ifndef RT_THREAD_MIN_WAVES
-#define RT_THREAD_MIN_WAVES 4
-#endif
+// Waves per SIMD each instantiation is compiled for: the most at which its
+// state (X, T, P, a, 1/a, n and the network held in registers) fits without
+// spilling to scratch.
+constexpr int thread_min_waves(int MT, int NT)
+{
+    return (MT <= 2 && NT <= 4) || (MT <= 4 && NT <= 2)                  ? 4
+         : MT <= 3 || (MT == 4 && NT <= 4) || (MT == 6 && NT <= 2)       ? 3
+         : (MT == 8 && NT == 8)                                         ? 1
+                                                                        : 2;
+}
 
 template <int MT, int NT>
-__global__ __launch_bounds__(256, RT_THREAD_MIN_WAVES) void rt_thread_kernel(rt_class_dev C)
+__global__ __launch_bounds__(256, thread_min_waves(MT, NT)) void rt_thread_kernel(rt_class_dev C)
 {
     rt_ws* const ws = C.ws;
     const uint32_t key0 = ws->key0, key1 = ws->key1;

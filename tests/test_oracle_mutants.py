@@ -40,8 +40,22 @@ MUTANTS = {
 }
 
 
+# mistakes in the direct method (Eq. 17-22 with keyed draws)
+DIRECT_MUTANTS = {
+    "dm_waiting_time_not_scaled": ("double tau = E / a0;", "double tau = E;"),
+    "dm_search_target_unscaled": ("double target = (double)(m2 + 1) * 0x1p-53 * a0;",
+                                  "double target = (double)(m2 + 1) * 0x1p-53;"),
+    "dm_one_uniform_for_both": ("uint64_t m2 = ((((uint64_t)w[3] << 32) | w[2]) >> 11);",
+                                "uint64_t m2 = m1;"),
+    "dm_next_channel_fires": ("if (run >= target) { mu = k; break; }",
+                              "if (run >= target) { mu = (k + 1) % M; break; }"),
+    "dm_counter_not_advanced": ("uint32_t ctr[4] = { (uint32_t)fired,",
+                                "uint32_t ctr[4] = { 0u,"),
+}
+
+
 def _build_mutant(tmp, name):
-    old, new = MUTANTS[name]
+    old, new = MUTANTS[name] if name in MUTANTS else DIRECT_MUTANTS[name]
     src = open(os.path.join(ORACLE_DIR, "rto.c")).read()
     assert src.count(old) == 1, name
     for f in ("rto.h", "dm.c"):
@@ -139,3 +153,67 @@ def test_pins_catch_planted_mistake(name):
 
 def test_pins_pass_on_the_real_oracle():
     assert _pin_failures(oracle.lib()) == []
+
+
+def _direct_pin_failures(L):
+    """A quick subset of the direct method's pins (tests/test_oracle_direct.py)
+    against library L; returns the names of the failed pins."""
+    failed = []
+
+    def dm(net, x0, t_end, grid, R, seed=1, **kw):
+        try:
+            return oracle.direct_simulate(net, np.asarray(x0, np.int32), t_end,
+                                          np.asarray(grid, float), seed, R, _lib=L, **kw)
+        except RuntimeError:
+            return None
+
+    k1, k2, T = 50.0, 1.0, 2.0
+    o = dm(W.birth_death(k1, k2), [0], T, [0.5, T], 8000, seed=5)
+    if o is None:
+        failed.append("bd_run")
+    else:
+        for g, t in enumerate((0.5, T)):
+            X = o["samples"][:, g, 0].astype(float)
+            m = k1 / k2 * (1 - math.exp(-k2 * t))
+            if abs(X.mean() - m) > 4.5 * math.sqrt(m / X.size) or \
+                    abs(X.var() - m) > 5 * m * math.sqrt(2.0 / X.size):
+                failed.append("bd_law")
+                break
+    c1, c2, n, t = 1.0, 2.0, 30, 0.4
+    o = dm(W.isomerisation(c1, c2), [n, 0], t, [t], 8000, seed=6)
+    if o is None:
+        failed.append("iso_run")
+    else:
+        p = c2 / (c1 + c2) + (1 - c2 / (c1 + c2)) * math.exp(-(c1 + c2) * t)
+        A = o["x_final"][:, 0].astype(float)
+        if abs(A.mean() - n * p) > 4.5 * math.sqrt(n * p * (1 - p) / A.size):
+            failed.append("iso_binomial")
+    rng = np.random.default_rng(5)
+    net = W.random_network(6, 14, rng)
+    x0 = rng.integers(0, 40, size=6).astype(np.int32)
+    o = dm(net, x0, 0.3, [0.3], 3000, seed=3)
+    if o is None:
+        failed.append("random_run")
+    else:
+        from test_oracle_law import _nu_dense
+        pred = x0[None, :].astype(np.int64) + o["n"].astype(np.int64) @ _nu_dense(net)
+        if not np.array_equal(pred, o["x_final"].astype(np.int64)) or (o["x_final"] < 0).any():
+            failed.append("eq5_identity")
+        r = oracle.simulate(net, x0, 0.3, [0.3], 99, 3000)
+        ps = [stats.ks_2samp(o["x_final"][:, j], r["x_final"][:, j]).pvalue for j in range(6)]
+        if min(ps) * 6 < 1e-4:
+            failed.append("random_time_two_sample")
+    return failed
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("name", sorted(DIRECT_MUTANTS))
+def test_direct_pins_catch_planted_mistake(name):
+    with tempfile.TemporaryDirectory() as tmp:
+        L = _build_mutant(tmp, name)
+        failed = _direct_pin_failures(L)
+    assert failed, "mutant %s passed every pin" % name
+
+
+def test_direct_pins_pass_on_the_real_oracle():
+    assert _direct_pin_failures(oracle.lib()) == []
