@@ -33,8 +33,12 @@ MUTANTS = {
     "time_step_halved": ("double t_new = t + d1;", "double t_new = t + 0.5 * d1;"),
     "argmax_instead_of_argmin": ("if (d < d1) { d2 = d1; d1 = d; mu = k; }",
                                  "if (d1 == INFINITY || d > d1) { d2 = d1; d1 = d; mu = k; }"),
-    "jump_sign_flipped": ("X[jb->nu_species[e]] += jb->nu_delta[e];",
-                          "X[jb->nu_species[e]] -= jb->nu_delta[e];"),
+    "jump_sign_flipped": ("T[mu] = P[mu];\n        t = t_new;\n"
+                          "        for (int e = jb->nu_ptr[mu]; e < jb->nu_ptr[mu + 1]; e++)\n"
+                          "            X[jb->nu_species[e]] += jb->nu_delta[e];",
+                          "T[mu] = P[mu];\n        t = t_new;\n"
+                          "        for (int e = jb->nu_ptr[mu]; e < jb->nu_ptr[mu + 1]; e++)\n"
+                          "            X[jb->nu_species[e]] -= jb->nu_delta[e];"),
     "philox_key_not_bumped": ("if (round > 0) { k0 += W0; k1 += W1; }", "if (round > 0) { k0 += W0; }"),
     "log_of_wrong_argument": ("double u = (double)(m + 1) * 0x1p-53;", "double u = (double)(m + 2) * 0x1p-53;"),
 }
