@@ -58,7 +58,8 @@ def parse():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--trajectories", type=int, default=1 << 20)
     ap.add_argument("--workload", default="all",
-                    choices=["all", "lv_ensemble", "large_random", "gradient", "batched"])
+                    choices=["all", "lv_ensemble", "large_random", "gradient", "batched",
+                             "direct"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--block", type=int, default=0)
@@ -161,6 +162,43 @@ def bench_lv_small(api, W, reps=5):
     return {"workload": "lotka_volterra_small", "trajectories": w.R, "t_end": w.t_end,
             "grid_points": len(w.sample_t), "firings_per_launch": fir,
             "kernel_ms": min(kms), "mapping": "thread"}
+
+
+def bench_direct(api, W, steps=2, warmup=1, R=1 << 20):
+    """Gillespie's direct method (the paper's comparison method, section 3) on
+    the headline Lotka-Volterra ensemble, same outputs except the internal
+    times, thread mapping: firings/s to set beside the random-time method's."""
+    import torch
+    w = W.lv_ensemble(R)
+    dev = torch.device("cuda:0")
+    net = api.Network(w.net, device=dev)
+    N, M, G = w.net.N, w.net.M, len(w.sample_t)
+    out = {"samples": torch.empty((R, G, N), dtype=torch.int32, device=dev),
+           "n": torch.empty((R, M), dtype=torch.int32, device=dev),
+           "x_final": torch.empty((R, N), dtype=torch.int32, device=dev),
+           "status": torch.empty((R,), dtype=torch.uint8, device=dev)}
+    x0 = torch.tensor(w.x0, dtype=torch.int32, device=dev)
+    s = torch.tensor(w.sample_t, dtype=torch.float64, device=dev)
+
+    def step():
+        return api.simulate(net, x0, w.t_end, s, R, seed=w.seed, out=out, want=tuple(out),
+                            method=api.METHOD_DIRECT)["stats"]
+
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    fir, kms = 0, []
+    for i in range(steps):
+        st = step()
+        fir += st["firings"]
+        kms.append(st["kernel_ms"])
+        log("direct method step %d: %.1f ms, %d firings" % (i, st["kernel_ms"], st["firings"]))
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    return {"workload": "lotka_volterra_ensemble", "method": "direct", "trajectories": R,
+            "value": fir / wall, "unit": "firings/s", "ms_per_step": wall / steps * 1e3,
+            "kernel_ms": sum(kms) / len(kms), "firings_per_step": fir / steps}
 
 
 def bench_large(api, W, steps, warmup, cpu_s=0.0):
@@ -362,8 +400,10 @@ def main():
 
     from paper_2103_00405_amd import api, workloads as W
 
-    if args.workload in ("large_random", "gradient", "batched"):
-        if args.workload == "large_random":
+    if args.workload in ("large_random", "gradient", "batched", "direct"):
+        if args.workload == "direct":
+            out = bench_direct(api, W, args.steps, args.warmup)
+        elif args.workload == "large_random":
             out = bench_large(api, W, args.steps, args.warmup)
         elif args.workload == "gradient":
             out = bench_gradient(api, W)
@@ -414,7 +454,10 @@ def main():
         res["calibration_copy_bytes"] = nb
     if args.workload == "all":
         cs = 0.0 if args.no_cpu_baseline else 5.0
+        direct = bench_direct(api, W)
+        direct["vs_random_time"] = direct["value"] / value
         res["secondary"] = {"lv_small": bench_lv_small(api, W),
+                            "direct_method": direct,
                             "large_random": bench_large(api, W, 2, 1, cpu_s=cs),
                             "gradient": bench_gradient(api, W),
                             "batched": bench_batched(api, W, 2, cpu_s=cs)}

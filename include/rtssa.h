@@ -87,12 +87,23 @@ typedef struct {
     int32_t reserved;
 } rtssa_stats;
 
+/* Simulation method.  RANDOM_TIME is the paper's next reaction random time
+ * algorithm (section 4, Table 2), the library's method.  DIRECT is
+ * Gillespie's direct method (section 3, Eq. 17-22), the method the paper
+ * compares against: total rate a_0 = sum_k a_k summed in channel order,
+ * waiting time RN(RN(-ln u1) / a_0), channel = the first whose running sum
+ * reaches RN(u2 a_0); u1 (words 1:0) and u2 (words 3:2) from one
+ * Philox4x32-10 block per firing at counter (firing index, 0xFFFFFFFF,
+ * trajectory, net_id).  DIRECT runs only in the thread mapping (M, N <= 8)
+ * and has no internal times: T_out and tie_step must be NULL. */
+enum { RTSSA_METHOD_RANDOM_TIME = 0, RTSSA_METHOD_DIRECT = 1 };
+
 typedef struct {
     uint64_t max_firings;  /* per trajectory; 0 = 10^7; at most 2^32 - 1 */
     int32_t mapping;       /* RTSSA_MAP_*; 0 = chosen from the network size */
     int32_t block;         /* workgroup size; 0 = the mapping's default */
     int32_t grid;          /* workgroups of the persistent grid; 0 = fill the GPU */
-    int32_t reserved;
+    int32_t method;        /* RTSSA_METHOD_*; 0 = random time */
 } rtssa_options;
 
 /* Message for the last failure on this thread (never NULL). */

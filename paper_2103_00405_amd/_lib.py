@@ -31,7 +31,7 @@ class Stats(C.Structure):
 
 class Options(C.Structure):
     _fields_ = [("max_firings", u64), ("mapping", i32), ("block", i32), ("grid", i32),
-                ("reserved", i32)]
+                ("method", i32)]
 
 
 class BatchItem(C.Structure):

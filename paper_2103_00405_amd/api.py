@@ -16,6 +16,7 @@ from . import _lib
 from ._lib import Options, Stats, check, lib
 
 MAP_AUTO, MAP_THREAD, MAP_WAVE, MAP_WORKGROUP = 0, 1, 2, 3
+METHOD_RANDOM_TIME, METHOD_DIRECT = 0, 1
 TRAJ_OK, TRAJ_ABSORBED, TRAJ_OVERFLOW, TRAJ_MAX_FIRINGS = 0, 1, 2, 3
 TIE_NONE = 0xFFFFFFFF
 
@@ -89,12 +90,18 @@ def simulate(net: Network, x0, t_end: float, sample_t, R: int, seed: int = 1, ne
              traj_offset: int = 0, max_firings: int = 10_000_000, mapping: int = MAP_AUTO,
              block: int = 0, grid: int = 0, want=("samples", "n", "T", "x_final", "t_last",
                                                   "status", "tie_step"),
-             with_hash: bool = False, stats: bool = True, out: Optional[dict] = None):
+             with_hash: bool = False, stats: bool = True, out: Optional[dict] = None,
+             method: int = METHOD_RANDOM_TIME):
     """Run R trajectories on the GPU; returns a dict of device tensors (+ 'stats').
 
     x0 is [N] (shared) or [R, N] (per trajectory), host or device.  sample_t is
     the sorted sample grid within [0, t_end].  ``want`` selects the outputs to
-    produce; ``out`` may supply preallocated tensors with the same keys."""
+    produce; ``out`` may supply preallocated tensors with the same keys.
+    ``method`` = METHOD_DIRECT runs Gillespie's direct method instead (thread
+    mapping only; it has no T or tie_step outputs, which are then dropped from
+    ``want``)."""
+    if method == METHOD_DIRECT:
+        want = tuple(k for k in want if k not in ("T", "tie_step"))
     dev = net.device
     N, M, R = net.N, net.M, int(R)
     x0 = torch.as_tensor(np.asarray(x0) if not torch.is_tensor(x0) else x0, dtype=torch.int32)
@@ -121,7 +128,7 @@ def simulate(net: Network, x0, t_end: float, sample_t, R: int, seed: int = 1, ne
             o[k] = torch.empty(shape, dtype=dt, device=dev)
     smp = o.get("samples")
     st_r, st_g, st_n = (smp.stride() if smp is not None else (0, 0, 0))
-    opt = Options(int(max_firings), int(mapping), int(block), int(grid), 0)
+    opt = Options(int(max_firings), int(mapping), int(block), int(grid), int(method))
     st = Stats()
     with torch.cuda.device(dev):
         check(lib().rtssa_simulate(net.handle, _ptr(x0), per_traj, float(t_end),

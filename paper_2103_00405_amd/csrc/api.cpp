@@ -62,13 +62,15 @@ int rt_pick_lanes(const rtssa_network* net, int requested)
 // workgroup size for the thread mapping.
 int rt_launch_class(int mapping, int max_M, int max_N, int max_nu, const rt_class_dev& C,
                     int block, int grid, int64_t lanes, hipStream_t stream, int* block_used,
-                    int* grid_used)
+                    int* grid_used, int method)
 {
     if (mapping == RTSSA_MAP_THREAD) {
         if (block <= 0) block = 256;
         *block_used = block;
-        return rt_launch_thread(max_M, max_N, C, block, grid, stream, grid_used, lanes);
+        return rt_launch_thread(max_M, max_N, C, block, grid, stream, grid_used, lanes, method);
     }
+    if (method != RTSSA_METHOD_RANDOM_TIME)
+        return rt_fail(RTSSA_E_UNSUPPORTED, "the direct method runs only in the thread mapping");
     if (mapping == RTSSA_MAP_WAVE) {
         int L = block > 0 ? block : rt_subwave_lanes(max_M);
         while (L < 64 && L < max_nu) L <<= 1;
@@ -183,8 +185,21 @@ extern "C" int rtssa_simulate(const rtssa_network* net, const int32_t* x0, int32
     if (stats) memset(stats, 0, sizeof(*stats));
     int rc = rt_check_run(net, x0, x0_per_traj, t_end, sample_t, G, traj_offset, R, stream);
     if (rc) return rc;
+    if (o.method != RTSSA_METHOD_RANDOM_TIME && o.method != RTSSA_METHOD_DIRECT)
+        return rt_fail(RTSSA_E_INVALID, "unknown method");
+    if (o.method == RTSSA_METHOD_DIRECT) {
+        if (T_out || tie_step)
+            return rt_fail(RTSSA_E_INVALID, "the direct method has no internal times or near-ties: "
+                                            "T_out and tie_step must be NULL");
+        if (!rt_thread_supported(net->M, net->N) ||
+            (o.mapping != RTSSA_MAP_AUTO && o.mapping != RTSSA_MAP_THREAD))
+            return rt_fail(RTSSA_E_UNSUPPORTED, "the direct method runs only in the thread mapping "
+                                                "(M, N <= 8)");
+    }
     if (R == 0) return RTSSA_OK;
-    int mapping = o.mapping == RTSSA_MAP_AUTO ? rt_auto_mapping(net) : o.mapping;
+    int mapping = o.method == RTSSA_METHOD_DIRECT
+                      ? RTSSA_MAP_THREAD
+                      : (o.mapping == RTSSA_MAP_AUTO ? rt_auto_mapping(net) : o.mapping);
 
     rt_run_scratch* sc = nullptr;
     rc = check_hip(hipMallocAsync((void**)&sc, sizeof(rt_run_scratch), stream), "scratch allocation");
@@ -215,7 +230,7 @@ extern "C" int rtssa_simulate(const rtssa_network* net, const int32_t* x0, int32
     int grid_used = 0, block_used = 0;
     if (!rc)
         rc = rt_launch_class(mapping, net->M, net->N, net->max_nu, C, o.block, o.grid, R, stream,
-                             &block_used, &grid_used);
+                             &block_used, &grid_used, o.method);
     if (!rc && stats) {
         hipEventRecord(ev1, stream);
         rt_ws h{};

@@ -129,6 +129,8 @@ static int batch_create(const rtssa_batch_item* items, int32_t count, const rtss
     if (opt) o = *opt;
     uint64_t maxf = o.max_firings ? o.max_firings : 10000000ull;
     if (maxf > 0xFFFFFFFFull) return rt_fail(RTSSA_E_INVALID, "max_firings must be < 2^32");
+    if (o.method != RTSSA_METHOD_RANDOM_TIME)
+        return rt_fail(RTSSA_E_UNSUPPORTED, "the batched form runs the random-time method");
     // validate every item (reads each sample grid once)
     for (int i = 0; i < count; ++i) {
         const rtssa_batch_item& b = items[i];

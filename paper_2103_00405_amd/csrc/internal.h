@@ -104,7 +104,7 @@ int rt_auto_mapping(const rtssa_network* net);
 int rt_auto_group_size(int M);
 int rt_launch_class(int mapping, int max_M, int max_N, int max_nu, const rt_class_dev& C,
                     int block, int grid, int64_t lanes, hipStream_t stream, int* block_used,
-                    int* grid_used);
+                    int* grid_used, int method = RTSSA_METHOD_RANDOM_TIME);
 rt_item_dev rt_make_item(const rtssa_network* net, const int32_t* x0, int32_t x0_per_traj,
                          double t_end, const double* sample_t, int32_t G, uint32_t net_id,
                          uint64_t traj_offset, int64_t R, int32_t* samples, int64_t s_stride_r,
@@ -118,8 +118,9 @@ void rt_fill_stats(rtssa_stats* stats, const rt_ws& h);
 int check_hip(hipError_t e, const char* what);
 
 // kernels: launchers take a class descriptor whose pointers are device memory
+// method: RTSSA_METHOD_RANDOM_TIME or RTSSA_METHOD_DIRECT
 int rt_launch_thread(int M, int N, const rt_class_dev& C, int block, int grid,
-                     hipStream_t stream, int* grid_used, int64_t lanes);
+                     hipStream_t stream, int* grid_used, int64_t lanes, int method);
 int rt_launch_setup(rt_ws* ws, unsigned long long* extra, int64_t n_extra, uint32_t key0,
                     uint32_t key1, const uint32_t* key_src, const rt_item_dev* item,
                     rt_item_dev* item_dst, int64_t* unit_start, hipStream_t stream);

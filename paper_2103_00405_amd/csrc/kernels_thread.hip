@@ -10,6 +10,11 @@
 // The step is the next reaction random time algorithm (section 4, Table 2)
 // in the internal-time form of Eq. 14-16: gaps (P_k - T_k)/a_k, argmin
 // (Eq. 25), internal-time advance, jump, and one fresh Exp(1) (Eq. 26).
+// The same kernel also runs Gillespie's direct method (section 3, Eq.
+// 17-22), the method the paper compares against: total rate a_0 = sum a_k,
+// waiting time Exp(1)/a_0 and a search of the running sums for the first to
+// reach u a_0, both numbers from one Philox block per firing at counter
+// (firing index, 0xFFFFFFFF, trajectory, net).
 #include <hip/hip_runtime.h>
 
 #include "internal.h"
@@ -66,7 +71,7 @@ constexpr int thread_min_waves(int MT, int NT)
                                                                         : 2;
 }
 
-template <int MT, int NT>
+template <int MT, int NT, int METHOD>
 __global__ __launch_bounds__(256, thread_min_waves(MT, NT)) void rt_thread_kernel(rt_class_dev C)
 {
     rt_ws* const ws = C.ws;
@@ -146,14 +151,38 @@ __global__ __launch_bounds__(256, thread_min_waves(MT, NT)) void rt_thread_kerne
             // gaps and argmin (lowest k wins ties; d2 = second smallest gap)
             double d1 = __builtin_inf(), d2 = __builtin_inf();
             int mu = 0;
+            if constexpr (METHOD == RTSSA_METHOD_RANDOM_TIME) {
 #pragma unroll
-            for (int k = 0; k < MT; ++k) {
-                const double raw = (Pk[k] - T[k]) * inv[k];
-                const double d = a[k] == 0.0 ? __builtin_inf() : fmax(raw, 0.0);
-                const bool lt = d < d1;
-                d2 = fmin(d2, fmax(d1, d));                // the two smallest of {d1, d2, d}
-                d1 = fmin(d1, d);
-                mu = lt ? k : mu;
+                for (int k = 0; k < MT; ++k) {
+                    const double raw = (Pk[k] - T[k]) * inv[k];
+                    const double d = a[k] == 0.0 ? __builtin_inf() : fmax(raw, 0.0);
+                    const bool lt = d < d1;
+                    d2 = fmin(d2, fmax(d1, d));            // the two smallest of {d1, d2, d}
+                    d1 = fmin(d1, d);
+                    mu = lt ? k : mu;
+                }
+            } else {
+                // direct method: total rate, one block for the waiting time and
+                // the search (padding channels add +0 and are never reached)
+                double a0 = 0.0;
+#pragma unroll
+                for (int k = 0; k < MT; ++k) a0 += a[k];
+                const rt_u4 w = rt_philox4x32_10(rt_u4{fired, 0xFFFFFFFFu, traj, net_id}, key0, key1);
+                const uint64_t m1 = (((uint64_t)w.y << 32) | w.x) >> 11;
+                const uint64_t m2 = (((uint64_t)w.w << 32) | w.z) >> 11;
+                const double E1 = rt_neglog_wave(m1, false, &ws->slow_logs, sc);
+                d1 = a0 == 0.0 ? __builtin_inf() : E1 / a0;
+                const double target = (double)(m2 + 1) * 0x1p-53 * a0;
+                double run = 0.0;
+                bool found = false;
+                mu = MT - 1;
+#pragma unroll
+                for (int k = 0; k < MT; ++k) {
+                    run += a[k];
+                    const bool hit = !found && run >= target;
+                    mu = hit ? k : mu;
+                    found = found || hit;
+                }
             }
             const double t_new = t + d1;
             const bool absorbed = d1 == __builtin_inf();
@@ -172,9 +201,12 @@ __global__ __launch_bounds__(256, thread_min_waves(MT, NT)) void rt_thread_kerne
             }
             const bool live = !fresh && !capped;          // a trajectory is in progress
             const bool event = live && !term;             // this pass may apply an event
-            const bool near_tie = event && d2 - d1 <= 1e-12 * d1;
+            const bool near_tie = METHOD == RTSSA_METHOD_RANDOM_TIME && event &&
+                                  d2 - d1 <= 1e-12 * d1;
             // a zero gap may have been clamped from a negative raw gap
-            const bool rare = !live || term || near_tie || d1 == 0.0 || !ok || s_next < t_new;
+            const bool rare = !live || term || near_tie ||
+                              (METHOD == RTSSA_METHOD_RANDOM_TIME && d1 == 0.0) || !ok ||
+                              s_next < t_new;
             if (__builtin_expect(__ballot(rare) != 0ull, 0)) {
                 if (event) {
                     if (near_tie) {
@@ -186,7 +218,7 @@ __global__ __launch_bounds__(256, thread_min_waves(MT, NT)) void rt_thread_kerne
                         ++g;
                         s_next = g < it->G ? it->s[g] : __builtin_inf();
                     }
-                    if (ok && d1 == 0.0) {
+                    if (METHOD == RTSSA_METHOD_RANDOM_TIME && ok && d1 == 0.0) {
                         bool clamped = false;
 #pragma unroll
                         for (int k = 0; k < MT; ++k)
@@ -203,7 +235,7 @@ __global__ __launch_bounds__(256, thread_min_waves(MT, NT)) void rt_thread_kerne
                     const bool good = st == RTSSA_TRAJ_OK || st == RTSSA_TRAJ_ABSORBED;
                     if (it->samples)
                         for (int32_t gg = g; gg < it->G; ++gg) write_sample(gg, !good);
-                    if (good) {
+                    if (METHOD == RTSSA_METHOD_RANDOM_TIME && good) {
                         const double dt = t_end - t;
 #pragma unroll
                         for (int k = 0; k < MT; ++k) T[k] = fma(a[k], dt, T[k]);
@@ -212,7 +244,7 @@ __global__ __launch_bounds__(256, thread_min_waves(MT, NT)) void rt_thread_kerne
 #pragma unroll
                         for (int k = 0; k < MT; ++k) if (k < M) it->n_out[r * M + k] = n[k];
                     }
-                    if (it->T_out) {
+                    if (METHOD == RTSSA_METHOD_RANDOM_TIME && it->T_out) {
 #pragma unroll
                         for (int k = 0; k < MT; ++k) if (k < M) it->T_out[r * M + k] = T[k];
                     }
@@ -223,7 +255,7 @@ __global__ __launch_bounds__(256, thread_min_waves(MT, NT)) void rt_thread_kerne
                     if (it->t_last) it->t_last[r] = t;
                     if (it->status) it->status[r] = (uint8_t)st;
                     if (it->seq_hash) it->seq_hash[r] = hash;
-                    if (it->tie_step) it->tie_step[r] = tie;
+                    if (METHOD == RTSSA_METHOD_RANDOM_TIME && it->tie_step) it->tie_step[r] = tie;
                     atomicAdd(&ws->firings, (unsigned long long)fired);
                     atomicAdd(&ws->status_count[st], 1ull);
                 }
@@ -247,22 +279,40 @@ __global__ __launch_bounds__(256, thread_min_waves(MT, NT)) void rt_thread_kerne
                         hash = kFnvOffset;
 #pragma unroll
                         for (int k = 0; k < MT; ++k) {
-                            T[k] = 0.0;
                             n[k] = 0;
                             a[k] = propensity<NT>(kind[k], s0[k], s1[k], c[k], X);
-                            inv[k] = 1.0 / a[k];
                         }
-                        // first internal firing times, one draw at a time
-#pragma unroll 1
-                        for (int k = 0; k < MT; ++k) {
-                            const double E0 = rt_exp1_wave(key0, key1, traj, net_id, (uint32_t)k,
-                                                           0u, &ws->slow_logs, sc);
+                        if constexpr (METHOD == RTSSA_METHOD_RANDOM_TIME) {
 #pragma unroll
-                            for (int q = 0; q < MT; ++q) Pk[q] = q == k ? E0 : Pk[q];
+                            for (int k = 0; k < MT; ++k) {
+                                T[k] = 0.0;
+                                inv[k] = 1.0 / a[k];
+                            }
+                            // first internal firing times, one draw at a time
+#pragma unroll 1
+                            for (int k = 0; k < MT; ++k) {
+                                const double E0 = rt_exp1_wave(key0, key1, traj, net_id,
+                                                               (uint32_t)k, 0u, &ws->slow_logs, sc);
+#pragma unroll
+                                for (int q = 0; q < MT; ++q) Pk[q] = q == k ? E0 : Pk[q];
+                            }
                         }
                     }
                 }
                 if (__ballot(stop) != 0ull) continue;   // started lanes compute their first gaps
+            }
+            if constexpr (METHOD == RTSSA_METHOD_DIRECT) {
+#pragma unroll
+                for (int k = 0; k < MT; ++k) n[k] += mu == k ? 1u : 0u;
+#pragma unroll
+                for (int j = 0; j < NT; ++j) X[j] = Xn[j];
+                t = t_new;
+                ++fired;
+                if (want_hash) hash = (hash ^ (unsigned long long)(uint32_t)mu) * kFnvPrime;
+#pragma unroll
+                for (int k = 0; k < MT; ++k) a[k] = propensity<NT>(kind[k], s0[k], s1[k], c[k], X);
+                capped = fired >= C.max_firings;
+                continue;
             }
             // internal times advance by a_k Delta (Eq. 15); the fired channel
             // lands exactly on its firing internal time
@@ -326,9 +376,11 @@ typedef void (*thread_kernel_t)(rt_class_dev);
 
 template <int MT, int NT>
 int launch_mn(const rt_class_dev& C, int block, int grid, hipStream_t stream, int* grid_used,
-              int64_t lanes_wanted)
+              int64_t lanes_wanted, int method)
 {
-    thread_kernel_t kfn = rt_thread_kernel<MT, NT>;
+    thread_kernel_t kfn = method == RTSSA_METHOD_DIRECT
+                              ? rt_thread_kernel<MT, NT, RTSSA_METHOD_DIRECT>
+                              : rt_thread_kernel<MT, NT, RTSSA_METHOD_RANDOM_TIME>;
     if (grid <= 0) {
         int dev = 0, cus = 0, per_cu = 0;
         hipGetDevice(&dev);
@@ -347,12 +399,12 @@ int launch_mn(const rt_class_dev& C, int block, int grid, hipStream_t stream, in
 
 template <int MT>
 int launch_m(int N, const rt_class_dev& C, int block, int grid, hipStream_t stream, int* gu,
-             int64_t lanes)
+             int64_t lanes, int method)
 {
-    if (N <= 1) return launch_mn<MT, 1>(C, block, grid, stream, gu, lanes);
-    if (N <= 2) return launch_mn<MT, 2>(C, block, grid, stream, gu, lanes);
-    if (N <= 4) return launch_mn<MT, 4>(C, block, grid, stream, gu, lanes);
-    return launch_mn<MT, 8>(C, block, grid, stream, gu, lanes);
+    if (N <= 1) return launch_mn<MT, 1>(C, block, grid, stream, gu, lanes, method);
+    if (N <= 2) return launch_mn<MT, 2>(C, block, grid, stream, gu, lanes, method);
+    if (N <= 4) return launch_mn<MT, 4>(C, block, grid, stream, gu, lanes, method);
+    return launch_mn<MT, 8>(C, block, grid, stream, gu, lanes, method);
 }
 
 }  // namespace
@@ -365,7 +417,7 @@ int rt_thread_supported(int M, int N)
 // M and N are the largest of the class (the kernel pads with dead channels
 // and absent species); lanes = trajectories wanted in flight.
 int rt_launch_thread(int M, int N, const rt_class_dev& C, int block, int grid,
-                     hipStream_t stream, int* grid_used, int64_t lanes)
+                     hipStream_t stream, int* grid_used, int64_t lanes, int method)
 {
     if (!rt_thread_supported(M, N))
         return rt_fail(RTSSA_E_UNSUPPORTED, "network too large for the thread mapping");
@@ -374,13 +426,13 @@ int rt_launch_thread(int M, int N, const rt_class_dev& C, int block, int grid,
         return rt_fail(RTSSA_E_INVALID, "thread mapping block must be a multiple of 64, <= 256");
     switch (M) {
         case 0:
-        case 1: return launch_m<1>(N, C, block, grid, stream, grid_used, lanes);
-        case 2: return launch_m<2>(N, C, block, grid, stream, grid_used, lanes);
-        case 3: return launch_m<3>(N, C, block, grid, stream, grid_used, lanes);
-        case 4: return launch_m<4>(N, C, block, grid, stream, grid_used, lanes);
+        case 1: return launch_m<1>(N, C, block, grid, stream, grid_used, lanes, method);
+        case 2: return launch_m<2>(N, C, block, grid, stream, grid_used, lanes, method);
+        case 3: return launch_m<3>(N, C, block, grid, stream, grid_used, lanes, method);
+        case 4: return launch_m<4>(N, C, block, grid, stream, grid_used, lanes, method);
         case 5:
-        case 6: return launch_m<6>(N, C, block, grid, stream, grid_used, lanes);
-        default: return launch_m<8>(N, C, block, grid, stream, grid_used, lanes);
+        case 6: return launch_m<6>(N, C, block, grid, stream, grid_used, lanes, method);
+        default: return launch_m<8>(N, C, block, grid, stream, grid_used, lanes, method);
     }
 }
 
