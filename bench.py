@@ -48,7 +48,7 @@ PEAK_LANE_SLOTS = 256 * 4 * 16 * 2.4e9   # CUs x SIMDs x lanes x clock = 3.93e13
 # from two rocprofv3 counter passes (FETCH_SIZE, WRITE_SIZE) scaled by the same
 # counters on a 1 GiB copy (factors 2.0 and 1.0).  Valid for the kernel as
 # profiled; set to None when the kernel changes until it is measured again.
-LV_TRAFFIC_BYTES_PER_LAUNCH = 5.399e9
+LV_TRAFFIC_BYTES_PER_LAUNCH = 1.326e9
 
 
 def parse():

@@ -32,13 +32,23 @@ __device__ __forceinline__ double u64_to_f64(uint64_t h)
     return fma((double)(uint32_t)(h >> 32), 0x1p32, (double)(uint32_t)h);
 }
 
+// X[j] for a wave-uniform j (a species index of the network): a switch
+// becomes scalar branches, so X stays in registers instead of being copied
+// to scratch memory for an indexed load.
 template <int NT>
 __device__ __forceinline__ int32_t pick(const int32_t (&X)[NT], int j)
 {
-    int32_t v = X[0];
-#pragma unroll
-    for (int q = 1; q < NT; ++q) v = (j == q) ? X[q] : v;
-    return v;
+    switch (j) {
+        case 1: if constexpr (NT > 1) return X[1]; break;
+        case 2: if constexpr (NT > 2) return X[2]; break;
+        case 3: if constexpr (NT > 3) return X[3]; break;
+        case 4: if constexpr (NT > 4) return X[4]; break;
+        case 5: if constexpr (NT > 5) return X[5]; break;
+        case 6: if constexpr (NT > 6) return X[6]; break;
+        case 7: if constexpr (NT > 7) return X[7]; break;
+        default: break;
+    }
+    return X[0];
 }
 
 // h_k(X) of Eq. 2 with the reaction kind fixed per channel (uniform branch).
@@ -60,24 +70,59 @@ __device__ __forceinline__ double propensity(int kind, int s0, int s1, double c,
     return c * u64_to_f64(h);
 }
 
+// Collects one lane's writes to one 64-byte line in its LDS buffer and
+// stores them together when the next write falls in another line (or on
+// flush); only the words the lane wrote are stored.
+struct rt_line_writer {
+    int32_t* buf;       // 16 words of LDS
+    uint64_t line;      // address >> 6 of the buffered line (~0: none)
+    uint32_t mask;      // words written
+
+    __device__ __forceinline__ void flush()
+    {
+        if (mask) {
+            int32_t* const base = (int32_t*)(line << 6);
+#pragma unroll
+            for (int w = 0; w < 16; ++w)
+                if (mask & (1u << w)) base[w] = buf[w];
+            mask = 0u;
+        }
+    }
+
+    __device__ __forceinline__ void put(int32_t* p, int32_t v)
+    {
+        const uint64_t addr = (uint64_t)p;
+        if ((addr >> 6) != line) {
+            flush();
+            line = addr >> 6;
+        }
+        const int w = (int)((addr >> 2) & 15u);
+        buf[w] = v;
+        mask |= 1u << w;
+    }
+};
+
 // Waves per SIMD each instantiation is compiled for: the most at which its
-// state (X, T, P, a, 1/a, n and the network held in registers) fits without
-// spilling to scratch.
-constexpr int thread_min_waves(int MT, int NT)
+// state (X, n, a and, for the random-time method, T, P and 1/a, in registers;
+// the network in SGPRs) fits without spilling to scratch.
+constexpr int thread_min_waves(int MT, int NT, int METHOD)
 {
-    return (MT <= 2 && NT <= 4) || (MT <= 4 && NT <= 2)                  ? 4
-         : MT <= 3 || (MT == 4 && NT <= 4) || (MT == 6 && NT <= 2)       ? 3
-         : (MT == 8 && NT == 8)                                         ? 1
-                                                                        : 2;
+    return METHOD == RTSSA_METHOD_DIRECT || MT <= 4 ? 4 : (MT == 8 && NT == 8 ? 2 : 3);
 }
 
 template <int MT, int NT, int METHOD>
-__global__ __launch_bounds__(256, thread_min_waves(MT, NT)) void rt_thread_kernel(rt_class_dev C)
+__global__ __launch_bounds__(256, thread_min_waves(MT, NT, METHOD)) void rt_thread_kernel(rt_class_dev C)
 {
     rt_ws* const ws = C.ws;
     const uint32_t key0 = ws->key0, key1 = ws->key1;
     __shared__ uint32_t log_scratch[4][RT_LOG_SCRATCH];     // one slice per wave
     uint32_t* sc = log_scratch[threadIdx.x >> 6];
+    // per-lane buffer of one 64-byte line of sample output: a lane's sample
+    // row is written a few bytes at a time, at its own event times; collecting
+    // the words of a line and storing them together lets the L2 write each
+    // line back once instead of once per sample point
+    __shared__ int32_t line_buf[256][16];
+    int32_t* const lb = line_buf[threadIdx.x];
 
     int item = C.exclusive ? -1 : 0;
     bool first = true;
@@ -92,7 +137,9 @@ __global__ __launch_bounds__(256, thread_min_waves(MT, NT)) void rt_thread_kerne
         }
         first = false;
         if (item >= C.count) break;
-        const rt_item_dev* it = C.items + item;
+        // read-only descriptor and network through the constant address space:
+        // with a uniform item the loads are scalar and the constants SGPRs
+        const rt_cptr<rt_item_dev> it = rt_const(C.items) + item;
         const rt_net_dev net = it->net;
         unsigned long long* const traj_ctr = C.item_next + item;
 
@@ -102,17 +149,17 @@ __global__ __launch_bounds__(256, thread_min_waves(MT, NT)) void rt_thread_kerne
 #pragma unroll
         for (int k = 0; k < MT; ++k) {
             if (k < net.M) {
-                int2 rr = net.react[k];
+                int2 rr = rt_const(net.react)[k];
                 kind[k] = (int)((uint32_t)rr.x >> 29);
                 s0[k] = rr.x & RT_SPECIES_MASK;
                 s1[k] = rr.y;
-                c[k] = net.c[k];
+                c[k] = rt_const(net.c)[k];
             } else {
                 kind[k] = RT_H_ZERO; s0[k] = 0; s1[k] = 0; c[k] = 0.0;   // dead padding channel
             }
 #pragma unroll
             for (int j = 0; j < NT; ++j)
-                nu[k][j] = (k < net.M && j < net.N) ? net.nu_dense[k * net.N + j] : 0;
+                nu[k][j] = (k < net.M && j < net.N) ? rt_const(net.nu_dense)[k * net.N + j] : 0;
         }
         const int N = net.N, M = net.M;
         const double t_end = it->t_end;
@@ -133,11 +180,12 @@ __global__ __launch_bounds__(256, thread_min_waves(MT, NT)) void rt_thread_kerne
         unsigned long long hash = kFnvOffset;
         int64_t r = 0;
 
+        rt_line_writer lw{lb, ~0ull, 0u};
         auto write_sample = [&](int32_t gg, bool invalid) {
             int32_t* dst = it->samples + r * it->ss_r + (int64_t)gg * it->ss_g;
 #pragma unroll
             for (int j = 0; j < NT; ++j)
-                if (j < N) dst[j * it->ss_n] = invalid ? -1 : X[j];
+                if (j < N) lw.put(dst + j * it->ss_n, invalid ? -1 : X[j]);
         };
 
         // Each pass is one firing of every active lane.  The common path is
@@ -233,8 +281,10 @@ __global__ __launch_bounds__(256, thread_min_waves(MT, NT)) void rt_thread_kerne
                                           : (absorbed ? RTSSA_TRAJ_ABSORBED
                                                       : (term ? RTSSA_TRAJ_OK : RTSSA_TRAJ_OVERFLOW));
                     const bool good = st == RTSSA_TRAJ_OK || st == RTSSA_TRAJ_ABSORBED;
-                    if (it->samples)
+                    if (it->samples) {
                         for (int32_t gg = g; gg < it->G; ++gg) write_sample(gg, !good);
+                        lw.flush();
+                    }
                     if (METHOD == RTSSA_METHOD_RANDOM_TIME && good) {
                         const double dt = t_end - t;
 #pragma unroll
