@@ -65,6 +65,14 @@ def _configure(L):
                                C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
                                C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
                                C.c_int32, C.POINTER(_Stats)]
+    L.rto_simulate_schedule.restype = C.c_int
+    L.rto_simulate_schedule.argtypes = [C.POINTER(_Net), C.c_void_p, C.c_int32, C.c_double,
+                                        C.c_void_p, C.c_int32, C.c_uint64, C.c_uint32,
+                                        C.c_uint64, C.c_int64, C.c_uint64,
+                                        C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
+                                        C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
+                                        C.c_int32, C.POINTER(_Stats),
+                                        C.c_int32, C.c_void_p, C.c_void_p]
     L.rto_direct_simulate.restype = C.c_int
     L.rto_direct_simulate.argtypes = [C.POINTER(_Net), C.c_void_p, C.c_int32, C.c_double,
                                       C.c_void_p, C.c_int32, C.c_uint64, C.c_uint32,
@@ -122,8 +130,10 @@ def neglog_u53(m):
 
 
 def simulate(net, x0, t_end, sample_t, seed, R, net_id=0, traj_offset=0,
-             max_firings=10_000_000, threads=0, _lib=None):
-    """Run R trajectories of the random-time algorithm; returns a dict of arrays."""
+             max_firings=10_000_000, threads=0, _lib=None, schedule=None):
+    """Run R trajectories of the random-time algorithm; returns a dict of arrays.
+    schedule = (times [B], rates [B][M]) gives piecewise-constant rates: the
+    network's c before times[0], rates[i] from times[i] on."""
     N, M = int(net.N), int(net.M)
     x0 = np.ascontiguousarray(x0, dtype=np.int32)
     per_traj = 1 if x0.ndim == 2 else 0
@@ -143,12 +153,17 @@ def simulate(net, x0, t_end, sample_t, seed, R, net_id=0, traj_offset=0,
     ns, keep = _net_struct(net)
     st = _Stats()
     L = _lib or lib()
-    rc = L.rto_simulate(C.byref(ns), _ptr(x0), per_traj, float(t_end), _ptr(s), G,
-                        int(seed), int(net_id), int(traj_offset), R, int(max_firings),
-                        _ptr(out["samples"]), _ptr(out["n"]), _ptr(out["T"]),
-                        _ptr(out["x_final"]), _ptr(out["t_last"]), _ptr(out["status"]),
-                        _ptr(out["seq_hash"]), _ptr(out["tie_step"]), int(threads),
-                        C.byref(st))
+    args = (C.byref(ns), _ptr(x0), per_traj, float(t_end), _ptr(s), G,
+            int(seed), int(net_id), int(traj_offset), R, int(max_firings),
+            _ptr(out["samples"]), _ptr(out["n"]), _ptr(out["T"]),
+            _ptr(out["x_final"]), _ptr(out["t_last"]), _ptr(out["status"]),
+            _ptr(out["seq_hash"]), _ptr(out["tie_step"]), int(threads), C.byref(st))
+    if schedule is None:
+        rc = L.rto_simulate(*args)
+    else:
+        times = np.ascontiguousarray(schedule[0], dtype=np.float64)
+        rates = np.ascontiguousarray(schedule[1], dtype=np.float64).reshape(times.size, M)
+        rc = L.rto_simulate_schedule(*args, int(times.size), _ptr(times), _ptr(rates))
     if rc not in (0,):
         raise RuntimeError("oracle rto_simulate failed with code %d (hard cases %d)"
                            % (rc, st.hard_cases))

@@ -124,13 +124,19 @@ static int64_t choose(int64_t x, int32_t s)
 }
 
 /* a_k = c_k * h_k(X), h_k = prod over reactant entries of C(X_j, sigma_j)
- * (Eq. 1-2); the product has at most two factors (molecularity <= 2). */
-static double propensity(const rto_network* net, const int32_t* X, int k)
+ * (Eq. 1-2); the product has at most two factors (molecularity <= 2).
+ * c is the rate constant in force (the network's, or a schedule piece's). */
+static double propensity_c(const rto_network* net, const int32_t* X, int k, double c)
 {
     int64_t h = 1;
     for (int e = net->react_ptr[k]; e < net->react_ptr[k + 1]; e++)
         h *= choose(X[net->react_species[e]], net->react_sigma[e]);
-    return net->c[k] * (double)h;
+    return c * (double)h;
+}
+
+static double propensity(const rto_network* net, const int32_t* X, int k)
+{
+    return propensity_c(net, X, k, net->c[k]);
 }
 
 /* ------------------------------------------------------------ one path */
@@ -155,6 +161,9 @@ typedef struct {
     uint64_t* seq_hash;
     int64_t r_begin, r_end;
     int32_t method;             /* 0: random time (Table 2), 1: direct method */
+    int32_t B;                  /* rate breakpoints (0: constant rates) */
+    const double* sched_t;      /* [B] breakpoint times */
+    const double* sched_c;      /* [B][M] rates from each breakpoint on */
     rto_stats stats;
 } job_t;
 
@@ -177,12 +186,17 @@ static void simulate_path(job_t* jb, int64_t r, int32_t* X, double* T, double* P
     const int32_t* x0 = jb->x0 + (jb->x0_per_traj ? (size_t)r * N : 0);
     for (int j = 0; j < N; j++) X[j] = x0[j];
     double t = 0.0;
+    /* piecewise-constant rates: the network's c before the first breakpoint,
+     * row i of sched_c from breakpoint i on */
+    const double* crate = net->c;
+    int32_t piece = 0;
+    double b_next = jb->B > 0 ? jb->sched_t[0] : INFINITY;
     for (int k = 0; k < M; k++) {
         T[k] = 0.0;
         n[k] = 0;
         P[k] = rto_exp1(seed, traj, nid, (uint32_t)k, 0);
         if (P[k] < 0) jb->stats.hard_cases++;
-        a[k] = propensity(net, X, k);
+        a[k] = propensity_c(net, X, k, crate[k]);
         inv[k] = a[k] > 0 ? 1.0 / a[k] : 0.0;
     }
     int32_t g = 0;
@@ -207,8 +221,25 @@ static void simulate_path(job_t* jb, int64_t r, int32_t* X, double* T, double* P
             if (d < d1) { d2 = d1; d1 = d; mu = k; }
             else if (d < d2) { d2 = d; }
         }
-        if (d1 == INFINITY) { st = RTO_ABSORBED; break; }
         double t_new = t + d1;
+        /* Eq. 28 with piecewise-constant c_k(t): when the next firing would
+         * fall after a rate breakpoint (before t_end), every internal clock
+         * runs to the breakpoint at the old rates, the propensities take the
+         * new rates, and the gaps are solved again from there */
+        if (b_next < jb->t_end && t_new > b_next) {
+            double db = b_next - t;
+            for (int k = 0; k < M; k++) T[k] = fma(a[k], db, T[k]);
+            t = b_next;
+            crate = jb->sched_c + (size_t)piece * M;
+            piece += 1;
+            b_next = piece < jb->B ? jb->sched_t[piece] : INFINITY;
+            for (int k = 0; k < M; k++) {
+                a[k] = propensity_c(net, X, k, crate[k]);
+                inv[k] = a[k] > 0 ? 1.0 / a[k] : 0.0;
+            }
+            continue;
+        }
+        if (d1 == INFINITY) { st = RTO_ABSORBED; break; }
         if (t_new > jb->t_end) break;
         if (d2 - d1 <= 1e-12 * d1) {
             jb->stats.near_ties++;
@@ -240,7 +271,7 @@ static void simulate_path(job_t* jb, int64_t r, int32_t* X, double* T, double* P
         /* a_k is a pure function of X: recomputing every channel equals
          * recomputing only the channels that read a changed species */
         for (int k = 0; k < M; k++) {
-            a[k] = propensity(net, X, k);
+            a[k] = propensity_c(net, X, k, crate[k]);
             inv[k] = a[k] > 0 ? 1.0 / a[k] : 0.0;
         }
         if (fired >= jb->max_firings) { st = RTO_MAX_FIRINGS; break; }
@@ -405,7 +436,8 @@ static int run_all(const rto_network* net, const int32_t* x0, int32_t x0_per_tra
                    uint64_t max_firings,
                    int32_t* samples, uint32_t* n_out, double* T_out, int32_t* x_final,
                    double* t_last, uint8_t* status, uint64_t* seq_hash, uint32_t* tie_step,
-                   int32_t nthreads, rto_stats* stats, int32_t method)
+                   int32_t nthreads, rto_stats* stats, int32_t method, int32_t B,
+                   const double* sched_t, const double* sched_c)
 {
     if (!net || net->N < 0 || net->M < 0 || R < 0 || G < 0) return RTO_E_INVALID;
     if (R == 0) { if (stats) memset(stats, 0, sizeof(*stats)); return RTO_SUCCESS; }
@@ -428,6 +460,7 @@ static int run_all(const rto_network* net, const int32_t* x0, int32_t x0_per_tra
         jb->status = status; jb->seq_hash = seq_hash;
         jb->r_begin = R * i / nt; jb->r_end = R * (i + 1) / nt;
         jb->method = method;
+        jb->B = B; jb->sched_t = sched_t; jb->sched_c = sched_c;
         pthread_create(&th[i], NULL, run_job, jb);
     }
     rto_stats tot;
@@ -455,7 +488,25 @@ int rto_simulate(const rto_network* net, const int32_t* x0, int32_t x0_per_traj,
 {
     return run_all(net, x0, x0_per_traj, t_end, sample_t, G, seed, net_id, traj_offset, R,
                    max_firings, samples, n_out, T_out, x_final, t_last, status, seq_hash,
-                   tie_step, nthreads, stats, 0);
+                   tie_step, nthreads, stats, 0, 0, NULL, NULL);
+}
+
+int rto_simulate_schedule(const rto_network* net, const int32_t* x0, int32_t x0_per_traj,
+                          double t_end, const double* sample_t, int32_t G,
+                          uint64_t seed, uint32_t net_id, uint64_t traj_offset, int64_t R,
+                          uint64_t max_firings,
+                          int32_t* samples, uint32_t* n_out, double* T_out, int32_t* x_final,
+                          double* t_last, uint8_t* status, uint64_t* seq_hash,
+                          uint32_t* tie_step, int32_t nthreads, rto_stats* stats,
+                          int32_t B, const double* sched_t, const double* sched_c)
+{
+    if (B < 0 || (B > 0 && (!sched_t || !sched_c))) return RTO_E_INVALID;
+    for (int32_t i = 0; i < B; i++)
+        if (!(sched_t[i] > (i ? sched_t[i - 1] : 0.0)) || !isfinite(sched_t[i]))
+            return RTO_E_INVALID;
+    return run_all(net, x0, x0_per_traj, t_end, sample_t, G, seed, net_id, traj_offset, R,
+                   max_firings, samples, n_out, T_out, x_final, t_last, status, seq_hash,
+                   tie_step, nthreads, stats, 0, B, sched_t, sched_c);
 }
 
 int rto_direct_simulate(const rto_network* net, const int32_t* x0, int32_t x0_per_traj,
@@ -468,5 +519,5 @@ int rto_direct_simulate(const rto_network* net, const int32_t* x0, int32_t x0_pe
 {
     return run_all(net, x0, x0_per_traj, t_end, sample_t, G, seed, net_id, traj_offset, R,
                    max_firings, samples, n_out, NULL, x_final, t_last, status, seq_hash,
-                   NULL, nthreads, stats, 1);
+                   NULL, nthreads, stats, 1, 0, NULL, NULL);
 }

@@ -28,8 +28,10 @@ MUTANTS = {
     "wrong_half_of_block": ("uint64_t word = (n & 1u) ?", "uint64_t word = (n & 0u) ?"),
     "final_clock_not_advanced": ("for (int k = 0; k < M; k++) T[k] = fma(a[k], dt, T[k]);",
                                  "for (int k = 0; k < M; k++) T[k] = T[k];"),
-    "rate_of_next_channel": ("return net->c[k] * (double)h;",
-                             "return net->c[(k + 1) % net->M] * (double)h;"),
+    "rate_of_next_channel": ("changed species */\n        for (int k = 0; k < M; k++) {\n"
+                             "            a[k] = propensity_c(net, X, k, crate[k]);",
+                             "changed species */\n        for (int k = 0; k < M; k++) {\n"
+                             "            a[k] = propensity_c(net, X, k, crate[(k + 1) % M]);"),
     "time_step_halved": ("double t_new = t + d1;", "double t_new = t + 0.5 * d1;"),
     "argmax_instead_of_argmin": ("if (d < d1) { d2 = d1; d1 = d; mu = k; }",
                                  "if (d1 == INFINITY || d > d1) { d2 = d1; d1 = d; mu = k; }"),
@@ -58,8 +60,19 @@ DIRECT_MUTANTS = {
 }
 
 
+# mistakes in the piecewise-constant rate schedule (Eq. 28 solved piece by piece)
+SCHEDULE_MUTANTS = {
+    "sched_clock_not_run_to_breakpoint": ("for (int k = 0; k < M; k++) T[k] = fma(a[k], db, T[k]);",
+                                          "for (int k = 0; k < M; k++) T[k] = T[k];"),
+    "sched_rates_one_piece_late": ("crate = jb->sched_c + (size_t)piece * M;",
+                                   "crate = piece ? jb->sched_c + (size_t)(piece - 1) * M : net->c;"),
+    "sched_time_not_moved": ("            t = b_next;\n            crate",
+                             "            crate"),
+}
+
+
 def _build_mutant(tmp, name):
-    old, new = MUTANTS[name] if name in MUTANTS else DIRECT_MUTANTS[name]
+    old, new = (MUTANTS.get(name) or DIRECT_MUTANTS.get(name) or SCHEDULE_MUTANTS[name])
     src = open(os.path.join(ORACLE_DIR, "rto.c")).read()
     assert src.count(old) == 1, name
     for f in ("rto.h", "dm.c"):
@@ -221,3 +234,43 @@ def test_direct_pins_catch_planted_mistake(name):
 
 def test_direct_pins_pass_on_the_real_oracle():
     assert _direct_pin_failures(oracle.lib()) == []
+
+
+def _schedule_pin_failures(L):
+    """A quick subset of the schedule pins (tests/test_oracle_schedule.py)."""
+    failed = []
+    try:
+        o = oracle.simulate(W.pure_birth(10.0), [0], 3.0, [0.5, 1.5, 2.5, 3.0], 1, 8000,
+                            schedule=([1.0, 2.0], [[0.0], [30.0]]), _lib=L)
+        for g, m in enumerate((5.0, 10.0, 25.0, 40.0)):
+            X = o["samples"][:, g, 0].astype(float)
+            if abs(X.mean() - m) > 4.5 * math.sqrt(m / X.size):
+                failed.append("birth_law")
+                break
+        if not np.allclose(o["T"][:, 0], 40.0, rtol=1e-13):
+            failed.append("birth_clock")
+        o = oracle.simulate(W.birth_death(50.0, 1.0), [0], 3.0, [1.5, 3.0], 2, 8000,
+                            schedule=([1.0], [[10.0, 1.0]]), _lib=L)
+        m1 = 50.0 * (1 - math.exp(-1.0))
+        for g, t in enumerate((1.5, 3.0)):
+            m = 10.0 + (m1 - 10.0) * math.exp(-(t - 1.0))
+            X = o["samples"][:, g, 0].astype(float)
+            if abs(X.mean() - m) > 4.5 * math.sqrt(m / X.size):
+                failed.append("bd_switch_law")
+                break
+    except RuntimeError:
+        failed.append("run")
+    return failed
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("name", sorted(SCHEDULE_MUTANTS))
+def test_schedule_pins_catch_planted_mistake(name):
+    with tempfile.TemporaryDirectory() as tmp:
+        L = _build_mutant(tmp, name)
+        failed = _schedule_pin_failures(L)
+    assert failed, "mutant %s passed every pin" % name
+
+
+def test_schedule_pins_pass_on_the_real_oracle():
+    assert _schedule_pin_failures(oracle.lib()) == []
