@@ -147,6 +147,22 @@ int rtssa_network_set_rates(rtssa_network* net, const double* c);
 int rtssa_network_info(const rtssa_network* net, int32_t* N, int32_t* M,
                        int64_t* dep_edges, int32_t* auto_mapping);
 
+/* Piecewise-constant rate constants (the time-dependent rates of the paper's
+ * discussion, Eq. 28, solved piece by piece): the network's c applies on
+ * [0, times[0]), rates[i*M .. i*M+M-1] from times[i] on.  times: B finite
+ * values, > 0, strictly increasing; rates: B x M values, each 0 or within
+ * [1e-280, 1e280].  Host arrays, copied.  B = 0 removes the schedule.  When
+ * the next firing would fall after a breakpoint (before t_end), every
+ * internal time runs to the breakpoint at the old rates
+ * (T_k = fma(a_k, b - t, T_k)), t becomes the breakpoint and every a_k and
+ * 1/a_k is recomputed with the new rates; no firing, no sample.  A network
+ * with a schedule runs with the random-time method in every mapping, not in
+ * the direct method (E_UNSUPPORTED).  Call it only while no launch using
+ * the network is in flight; while a batch holds the network it fails
+ * with E_INVALID (the batch keeps the schedule's device address). */
+int rtssa_network_set_schedule(rtssa_network* net, int32_t B, const double* times,
+                               const double* rates);
+
 /*
  * Simulate trajectories traj_offset .. traj_offset + R - 1 of the network on
  * the GPU (the whole hot path of section 4, Table 2, in one launch).
@@ -201,8 +217,10 @@ int rtssa_score_grad(const double* f, const uint32_t* n, const double* T, int64_
  * kernel mapping (thread, sub-wavefront lanes per trajectory, workgroup
  * size; taken from the plan file written by rtssa_autotune when plan_path
  * names one, else from the network size), copies their descriptors to the
- * device and owns them; the caller keeps every input and output buffer alive
- * and unchanged in address until rtssa_batch_destroy.  rtssa_batch_run runs
+ * device and owns them; the caller keeps every network, input and output
+ * buffer alive and unchanged in address until rtssa_batch_destroy (new rate
+ * constants from rtssa_network_set_rates are seen by later runs; a rate
+ * schedule cannot be changed meanwhile).  rtssa_batch_run runs
  * every item: with use_graph = 1 the first run captures a hipGraph (one
  * persistent kernel per class on parallel branches) and later runs replay
  * it; with 0 the kernels are enqueued directly.  The results equal those of

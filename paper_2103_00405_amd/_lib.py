@@ -48,6 +48,7 @@ SIGNATURES = {
     "rtssa_network_create": (C.c_int, [i32, i32, vp, vp, vp, vp, vp, vp, vp, C.POINTER(vp)]),
     "rtssa_network_destroy": (C.c_int, [vp]),
     "rtssa_network_set_rates": (C.c_int, [vp, vp]),
+    "rtssa_network_set_schedule": (C.c_int, [vp, i32, vp, vp]),
     "rtssa_network_info": (C.c_int, [vp, vp, vp, vp, vp]),
     "rtssa_simulate": (C.c_int, [vp, vp, i32, f64, vp, i32, u64, u32, u64, i64, vp, i64, i64,
                                  i64, vp, vp, vp, vp, vp, vp, vp, C.POINTER(Options), vp,

@@ -57,6 +57,7 @@ class Network:
             check(lib().rtssa_network_create(self.N, self.M, *[a.ctypes.data for a in arrs],
                                              c.ctypes.data, C.byref(self._h)))
         self.c = c[: self.M].copy()
+        self.schedule = None
 
     def set_rates(self, c):
         c = np.ascontiguousarray(c, dtype=np.float64)
@@ -65,6 +66,21 @@ class Network:
         with torch.cuda.device(self.device):
             check(lib().rtssa_network_set_rates(self._h, c.ctypes.data))
         self.c = c.copy()
+
+    def set_schedule(self, times=None, rates=None):
+        """Piecewise-constant rates (Eq. 28 solved piece by piece): the
+        network's c before times[0], rates[i] ([M]) from times[i] on.  Call
+        with no arguments (or an empty ``times``) to remove the schedule."""
+        t = np.ascontiguousarray([] if times is None else times, dtype=np.float64).ravel()
+        B = int(t.size)
+        r = np.ascontiguousarray(np.zeros((0, self.M)) if rates is None else rates,
+                                 dtype=np.float64)
+        if r.shape != (B, self.M):
+            raise ValueError("rates must be [%d, %d], got %s" % (B, self.M, r.shape))
+        with torch.cuda.device(self.device):
+            check(lib().rtssa_network_set_schedule(self._h, B, t.ctypes.data if B else None,
+                                                   r.ctypes.data if B else None))
+        self.schedule = (t.copy(), r.copy()) if B else None
 
     def info(self):
         N, M, mp = C.c_int32(), C.c_int32(), C.c_int32()
@@ -269,14 +285,19 @@ class Batch:
                             trajectories=r.value, max_M=mm.value))
         return out
 
-    def __del__(self):
+    def close(self):
+        """Release the batch's device descriptors, streams and graph (its
+        networks may then take a new rate schedule)."""
         h = getattr(self, "_h", None)
-        try:
-            if h and _lib._lib is not None:
-                _lib._lib.rtssa_batch_destroy(h)
-        except Exception:
-            pass
         self._h = None
+        if h and _lib._lib is not None:
+            _lib._lib.rtssa_batch_destroy(h)
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:      # interpreter shutdown: module globals may be gone
+            pass
 
 
 def autotune(batch_jobs_items, plan_path, samples=16):

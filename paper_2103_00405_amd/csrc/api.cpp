@@ -188,6 +188,8 @@ extern "C" int rtssa_simulate(const rtssa_network* net, const int32_t* x0, int32
     if (o.method != RTSSA_METHOD_RANDOM_TIME && o.method != RTSSA_METHOD_DIRECT)
         return rt_fail(RTSSA_E_INVALID, "unknown method");
     if (o.method == RTSSA_METHOD_DIRECT) {
+        if (net->dev.sched_B > 0)
+            return rt_fail(RTSSA_E_UNSUPPORTED, "rate schedules run with the random-time method");
         if (T_out || tie_step)
             return rt_fail(RTSSA_E_INVALID, "the direct method has no internal times or near-ties: "
                                             "T_out and tie_step must be NULL");
@@ -218,6 +220,7 @@ extern "C" int rtssa_simulate(const rtssa_network* net, const int32_t* x0, int32
     C.max_N = net->N;
     C.max_M = net->M;
     C.max_firings = (uint32_t)maxf;
+    C.has_schedule = net->dev.sched_B > 0;
 
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     if (stats) {

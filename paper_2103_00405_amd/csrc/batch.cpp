@@ -107,6 +107,7 @@ struct rtssa_batch {
     hipEvent_t fork = nullptr;
     std::vector<hipEvent_t> joins;
     int device = -1;
+    bool holds_nets = false;       // batch_refs of the items' networks taken
 };
 
 static int batch_create(const rtssa_batch_item* items, int32_t count, const rtssa_options* opt,
@@ -214,6 +215,8 @@ static int batch_create(const rtssa_batch_item* items, int32_t count, const rtss
         c.dev.max_N = c.max_N;
         c.dev.max_M = c.max_M;
         c.dev.max_firings = (uint32_t)maxf;
+        c.dev.has_schedule = 0;
+        for (int i : c.members) c.dev.has_schedule |= items[i].net->dev.sched_B > 0;
         if (!rc && ci > 0)
             rc = check_hip(hipStreamCreateWithFlags(&c.side, hipStreamNonBlocking), "stream");
     }
@@ -227,6 +230,10 @@ static int batch_create(const rtssa_batch_item* items, int32_t count, const rtss
         rtssa_batch_destroy(B);
         return rc;
     }
+    // the items' descriptors hold each network's device pointers: its
+    // schedule must not be reallocated while this batch exists
+    for (const auto& it : B->items) ++const_cast<rtssa_network*>(it.net)->batch_refs;
+    B->holds_nets = true;
     *out = B;
     return RTSSA_OK;
 }
@@ -340,6 +347,8 @@ extern "C" int rtssa_batch_info(const rtssa_batch* B, int32_t cls, int32_t* mapp
 extern "C" int rtssa_batch_destroy(rtssa_batch* B)
 {
     if (!B) return RTSSA_OK;
+    if (B->holds_nets)
+        for (const auto& it : B->items) --const_cast<rtssa_network*>(it.net)->batch_refs;
     if (B->exec) hipGraphExecDestroy(B->exec);
     if (B->graph) hipGraphDestroy(B->graph);
     for (auto& c : B->classes)

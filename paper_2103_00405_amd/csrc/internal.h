@@ -32,6 +32,11 @@ struct rt_net_dev {
     const int32_t* dep_ptr;  // [M+1] dependency graph D(mu)
     const int32_t* dep_idx;
     const int32_t* nu_dense; // [M][N], only for networks of the thread mapping
+    // piecewise-constant rates: c applies on [0, sched_t[0]); row i of
+    // sched_c ([B][M]) from sched_t[i] on (sched_B = 0: constant rates)
+    int32_t sched_B;
+    const double* sched_t;
+    const double* sched_c;
 };
 
 struct rtssa_network {
@@ -43,6 +48,8 @@ struct rtssa_network {
     int32_t max_dep = 0;     // largest |D(mu)|
     int device = -1;
     void* dev_block = nullptr;  // one allocation holding every device table
+    void* sched_block = nullptr;  // device copy of the rate schedule (times, rates)
+    int32_t batch_refs = 0;       // batch items holding this network's device pointers
     rt_net_dev dev{};
 };
 
@@ -95,7 +102,7 @@ struct rt_class_dev {
     int32_t max_N;
     int32_t max_M;
     uint32_t max_firings;
-    int32_t pad;
+    int32_t has_schedule;   // some item's network has a rate schedule
 };
 
 // error reporting and mapping choice (api.cpp)

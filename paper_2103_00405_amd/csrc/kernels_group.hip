@@ -21,6 +21,10 @@
 //          Gibson & Bruck's dependency graph cited in section 5) set stale
 //          bits; the owner of mu draws the fresh Exp(1) (barrier 2) and
 //          counts the firing in n_mu.
+// With piecewise-constant rates (Eq. 28), a next firing that would fall past
+// the next rate breakpoint b instead runs every clock to b at the old rates
+// (a pending event with no fired channel) and marks every slot stale, so the
+// next pass takes the new rates; the branch is uniform over the workgroup.
 #include <hip/hip_runtime.h>
 
 #include "internal.h"
@@ -76,11 +80,14 @@ __device__ __forceinline__ int group_find_item(rt_cptr<int64_t> unit_start, int 
 }
 
 // Waves per SIMD the register allocation aims at: 16 slots of channel state
-// fit 2, 8 fit 3, fewer fit 4.
-constexpr int group_min_waves(int S) { return S >= 16 ? 2 : (S >= 8 ? 3 : 4); }
+// fit 2, 8 fit 3 (2 with a rate schedule's state), fewer fit 4.
+constexpr int group_min_waves(int S, bool SCHED)
+{
+    return S >= 16 || (SCHED && S >= 8) ? 2 : (S >= 8 ? 3 : 4);
+}
 
-template <int L, int S>
-__global__ __launch_bounds__(L, group_min_waves(S)) void rt_group_kernel(rt_class_dev C)
+template <int L, int S, bool SCHED>
+__global__ __launch_bounds__(L, group_min_waves(S, SCHED)) void rt_group_kernel(rt_class_dev C)
 {
     constexpr int W = L / 64;
     constexpr int LOG2L = __builtin_ctz(L);
@@ -131,6 +138,12 @@ __global__ __launch_bounds__(L, group_min_waves(S)) void rt_group_kernel(rt_clas
         const uint32_t traj = it->traj_offset + (uint32_t)r;
         const uint32_t net_id = it->net_id;
         const double t_end = it->t_end;
+        // rates in force: the network's c before the first breakpoint, row
+        // i of the schedule from breakpoint i on
+        const int32_t sB = SCHED ? net.sched_B : 0;
+        rt_cptr<double> crate = cc;
+        int32_t piece = 0;
+        double b_next = sB > 0 ? rt_const(net.sched_t)[0] : __builtin_inf();
         const int32_t* x0 = it->x0 + (it->x0_per_traj ? r * N : 0);
         for (int j = tid; j < N; j += L) X[j] = x0[j];
         for (int k = tid; k < M; k += L) nk[k] = 0u;
@@ -172,8 +185,8 @@ __global__ __launch_bounds__(L, group_min_waves(S)) void rt_group_kernel(rt_clas
 #pragma unroll
                 for (int s = 0; s < S; ++s) T[s] = fma(a[s], delta, T[s]);
                 // ... except the fired one, which is set to its firing time and
-                // gets its next one (Eq. 26)
-                if (tid == (mu & (L - 1))) {
+                // gets its next one (Eq. 26); mu < 0 after a rate breakpoint
+                if ((!SCHED || mu >= 0) && tid == (mu & (L - 1))) {
                     const int sm = mu >> LOG2L;
 #pragma unroll
                     for (int s = 0; s < S; ++s) {
@@ -192,7 +205,7 @@ __global__ __launch_bounds__(L, group_min_waves(S)) void rt_group_kernel(rt_clas
                     const int s1 = __builtin_ctz(stale);
                     stale &= stale - 1u;
                     const int k = tid + s1 * L;
-                    const double an = group_propensity(react[k], cc[k], X);
+                    const double an = group_propensity(react[k], crate[k], X);
                     const double in = 1.0 / an;
 #pragma unroll
                     for (int s = 0; s < S; ++s) {
@@ -224,6 +237,25 @@ __global__ __launch_bounds__(L, group_min_waves(S)) void rt_group_kernel(rt_clas
             const double d1 = loc.d1, d2 = loc.d2;
             mu = __builtin_amdgcn_readfirstlane(loc.k);
             const double t_new = t + d1;
+            // (the test is uniform; readfirstlane keeps the schedule state scalar)
+            if (SCHED && __builtin_amdgcn_readfirstlane(b_next < t_end && t_new > b_next)) {
+                // the next firing would come after a rate breakpoint: the
+                // clocks run to it at the old rates, then every propensity
+                // takes the new ones and the gaps are solved again (Eq. 28)
+                delta = b_next - t;
+                t = b_next;
+                crate = rt_const(net.sched_c) + (size_t)piece * M;
+                ++piece;
+                b_next = piece < sB ? rt_const(net.sched_t)[piece] : __builtin_inf();
+                uint32_t all = 0u;
+#pragma unroll
+                for (int s = 0; s < S; ++s) all |= tid + s * L < M ? 1u << s : 0u;
+                stale_w[tid] = all;
+                mu = -1;
+                pending = true;
+                __syncthreads();                           // wave_min is rewritten next
+                continue;
+            }
             if (d1 == __builtin_inf()) { st = RTSSA_TRAJ_ABSORBED; break; }
             if (t_new > t_end) { st = RTSSA_TRAJ_OK; break; }
             if (d2 - d1 <= 1e-12 * d1) {
@@ -329,11 +361,14 @@ __global__ __launch_bounds__(L, group_min_waves(S)) void rt_group_kernel(rt_clas
 typedef void (*group_kernel_t)(rt_class_dev);
 
 template <int L, int S>
-group_kernel_t pick_kernel() { return rt_group_kernel<L, S>; }
-
-group_kernel_t select_group(int L, int S)
+group_kernel_t pick_kernel(bool sched)
 {
-#define RT_CASE(l, s) if (L == l && S == s) return pick_kernel<l, s>();
+    return sched ? rt_group_kernel<L, S, true> : rt_group_kernel<L, S, false>;
+}
+
+group_kernel_t select_group(int L, int S, bool sched)
+{
+#define RT_CASE(l, s) if (L == l && S == s) return pick_kernel<l, s>(sched);
     RT_CASE(64, 1) RT_CASE(64, 2) RT_CASE(64, 4) RT_CASE(64, 8) RT_CASE(64, 16)
     RT_CASE(256, 1) RT_CASE(256, 2) RT_CASE(256, 4) RT_CASE(256, 8) RT_CASE(256, 16)
     RT_CASE(128, 4) RT_CASE(128, 8) RT_CASE(128, 16)
@@ -360,14 +395,14 @@ int rt_group_slots(int M, int L)
 
 bool rt_group_supported(int M, int L)
 {
-    return M >= 1 && select_group(L, rt_group_slots(M, L)) != nullptr;
+    return M >= 1 && select_group(L, rt_group_slots(M, L), false) != nullptr;
 }
 
 int rt_launch_group(int M, int max_N, int max_M, const rt_class_dev& C, int L, int grid,
                     hipStream_t stream, int* grid_used)
 {
     const int S = rt_group_slots(M, L);
-    group_kernel_t kfn = select_group(L, S);
+    group_kernel_t kfn = select_group(L, S, C.has_schedule != 0);
     if (!kfn) return rt_fail(RTSSA_E_UNSUPPORTED, "no group kernel for this network size and L");
     const size_t lds = rt_group_lds_bytes(max_N, max_M, L);
     if (lds > 96 * 1024) return rt_fail(RTSSA_E_UNSUPPORTED, "network too large for LDS");

@@ -17,6 +17,10 @@
 // counter by one lane per group; every rare event (start or end of a
 // trajectory, a sample point, a near-tie, a clamped gap, an overflow, the
 // firing cap) is handled in a branch entered only when some group needs it.
+// With piecewise-constant rates (SCHED, Eq. 28), a rate breakpoint passed by
+// a group's next firing is one more such event: the group's clocks run to the
+// breakpoint at the old rates (a pending event with no fired channel) and
+// every slot turns stale, so the next pass takes the new rates.
 #include <hip/hip_runtime.h>
 
 #include "internal.h"
@@ -74,11 +78,12 @@ __device__ __forceinline__ int find_item(rt_cptr<int64_t> unit_start, int count,
 }
 
 // Waves per SIMD the register allocation must allow: 8 slots of channel
-// state fit 3; fewer slots are left to the compiler (they land at 3).
-constexpr int subwave_min_waves(int S) { return S >= 8 ? 3 : 2; }
+// state fit 3 (2 with a rate schedule's state); fewer slots are left to the
+// compiler (they land at 3).
+constexpr int subwave_min_waves(int S, bool SCHED) { return S >= 8 && !SCHED ? 3 : 2; }
 
-template <int L, int S>
-__global__ __launch_bounds__(kBlock, subwave_min_waves(S)) void rt_subwave_kernel(rt_class_dev C)
+template <int L, int S, bool SCHED>
+__global__ __launch_bounds__(kBlock, subwave_min_waves(S, SCHED)) void rt_subwave_kernel(rt_class_dev C)
 {
     constexpr unsigned long long kGroupBits = L == 64 ? ~0ull : ((1ull << L) - 1ull);
     rt_ws* const ws = C.ws;
@@ -109,6 +114,9 @@ __global__ __launch_bounds__(kBlock, subwave_min_waves(S)) void rt_subwave_kerne
     int32_t g = 0;
     unsigned long long hash = kFnvOffset;
     bool active = true, fresh = true, capped = false, pending = false;
+    // rate schedule: breakpoints passed, and the next one
+    int32_t piece = 0;
+    double b_next = __builtin_inf();
 
     while (__ballot(active) != 0ull) {
         if (!active) continue;
@@ -118,8 +126,9 @@ __global__ __launch_bounds__(kBlock, subwave_min_waves(S)) void rt_subwave_kerne
             // every internal clock advances by a_k delta (Eq. 15) ...
 #pragma unroll
             for (int s = 0; s < S; ++s) T[s] = fma(a[s], delta, T[s]);
-            // ... except the fired one: its firing time, then the next (Eq. 26)
-            if (li == (mu & (L - 1))) {
+            // ... except the fired one: its firing time, then the next (Eq. 26);
+            // mu < 0 after a rate breakpoint
+            if ((!SCHED || mu >= 0) && li == (mu & (L - 1))) {
                 const int sm = mu >> LOG2L;
 #pragma unroll
                 for (int s = 0; s < S; ++s) {
@@ -133,13 +142,18 @@ __global__ __launch_bounds__(kBlock, subwave_min_waves(S)) void rt_subwave_kerne
             unsigned int stale = stale_w[li];
             stale_w[li] = 0u;
             pending = false;
+            // rates in force: c before the first breakpoint, row i of the
+            // schedule from breakpoint i on
+            const rt_cptr<double> crate =
+                SCHED && piece > 0 ? rt_const(net->sched_c) + (size_t)(piece - 1) * M
+                                   : rt_const(net->c);
             // refresh one stale slot at a time (rare; keeps the code and the
             // register footprint of the propensity out of the unrolled pass)
             while (stale) {
                 const int s1 = __builtin_ctz(stale);
                 stale &= stale - 1u;
                 const int k = li + s1 * L;
-                const double an = sw_propensity(rt_const(net->react)[k], rt_const(net->c)[k], X);
+                const double an = sw_propensity(rt_const(net->react)[k], crate[k], X);
                 const double in = 1.0 / an;
 #pragma unroll
                 for (int s = 0; s < S; ++s) {
@@ -162,9 +176,11 @@ __global__ __launch_bounds__(kBlock, subwave_min_waves(S)) void rt_subwave_kerne
         const int kmin = loc.k;
         const double t_new = t + d1;
         const bool absorbed = d1 == __builtin_inf();
-        const bool term = absorbed || t_new > t_end;
         const bool live = !fresh && !capped;
-        const bool event = live && !term;
+        // the next firing would come after a rate breakpoint (Eq. 28)
+        const bool brk = SCHED && live && b_next < t_end && t_new > b_next;
+        const bool term = !brk && (absorbed || t_new > t_end);
+        const bool event = live && !term && !brk;
         // ---- the jump v_mu, checked against [0, 2^31 - 1] by lanes < |v_mu|
         int nb = 0, ne = 0;
         if (event) {
@@ -183,7 +199,8 @@ __global__ __launch_bounds__(kBlock, subwave_min_waves(S)) void rt_subwave_kerne
         const bool ok = (__ballot(!okl) & gmask) == 0ull;
         const bool near_tie = event && d2 - d1 <= 1e-12 * d1;
         // a zero gap may have been clamped from a negative raw gap
-        const bool rare = !live || term || near_tie || d1 == 0.0 || !ok || s_next < t_new;
+        const bool rare =
+            !live || term || near_tie || d1 == 0.0 || !ok || s_next < t_new || brk;
         if (__builtin_expect(__ballot(rare) != 0ull, 0)) {
             if (event) {
                 if (near_tie) {
@@ -267,6 +284,9 @@ __global__ __launch_bounds__(kBlock, subwave_min_waves(S)) void rt_subwave_kerne
                     t = 0.0;
                     g = 0;
                     s_next = it->G > 0 ? rt_const(it->s)[0] : __builtin_inf();
+                    piece = 0;
+                    b_next = SCHED && it->net.sched_B > 0 ? rt_const(it->net.sched_t)[0]
+                                                          : __builtin_inf();
                     fired = 0;
                     tie = kTieNone;
                     hash = kFnvOffset;
@@ -298,7 +318,24 @@ __global__ __launch_bounds__(kBlock, subwave_min_waves(S)) void rt_subwave_kerne
                     }
                 }
             }
-            if (__ballot(stop) != 0ull) continue;         // started groups compute first gaps
+            if (SCHED && brk) {
+                // the clocks run to the breakpoint at the old rates, then
+                // every propensity takes the new ones
+                delta = b_next - t;
+                t = b_next;
+                ++piece;
+                b_next = piece < net->sched_B ? rt_const(net->sched_t)[piece]
+                                              : __builtin_inf();
+                uint32_t all = 0u;
+#pragma unroll
+                for (int s = 0; s < S; ++s) all |= li + s * L < M ? 1u << s : 0u;
+                stale_w[li] = all;
+                mu = -1;
+                pending = true;
+            }
+            // started groups compute first gaps, groups past a breakpoint
+            // solve again; the others repeat their (idempotent) pass
+            if (__ballot(stop || brk) != 0ull) continue;
         }
         // ---- the event: jump, dependency flags, fresh draw by the owner lane
         mu = kmin;
@@ -329,11 +366,14 @@ __global__ __launch_bounds__(kBlock, subwave_min_waves(S)) void rt_subwave_kerne
 typedef void (*subwave_kernel_t)(rt_class_dev);
 
 template <int L, int S>
-subwave_kernel_t sw_pick() { return rt_subwave_kernel<L, S>; }
-
-subwave_kernel_t select_subwave(int L, int S)
+subwave_kernel_t sw_pick(bool sched)
 {
-#define RT_CASE(l, s) if (L == l && S == s) return sw_pick<l, s>();
+    return sched ? rt_subwave_kernel<L, S, true> : rt_subwave_kernel<L, S, false>;
+}
+
+subwave_kernel_t select_subwave(int L, int S, bool sched)
+{
+#define RT_CASE(l, s) if (L == l && S == s) return sw_pick<l, s>(sched);
     RT_CASE(4, 2) RT_CASE(4, 4) RT_CASE(4, 8)
     RT_CASE(8, 4) RT_CASE(8, 8)
     RT_CASE(16, 4) RT_CASE(16, 8)
@@ -367,7 +407,7 @@ int rt_launch_subwave(int max_M, const rt_class_dev& C, int L, int grid, hipStre
                       int* grid_used)
 {
     const int S = rt_subwave_slots(max_M, L);
-    subwave_kernel_t kfn = select_subwave(L, S);
+    subwave_kernel_t kfn = select_subwave(L, S, C.has_schedule != 0);
     if (!kfn) return rt_fail(RTSSA_E_UNSUPPORTED, "no sub-wave kernel for this size");
     const int NP = (C.max_N + 3) & ~3, MP = (C.max_M + 3) & ~3;
     const size_t lds = (size_t)(kBlock / L) * (NP + L + MP) * 4;

@@ -104,14 +104,20 @@ struct rt_line_writer {
 
 // Waves per SIMD each instantiation is compiled for: the most at which its
 // state (X, n, a and, for the random-time method, T, P and 1/a, in registers;
-// the network in SGPRs) fits without spilling to scratch.
-constexpr int thread_min_waves(int MT, int NT, int METHOD)
+// the network in SGPRs; with a rate schedule, the lane's rates too) fits
+// without spilling to scratch.
+constexpr int thread_min_waves(int MT, int NT, int METHOD, bool SCHED)
 {
-    return METHOD == RTSSA_METHOD_DIRECT || MT <= 4 ? 4 : (MT == 8 && NT == 8 ? 2 : 3);
+    if (METHOD == RTSSA_METHOD_DIRECT) return 4;
+    if (!SCHED) return MT <= 4 ? 4 : (MT == 8 && NT == 8 ? 2 : 3);
+    // with a schedule each lane also holds its rates in force
+    if (MT <= 2 || (MT <= 4 && NT <= 4)) return 4;
+    if (MT <= 4 || (MT == 6 && NT <= 4)) return 3;
+    return 2;
 }
 
-template <int MT, int NT, int METHOD>
-__global__ __launch_bounds__(256, thread_min_waves(MT, NT, METHOD)) void rt_thread_kernel(rt_class_dev C)
+template <int MT, int NT, int METHOD, bool SCHED>
+__global__ __launch_bounds__(256, thread_min_waves(MT, NT, METHOD, SCHED)) void rt_thread_kernel(rt_class_dev C)
 {
     rt_ws* const ws = C.ws;
     const uint32_t key0 = ws->key0, key1 = ws->key1;
@@ -162,6 +168,10 @@ __global__ __launch_bounds__(256, thread_min_waves(MT, NT, METHOD)) void rt_thre
                 nu[k][j] = (k < net.M && j < net.N) ? rt_const(net.nu_dense)[k * net.N + j] : 0;
         }
         const int N = net.N, M = net.M;
+        // rate schedule of the item (SCHED builds only): breakpoints and rows
+        const int32_t sB = SCHED ? net.sched_B : 0;
+        const rt_cptr<double> sched_t = rt_const(net.sched_t);
+        const rt_cptr<double> sched_c = rt_const(net.sched_c);
         const double t_end = it->t_end;
         const uint32_t net_id = it->net_id, traj_offset = it->traj_offset;
         const bool want_hash = it->seq_hash != nullptr;
@@ -175,6 +185,13 @@ __global__ __launch_bounds__(256, thread_min_waves(MT, NT, METHOD)) void rt_thre
 #pragma unroll
         for (int k = 0; k < MT; ++k) { T[k] = 0.0; Pk[k] = 0.0; a[k] = 0.0; inv[k] = 0.0; n[k] = 0; }
         double t = 0.0, s_next = 0.0;
+        // SCHED: the rates in force for this lane's trajectory, the index of
+        // the next breakpoint and its time
+        double cl[MT];
+        int32_t piece = 0;
+        double b_next = __builtin_inf();
+#pragma unroll
+        for (int k = 0; k < MT; ++k) cl[k] = c[k];
         int32_t g = 0;
         uint32_t fired = 0, tie = kTieNone, traj = 0;
         unsigned long long hash = kFnvOffset;
@@ -233,8 +250,12 @@ __global__ __launch_bounds__(256, thread_min_waves(MT, NT, METHOD)) void rt_thre
                 }
             }
             const double t_new = t + d1;
-            const bool absorbed = d1 == __builtin_inf();
-            const bool term = absorbed || t_new > t_end;
+            const bool live = !fresh && !capped;          // a trajectory is in progress
+            // a rate breakpoint before the next firing (and before t_end):
+            // Eq. 28 is solved again from there
+            const bool brk = SCHED && live && b_next < t_end && t_new > b_next;
+            const bool absorbed = !brk && d1 == __builtin_inf();
+            const bool term = !brk && (absorbed || t_new > t_end);
             // jump v_mu, checked against [0, 2^31 - 1]
             int32_t Xn[NT];
             bool ok = true;
@@ -247,12 +268,11 @@ __global__ __launch_bounds__(256, thread_min_waves(MT, NT, METHOD)) void rt_thre
                 ok = ok && v >= 0 && v <= 0x7FFFFFFF;
                 Xn[j] = (int32_t)v;
             }
-            const bool live = !fresh && !capped;          // a trajectory is in progress
-            const bool event = live && !term;             // this pass may apply an event
+            const bool event = live && !term && !brk;     // this pass may apply an event
             const bool near_tie = METHOD == RTSSA_METHOD_RANDOM_TIME && event &&
                                   d2 - d1 <= 1e-12 * d1;
             // a zero gap may have been clamped from a negative raw gap
-            const bool rare = !live || term || near_tie ||
+            const bool rare = !live || term || brk || near_tie ||
                               (METHOD == RTSSA_METHOD_RANDOM_TIME && d1 == 0.0) || !ok ||
                               s_next < t_new;
             if (__builtin_expect(__ballot(rare) != 0ull, 0)) {
@@ -274,7 +294,24 @@ __global__ __launch_bounds__(256, thread_min_waves(MT, NT, METHOD)) void rt_thre
                         if (clamped) atomicAdd(&ws->clamps, 1ull);
                     }
                 }
-                const bool stop = !live || term || !ok;
+                if (SCHED && brk) {
+                    // every internal clock runs to the breakpoint at the old
+                    // rates; the propensities take the next piece's rates
+                    const double db = b_next - t;
+#pragma unroll
+                    for (int k = 0; k < MT; ++k) T[k] = fma(a[k], db, T[k]);
+                    t = b_next;
+#pragma unroll
+                    for (int k = 0; k < MT; ++k) cl[k] = k < M ? sched_c[piece * M + k] : 0.0;
+                    ++piece;
+                    b_next = piece < sB ? sched_t[piece] : __builtin_inf();
+#pragma unroll
+                    for (int k = 0; k < MT; ++k) {
+                        a[k] = propensity<NT>(kind[k], s0[k], s1[k], cl[k], X);
+                        inv[k] = 1.0 / a[k];
+                    }
+                }
+                const bool stop = !live || term || (!ok && !brk);
                 if (stop && !fresh) {
                     // end of the trajectory
                     const int st = capped ? RTSSA_TRAJ_MAX_FIRINGS
@@ -327,10 +364,16 @@ __global__ __launch_bounds__(256, thread_min_waves(MT, NT, METHOD)) void rt_thre
                         fired = 0;
                         tie = kTieNone;
                         hash = kFnvOffset;
+                        if constexpr (SCHED) {
+                            piece = 0;
+                            b_next = sB > 0 ? sched_t[0] : __builtin_inf();
+#pragma unroll
+                            for (int k = 0; k < MT; ++k) cl[k] = c[k];
+                        }
 #pragma unroll
                         for (int k = 0; k < MT; ++k) {
                             n[k] = 0;
-                            a[k] = propensity<NT>(kind[k], s0[k], s1[k], c[k], X);
+                            a[k] = propensity<NT>(kind[k], s0[k], s1[k], SCHED ? cl[k] : c[k], X);
                         }
                         if constexpr (METHOD == RTSSA_METHOD_RANDOM_TIME) {
 #pragma unroll
@@ -349,7 +392,8 @@ __global__ __launch_bounds__(256, thread_min_waves(MT, NT, METHOD)) void rt_thre
                         }
                     }
                 }
-                if (__ballot(stop) != 0ull) continue;   // started lanes compute their first gaps
+                // started lanes (and lanes past a breakpoint) compute their gaps
+                if (__ballot(stop || brk) != 0ull) continue;
             }
             if constexpr (METHOD == RTSSA_METHOD_DIRECT) {
 #pragma unroll
@@ -360,7 +404,7 @@ __global__ __launch_bounds__(256, thread_min_waves(MT, NT, METHOD)) void rt_thre
                 ++fired;
                 if (want_hash) hash = (hash ^ (unsigned long long)(uint32_t)mu) * kFnvPrime;
 #pragma unroll
-                for (int k = 0; k < MT; ++k) a[k] = propensity<NT>(kind[k], s0[k], s1[k], c[k], X);
+                for (int k = 0; k < MT; ++k) a[k] = propensity<NT>(kind[k], s0[k], s1[k], SCHED ? cl[k] : c[k], X);
                 capped = fired >= C.max_firings;
                 continue;
             }
@@ -388,7 +432,7 @@ __global__ __launch_bounds__(256, thread_min_waves(MT, NT, METHOD)) void rt_thre
 #pragma unroll
             for (int k = 0; k < MT; ++k) {
                 Pk[k] = (mu == k) ? p_mu : Pk[k];
-                a[k] = propensity<NT>(kind[k], s0[k], s1[k], c[k], X);
+                a[k] = propensity<NT>(kind[k], s0[k], s1[k], SCHED ? cl[k] : c[k], X);
                 inv[k] = 1.0 / a[k];
             }
             capped = fired >= C.max_firings;
@@ -426,11 +470,12 @@ typedef void (*thread_kernel_t)(rt_class_dev);
 
 template <int MT, int NT>
 int launch_mn(const rt_class_dev& C, int block, int grid, hipStream_t stream, int* grid_used,
-              int64_t lanes_wanted, int method)
+              int64_t lanes_wanted, int method, bool sched)
 {
     thread_kernel_t kfn = method == RTSSA_METHOD_DIRECT
-                              ? rt_thread_kernel<MT, NT, RTSSA_METHOD_DIRECT>
-                              : rt_thread_kernel<MT, NT, RTSSA_METHOD_RANDOM_TIME>;
+                              ? rt_thread_kernel<MT, NT, RTSSA_METHOD_DIRECT, false>
+                              : (sched ? rt_thread_kernel<MT, NT, RTSSA_METHOD_RANDOM_TIME, true>
+                                       : rt_thread_kernel<MT, NT, RTSSA_METHOD_RANDOM_TIME, false>);
     if (grid <= 0) {
         int dev = 0, cus = 0, per_cu = 0;
         hipGetDevice(&dev);
@@ -449,12 +494,12 @@ int launch_mn(const rt_class_dev& C, int block, int grid, hipStream_t stream, in
 
 template <int MT>
 int launch_m(int N, const rt_class_dev& C, int block, int grid, hipStream_t stream, int* gu,
-             int64_t lanes, int method)
+             int64_t lanes, int method, bool sched)
 {
-    if (N <= 1) return launch_mn<MT, 1>(C, block, grid, stream, gu, lanes, method);
-    if (N <= 2) return launch_mn<MT, 2>(C, block, grid, stream, gu, lanes, method);
-    if (N <= 4) return launch_mn<MT, 4>(C, block, grid, stream, gu, lanes, method);
-    return launch_mn<MT, 8>(C, block, grid, stream, gu, lanes, method);
+    if (N <= 1) return launch_mn<MT, 1>(C, block, grid, stream, gu, lanes, method, sched);
+    if (N <= 2) return launch_mn<MT, 2>(C, block, grid, stream, gu, lanes, method, sched);
+    if (N <= 4) return launch_mn<MT, 4>(C, block, grid, stream, gu, lanes, method, sched);
+    return launch_mn<MT, 8>(C, block, grid, stream, gu, lanes, method, sched);
 }
 
 }  // namespace
@@ -469,6 +514,9 @@ int rt_thread_supported(int M, int N)
 int rt_launch_thread(int M, int N, const rt_class_dev& C, int block, int grid,
                      hipStream_t stream, int* grid_used, int64_t lanes, int method)
 {
+    const bool sched = C.has_schedule != 0;
+    if (sched && method != RTSSA_METHOD_RANDOM_TIME)
+        return rt_fail(RTSSA_E_UNSUPPORTED, "rate schedules run with the random-time method");
     if (!rt_thread_supported(M, N))
         return rt_fail(RTSSA_E_UNSUPPORTED, "network too large for the thread mapping");
     if (block <= 0) block = 256;
@@ -476,13 +524,13 @@ int rt_launch_thread(int M, int N, const rt_class_dev& C, int block, int grid,
         return rt_fail(RTSSA_E_INVALID, "thread mapping block must be a multiple of 64, <= 256");
     switch (M) {
         case 0:
-        case 1: return launch_m<1>(N, C, block, grid, stream, grid_used, lanes, method);
-        case 2: return launch_m<2>(N, C, block, grid, stream, grid_used, lanes, method);
-        case 3: return launch_m<3>(N, C, block, grid, stream, grid_used, lanes, method);
-        case 4: return launch_m<4>(N, C, block, grid, stream, grid_used, lanes, method);
+        case 1: return launch_m<1>(N, C, block, grid, stream, grid_used, lanes, method, sched);
+        case 2: return launch_m<2>(N, C, block, grid, stream, grid_used, lanes, method, sched);
+        case 3: return launch_m<3>(N, C, block, grid, stream, grid_used, lanes, method, sched);
+        case 4: return launch_m<4>(N, C, block, grid, stream, grid_used, lanes, method, sched);
         case 5:
-        case 6: return launch_m<6>(N, C, block, grid, stream, grid_used, lanes, method);
-        default: return launch_m<8>(N, C, block, grid, stream, grid_used, lanes, method);
+        case 6: return launch_m<6>(N, C, block, grid, stream, grid_used, lanes, method, sched);
+        default: return launch_m<8>(N, C, block, grid, stream, grid_used, lanes, method, sched);
     }
 }
 

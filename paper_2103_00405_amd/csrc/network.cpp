@@ -180,11 +180,12 @@ extern "C" int rtssa_network_create(int32_t N, int32_t M, const int32_t* react_p
 extern "C" int rtssa_network_destroy(rtssa_network* net)
 {
     if (!net) return RTSSA_OK;
-    if (net->dev_block) {
+    if (net->dev_block || net->sched_block) {
         int cur = -1;
         hipGetDevice(&cur);
         if (net->device >= 0 && cur != net->device) hipSetDevice(net->device);
-        hipFree(net->dev_block);
+        if (net->dev_block) hipFree(net->dev_block);
+        if (net->sched_block) hipFree(net->sched_block);
         if (cur >= 0 && cur != net->device) hipSetDevice(cur);
     }
     delete net;
@@ -214,5 +215,53 @@ extern "C" int rtssa_network_info(const rtssa_network* net, int32_t* N, int32_t*
     if (M) *M = net->M;
     if (dep_edges) *dep_edges = net->dep_ptr.empty() ? 0 : net->dep_ptr[net->M];
     if (auto_mapping) *auto_mapping = rt_auto_mapping(net);
+    return RTSSA_OK;
+}
+
+extern "C" int rtssa_network_set_schedule(rtssa_network* net, int32_t B, const double* times,
+                                          const double* rates)
+{
+    if (!net) return rt_fail(RTSSA_E_INVALID, "net is NULL");
+    if (net->batch_refs > 0)
+        return rt_fail(RTSSA_E_INVALID, "the network is part of a batch; destroy the batch first");
+    if (B < 0 || (B > 0 && (!times || (!rates && net->M > 0))))
+        return rt_fail(RTSSA_E_INVALID, "bad schedule arguments");
+    for (int32_t i = 0; i < B; ++i)
+        if (!isfinite(times[i]) || !(times[i] > (i ? times[i - 1] : 0.0)))
+            return rt_fail(RTSSA_E_INVALID, "breakpoint times must be finite, > 0 and increasing");
+    for (int64_t q = 0; q < (int64_t)B * net->M; ++q) {
+        int rc = validate_rate(rates[q], (int)(q % std::max(1, net->M)));
+        if (rc) return rc;
+    }
+    // the schedule lives on the network's device
+    struct device_guard {
+        int prev = -1;
+        explicit device_guard(int d)
+        {
+            if (d >= 0 && hipGetDevice(&prev) == hipSuccess && prev != d) hipSetDevice(d);
+            else prev = -1;
+        }
+        ~device_guard() { if (prev >= 0) hipSetDevice(prev); }
+    } guard(net->device);
+    void* blk = nullptr;
+    if (B > 0) {
+        const size_t tb = (size_t)B * sizeof(double), cb = (size_t)B * net->M * sizeof(double);
+        const size_t toff = 0, coff = (tb + 255) / 256 * 256;
+        if (hipMalloc(&blk, coff + cb + 256) != hipSuccess)
+            return rt_fail(RTSSA_E_NOMEM, "device allocation of the schedule failed");
+        if (hipMemcpy((char*)blk + toff, times, tb, hipMemcpyHostToDevice) != hipSuccess ||
+            (cb && hipMemcpy((char*)blk + coff, rates, cb, hipMemcpyHostToDevice) != hipSuccess)) {
+            hipFree(blk);
+            return rt_fail(RTSSA_E_HIP, "copy of the schedule failed");
+        }
+        net->dev.sched_t = (const double*)((char*)blk + toff);
+        net->dev.sched_c = (const double*)((char*)blk + coff);
+    } else {
+        net->dev.sched_t = nullptr;
+        net->dev.sched_c = nullptr;
+    }
+    if (net->sched_block) hipFree(net->sched_block);
+    net->sched_block = blk;
+    net->dev.sched_B = B;
     return RTSSA_OK;
 }
