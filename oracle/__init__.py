@@ -73,6 +73,8 @@ def _configure(L):
                                         C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
                                         C.c_int32, C.POINTER(_Stats),
                                         C.c_int32, C.c_void_p, C.c_void_p]
+    L.rto_lazy_simulate.restype = C.c_int
+    L.rto_lazy_simulate.argtypes = L.rto_simulate.argtypes
     L.rto_direct_simulate.restype = C.c_int
     L.rto_direct_simulate.argtypes = [C.POINTER(_Net), C.c_void_p, C.c_int32, C.c_double,
                                       C.c_void_p, C.c_int32, C.c_uint64, C.c_uint32,
@@ -130,10 +132,13 @@ def neglog_u53(m):
 
 
 def simulate(net, x0, t_end, sample_t, seed, R, net_id=0, traj_offset=0,
-             max_firings=10_000_000, threads=0, _lib=None, schedule=None):
+             max_firings=10_000_000, threads=0, _lib=None, schedule=None, lazy=False):
     """Run R trajectories of the random-time algorithm; returns a dict of arrays.
     schedule = (times [B], rates [B][M]) gives piecewise-constant rates: the
-    network's c before times[0], rates[i] from times[i] on."""
+    network's c before times[0], rates[i] from times[i] on.  lazy = True runs
+    the lazy form (dependency-graph updates, smallest absolute firing time)."""
+    if lazy and schedule is not None:
+        raise ValueError("the lazy form takes no rate schedule")
     N, M = int(net.N), int(net.M)
     x0 = np.ascontiguousarray(x0, dtype=np.int32)
     per_traj = 1 if x0.ndim == 2 else 0
@@ -158,7 +163,9 @@ def simulate(net, x0, t_end, sample_t, seed, R, net_id=0, traj_offset=0,
             _ptr(out["samples"]), _ptr(out["n"]), _ptr(out["T"]),
             _ptr(out["x_final"]), _ptr(out["t_last"]), _ptr(out["status"]),
             _ptr(out["seq_hash"]), _ptr(out["tie_step"]), int(threads), C.byref(st))
-    if schedule is None:
+    if lazy:
+        rc = L.rto_lazy_simulate(*args)
+    elif schedule is None:
         rc = L.rto_simulate(*args)
     else:
         times = np.ascontiguousarray(schedule[0], dtype=np.float64)

@@ -160,7 +160,9 @@ typedef struct {
     uint8_t* status;
     uint64_t* seq_hash;
     int64_t r_begin, r_end;
-    int32_t method;             /* 0: random time (Table 2), 1: direct method */
+    int32_t method;             /* 0: random time (Table 2), 1: direct method, 2: lazy form */
+    const int32_t* dep_ptr;     /* D(mu) lists (lazy form) */
+    const int32_t* dep_idx;
     int32_t B;                  /* rate breakpoints (0: constant rates) */
     const double* sched_t;      /* [B] breakpoint times */
     const double* sched_c;      /* [B][M] rates from each breakpoint on */
@@ -298,6 +300,139 @@ static void simulate_path(job_t* jb, int64_t r, int32_t* X, double* T, double* P
     jb->stats.status_count[st]++;
 }
 
+/* ------------------------------------------------ the lazy form */
+/* Section 5 recalls Gibson and Bruck's dependency graph: after a firing only
+ * the channels whose propensity reads a species the firing changed get new
+ * propensities.  Kept in internal times (Eq. 14-16), that gives a lazy form of
+ * the same algorithm: a channel's internal time is brought up to date only
+ * when its propensity changes or it fires, and the next event belongs to the
+ * channel with the smallest absolute next firing time tau_k (t + gap_k in
+ * exact arithmetic).  The draws E(k, n) and the law are those of
+ * simulate_path; the rounding differs, so this is a reference of its own.
+ *
+ *   per channel: T_k is the internal time at time s_k; a_k is the propensity
+ *     in force since s_k; tau_k = +inf if a_k = 0, else
+ *     s_k + max(0, RN(RN(P_k - T_k) * inv_k)).
+ *   event: mu = the lowest k among the smallest tau_k, t_new = tau_mu;
+ *     d1 = RN(t_new - t) and d2 = RN(tau_(2) - t) (second smallest tau) feed
+ *     the near-tie rule of simulate_path.  Then T_mu = P_mu,
+ *     P_mu += E(mu, n_mu), s_mu = t_new; every other k in D(mu):
+ *     T_k = fma(a_k, RN(t_new - s_k), T_k), s_k = t_new; every k in D(mu) and
+ *     mu get new a_k, inv_k and tau_k (a negative raw gap is clamped to 0
+ *     and counted).
+ *   end: T_k = fma(a_k, RN(t_stop - s_k), T_k) for every k, with t_stop =
+ *     t_end after OK or ABSORBED and the last event's time otherwise.
+ * D(mu) holds the channels with a reactant species whose net change in nu_mu
+ * is not zero (build_deps). */
+static void lazy_refresh(job_t* jb, const int32_t* X, int k, double t, const double* T,
+                         const double* P, double* a, double* inv, double* tau)
+{
+    a[k] = propensity(jb->net, X, k);
+    inv[k] = a[k] > 0 ? 1.0 / a[k] : 0.0;
+    if (a[k] == 0.0) {
+        tau[k] = INFINITY;
+        return;
+    }
+    double gap = (P[k] - T[k]) * inv[k];
+    if (gap < 0.0) {
+        jb->stats.clamps++;
+        gap = 0.0;
+    }
+    tau[k] = t + gap;
+}
+
+static void simulate_path_lazy(job_t* jb, int64_t r, int32_t* X, double* T, double* P,
+                               double* a, double* inv, uint32_t* n, double* s_up, double* tau)
+{
+    const rto_network* net = jb->net;
+    const int N = net->N, M = net->M;
+    const uint32_t traj = (uint32_t)(jb->traj_offset + (uint64_t)r);
+    const uint64_t seed = jb->seed;
+    const uint32_t nid = jb->net_id;
+
+    const int32_t* x0 = jb->x0 + (jb->x0_per_traj ? (size_t)r * N : 0);
+    for (int j = 0; j < N; j++) X[j] = x0[j];
+    double t = 0.0;
+    for (int k = 0; k < M; k++) {
+        T[k] = 0.0;
+        s_up[k] = 0.0;
+        n[k] = 0;
+        P[k] = rto_exp1(seed, traj, nid, (uint32_t)k, 0);
+        if (P[k] < 0) jb->stats.hard_cases++;
+        lazy_refresh(jb, X, k, 0.0, T, P, a, inv, tau);
+    }
+    int32_t g = 0;
+    uint64_t fired = 0;
+    uint8_t st = RTO_OK;
+    uint32_t tie = TIE_NONE;
+    uint64_t hash = 0xcbf29ce484222325ull;
+
+    for (;;) {
+        int mu = -1;
+        double tau1 = INFINITY, tau2 = INFINITY;
+        for (int k = 0; k < M; k++) {
+            if (tau[k] < tau1) { tau2 = tau1; tau1 = tau[k]; mu = k; }
+            else if (tau[k] < tau2) { tau2 = tau[k]; }
+        }
+        if (tau1 == INFINITY) { st = RTO_ABSORBED; break; }
+        double t_new = tau1;
+        if (t_new > jb->t_end) break;
+        double d1 = t_new - t, d2 = tau2 - t;
+        if (d2 - d1 <= 1e-12 * d1) {
+            jb->stats.near_ties++;
+            if (tie == TIE_NONE) tie = (uint32_t)fired;
+        }
+        while (g < jb->G && jb->s[g] < t_new) { write_sample(jb, r, g, X, 0); g++; }
+        int ok = 1;
+        for (int e = jb->nu_ptr[mu]; e < jb->nu_ptr[mu + 1]; e++) {
+            int64_t v = (int64_t)X[jb->nu_species[e]] + jb->nu_delta[e];
+            if (v < 0 || v > INT32_MAX) ok = 0;
+        }
+        if (!ok) { st = RTO_OVERFLOW; break; }
+        for (int e = jb->nu_ptr[mu]; e < jb->nu_ptr[mu + 1]; e++)
+            X[jb->nu_species[e]] += jb->nu_delta[e];
+        t = t_new;
+        n[mu] += 1;
+        fired += 1;
+        hash = (hash ^ (uint64_t)(uint32_t)mu) * 0x100000001b3ull;
+        /* the fired channel lands on its firing internal time and gets the
+         * next one (Eq. 26) */
+        T[mu] = P[mu];
+        s_up[mu] = t;
+        const uint32_t n_mu = n[mu];
+        double E_mu = rto_exp1(seed, traj, nid, (uint32_t)mu, n_mu);
+        if (E_mu < 0) jb->stats.hard_cases++;
+        P[mu] += E_mu;
+        lazy_refresh(jb, X, mu, t, T, P, a, inv, tau);
+        /* each dependent runs its clock to t at its old propensity (Eq. 15),
+         * then takes the new one */
+        for (int q = jb->dep_ptr[mu]; q < jb->dep_ptr[mu + 1]; q++) {
+            int k = jb->dep_idx[q];
+            if (k == mu) continue;
+            T[k] = fma(a[k], t - s_up[k], T[k]);
+            s_up[k] = t;
+            lazy_refresh(jb, X, k, t, T, P, a, inv, tau);
+        }
+        if (fired >= jb->max_firings) { st = RTO_MAX_FIRINGS; break; }
+    }
+
+    int good = st == RTO_OK || st == RTO_ABSORBED;
+    double t_stop = good ? jb->t_end : t;
+    for (int k = 0; k < M; k++) T[k] = fma(a[k], t_stop - s_up[k], T[k]);
+    while (g < jb->G) { write_sample(jb, r, g, X, !good); g++; }
+    for (int k = 0; k < M; k++) {
+        jb->n_out[(size_t)r * M + k] = n[k];
+        jb->T_out[(size_t)r * M + k] = T[k];
+    }
+    for (int j = 0; j < N; j++) jb->x_final[(size_t)r * N + j] = X[j];
+    jb->t_last[r] = t;
+    jb->status[r] = st;
+    jb->seq_hash[r] = hash;
+    jb->tie_step[r] = tie;
+    jb->stats.firings += fired;
+    jb->stats.status_count[st]++;
+}
+
 /* ------------------------------------------------ the direct method */
 /* Gillespie's direct method, the comparison method of section 3 and of the
  * discussion (Eq. 17-22): with the total rate a_0 = sum_k a_k (summed in
@@ -387,11 +522,14 @@ static void* run_job(void* arg)
     double* a = (double*)malloc(sizeof(double) * (M > 0 ? M : 1));
     double* inv = (double*)malloc(sizeof(double) * (M > 0 ? M : 1));
     uint32_t* n = (uint32_t*)malloc(sizeof(uint32_t) * (M > 0 ? M : 1));
+    double* s_up = (double*)malloc(sizeof(double) * (M > 0 ? M : 1));
+    double* tau = (double*)malloc(sizeof(double) * (M > 0 ? M : 1));
     for (int64_t r = jb->r_begin; r < jb->r_end; r++) {
         if (jb->method == 1) simulate_path_direct(jb, r, X, a, n);
+        else if (jb->method == 2) simulate_path_lazy(jb, r, X, T, P, a, inv, n, s_up, tau);
         else simulate_path(jb, r, X, T, P, a, inv, n);
     }
-    free(X); free(T); free(P); free(a); free(inv); free(n);
+    free(X); free(T); free(P); free(a); free(inv); free(n); free(s_up); free(tau);
     return NULL;
 }
 
@@ -422,6 +560,33 @@ static void build_nu(const rto_network* net, int32_t* ptr, int32_t* sp, int32_t*
     ptr[net->M] = pos;
 }
 
+/* D(mu) for every mu as CSR lists: channel k is in D(mu) when one of its
+ * reactant species has a nonzero net change in nu_mu; each k once, in
+ * increasing order. */
+static void build_deps(const rto_network* net, const int32_t* nu_ptr, const int32_t* nu_sp,
+                       int32_t** dptr, int32_t** didx)
+{
+    const int M = net->M;
+    int32_t* ptr = (int32_t*)malloc(sizeof(int32_t) * (M + 1));
+    size_t cap = 16, len = 0;
+    int32_t* idx = (int32_t*)malloc(sizeof(int32_t) * cap);
+    for (int mu = 0; mu < M; mu++) {
+        ptr[mu] = (int32_t)len;
+        for (int k = 0; k < M; k++) {
+            int reads = 0;
+            for (int e = net->react_ptr[k]; e < net->react_ptr[k + 1] && !reads; e++)
+                for (int q = nu_ptr[mu]; q < nu_ptr[mu + 1]; q++)
+                    if (nu_sp[q] == net->react_species[e]) reads = 1;
+            if (!reads) continue;
+            if (len == cap) { cap *= 2; idx = (int32_t*)realloc(idx, sizeof(int32_t) * cap); }
+            idx[len++] = k;
+        }
+    }
+    ptr[M] = (int32_t)len;
+    *dptr = ptr;
+    *didx = idx;
+}
+
 static int n_threads(int32_t req, int64_t R)
 {
     long nt = req > 0 ? req : sysconf(_SC_NPROCESSORS_ONLN);
@@ -446,6 +611,8 @@ static int run_all(const rto_network* net, const int32_t* x0, int32_t x0_per_tra
     int32_t* nu_sp = (int32_t*)malloc(sizeof(int32_t) * (nnz + 1));
     int32_t* nu_dl = (int32_t*)malloc(sizeof(int32_t) * (nnz + 1));
     build_nu(net, nu_ptr, nu_sp, nu_dl);
+    int32_t *dep_ptr = NULL, *dep_idx = NULL;
+    if (method == 2) build_deps(net, nu_ptr, nu_sp, &dep_ptr, &dep_idx);
 
     int nt = n_threads(nthreads, R);
     job_t* jobs = (job_t*)calloc((size_t)nt, sizeof(job_t));
@@ -460,6 +627,7 @@ static int run_all(const rto_network* net, const int32_t* x0, int32_t x0_per_tra
         jb->status = status; jb->seq_hash = seq_hash;
         jb->r_begin = R * i / nt; jb->r_end = R * (i + 1) / nt;
         jb->method = method;
+        jb->dep_ptr = dep_ptr; jb->dep_idx = dep_idx;
         jb->B = B; jb->sched_t = sched_t; jb->sched_c = sched_c;
         pthread_create(&th[i], NULL, run_job, jb);
     }
@@ -474,7 +642,7 @@ static int run_all(const rto_network* net, const int32_t* x0, int32_t x0_per_tra
         for (int q = 0; q < 4; q++) tot.status_count[q] += jobs[i].stats.status_count[q];
     }
     if (stats) *stats = tot;
-    free(jobs); free(th); free(nu_ptr); free(nu_sp); free(nu_dl);
+    free(jobs); free(th); free(nu_ptr); free(nu_sp); free(nu_dl); free(dep_ptr); free(dep_idx);
     return tot.hard_cases ? RTO_E_HARDCASE : RTO_SUCCESS;
 }
 
@@ -507,6 +675,19 @@ int rto_simulate_schedule(const rto_network* net, const int32_t* x0, int32_t x0_
     return run_all(net, x0, x0_per_traj, t_end, sample_t, G, seed, net_id, traj_offset, R,
                    max_firings, samples, n_out, T_out, x_final, t_last, status, seq_hash,
                    tie_step, nthreads, stats, 0, B, sched_t, sched_c);
+}
+
+int rto_lazy_simulate(const rto_network* net, const int32_t* x0, int32_t x0_per_traj,
+                      double t_end, const double* sample_t, int32_t G,
+                      uint64_t seed, uint32_t net_id, uint64_t traj_offset, int64_t R,
+                      uint64_t max_firings,
+                      int32_t* samples, uint32_t* n_out, double* T_out, int32_t* x_final,
+                      double* t_last, uint8_t* status, uint64_t* seq_hash, uint32_t* tie_step,
+                      int32_t nthreads, rto_stats* stats)
+{
+    return run_all(net, x0, x0_per_traj, t_end, sample_t, G, seed, net_id, traj_offset, R,
+                   max_firings, samples, n_out, T_out, x_final, t_last, status, seq_hash,
+                   tie_step, nthreads, stats, 2, 0, NULL, NULL);
 }
 
 int rto_direct_simulate(const rto_network* net, const int32_t* x0, int32_t x0_per_traj,

@@ -71,8 +71,28 @@ SCHEDULE_MUTANTS = {
 }
 
 
+# mistakes in the lazy form (dependency-graph updates in internal times)
+LAZY_MUTANTS = {
+    "lazy_dependents_not_advanced": ("T[k] = fma(a[k], t - s_up[k], T[k]);", "T[k] = T[k];"),
+    "lazy_clock_not_restamped": ("            T[k] = fma(a[k], t - s_up[k], T[k]);\n"
+                                 "            s_up[k] = t;\n",
+                                 "            T[k] = fma(a[k], t - s_up[k], T[k]);\n"),
+    "lazy_advance_at_new_rate": ("            T[k] = fma(a[k], t - s_up[k], T[k]);\n"
+                                 "            s_up[k] = t;\n"
+                                 "            lazy_refresh(jb, X, k, t, T, P, a, inv, tau);",
+                                 "            lazy_refresh(jb, X, k, t, T, P, a, inv, tau);\n"
+                                 "            T[k] = fma(a[k], t - s_up[k], T[k]);\n"
+                                 "            s_up[k] = t;"),
+    "lazy_fired_not_refreshed": ("        lazy_refresh(jb, X, mu, t, T, P, a, inv, tau);\n", ""),
+    "lazy_tau_not_offset": ("tau[k] = t + gap;", "tau[k] = gap;"),
+    "lazy_no_final_advance": ("double t_stop = good ? jb->t_end : t;", "double t_stop = t;"),
+    "lazy_reused_draw": ("(uint32_t)mu, n_mu);", "(uint32_t)mu, n_mu - 1);"),
+}
+
+
 def _build_mutant(tmp, name):
-    old, new = (MUTANTS.get(name) or DIRECT_MUTANTS.get(name) or SCHEDULE_MUTANTS[name])
+    old, new = (MUTANTS.get(name) or DIRECT_MUTANTS.get(name) or SCHEDULE_MUTANTS.get(name)
+                or LAZY_MUTANTS[name])
     src = open(os.path.join(ORACLE_DIR, "rto.c")).read()
     assert src.count(old) == 1, name
     for f in ("rto.h", "dm.c"):
@@ -274,3 +294,58 @@ def test_schedule_pins_catch_planted_mistake(name):
 
 def test_schedule_pins_pass_on_the_real_oracle():
     assert _schedule_pin_failures(oracle.lib()) == []
+
+
+def _lazy_pin_failures(L):
+    """A quick subset of the lazy-form pins (tests/test_oracle_lazy.py)."""
+    failed = []
+
+    def sim(net, x0, t_end, grid, R, seed=1, lazy=True):
+        try:
+            return oracle.simulate(net, np.asarray(x0, np.int32), t_end, np.asarray(grid, float),
+                                   seed, R, max_firings=5000, lazy=lazy, _lib=L)
+        except RuntimeError:
+            return None
+
+    k1, k2, T = 50.0, 1.0, 2.0
+    o = sim(W.birth_death(k1, k2), [0], T, [T], 8000, seed=5)
+    if o is None or (o["status"] > oracle.STATUS_ABSORBED).any():
+        failed.append("bd_run")
+    else:
+        X = o["x_final"][:, 0].astype(float)
+        m = k1 / k2 * (1 - math.exp(-k2 * T))
+        if abs(X.mean() - m) > 4.5 * math.sqrt(m / X.size) or \
+                abs(X.var() - m) > 5 * m * math.sqrt(2.0 / X.size):
+            failed.append("bd_law")
+        S = o["n"].astype(float) - o["T"]
+        for kk in range(2):
+            ET = o["T"][:, kk].mean()
+            if abs(S[:, kk].mean()) > 4.5 * math.sqrt(ET / S.shape[0]):
+                failed.append("martingale")
+                break
+        if not np.allclose(o["T"][:, 0], k1 * T, rtol=1e-12):
+            failed.append("constant_rate_clock")
+    from test_oracle_law import _cme_dimer, _chisq_discrete
+    o = sim(W.dimerisation(0.05, 1.0), [30, 0], 0.8, [0.8], 8000, seed=8)
+    if o is None or _chisq_discrete(o["x_final"][:, 1], np.arange(16),
+                                    _cme_dimer(0.05, 1.0, 30, 0, 0.8)) < 1e-4:
+        failed.append("dimer_cme")
+    w = W.lv_small(64)
+    e = sim(w.net, w.x0, 5.0, [5.0], 64, seed=9, lazy=False)
+    z = sim(w.net, w.x0, 5.0, [5.0], 64, seed=9)
+    if e is None or z is None or (e["seq_hash"] == z["seq_hash"]).mean() < 0.95:
+        failed.append("eager_sequences")
+    return failed
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("name", sorted(LAZY_MUTANTS))
+def test_lazy_pins_catch_planted_mistake(name):
+    with tempfile.TemporaryDirectory() as tmp:
+        L = _build_mutant(tmp, name)
+        failed = _lazy_pin_failures(L)
+    assert failed, "mutant %s passed every pin" % name
+
+
+def test_lazy_pins_pass_on_the_real_oracle():
+    assert _lazy_pin_failures(oracle.lib()) == []
