@@ -92,7 +92,7 @@ def cpu_baseline(w, target_s):
             "sample": "first %d of the %d trajectories (%d firings, %.1f s)" % (R, w.R, fir, dt)}
 
 
-def run_ensemble(api, w, steps, warmup, block=0, grid=0, mapping=0):
+def run_ensemble(api, w, steps, warmup, block=0, grid=0, mapping=0, method=0):
     import torch
     dev = torch.device("cuda:0")
     net = api.Network(w.net, device=dev)
@@ -109,7 +109,7 @@ def run_ensemble(api, w, steps, warmup, block=0, grid=0, mapping=0):
 
     def step():
         return api.simulate(net, x0, w.t_end, s, R, seed=w.seed, out=out, want=tuple(out),
-                            block=block, grid=grid, mapping=mapping)["stats"]
+                            block=block, grid=grid, mapping=mapping, method=method)["stats"]
 
     for i in range(warmup):
         st = step()

@@ -95,8 +95,21 @@ typedef struct {
  * reaches RN(u2 a_0); u1 (words 1:0) and u2 (words 3:2) from one
  * Philox4x32-10 block per firing at counter (firing index, 0xFFFFFFFF,
  * trajectory, net_id).  DIRECT runs only in the thread mapping (M, N <= 8)
- * and has no internal times: T_out and tie_step must be NULL. */
-enum { RTSSA_METHOD_RANDOM_TIME = 0, RTSSA_METHOD_DIRECT = 1 };
+ * and has no internal times: T_out and tie_step must be NULL.
+ * LAZY is the random-time algorithm with the dependency-graph updates of
+ * section 5 kept in internal times, for large networks: after a firing of mu
+ * only mu and the channels of D(mu) are touched; each runs its internal
+ * time from its last update s_k at its old propensity,
+ * T_k = fma(a_k, RN(t - s_k), T_k) (mu: T_mu = P_mu, then P_mu += E), takes
+ * its new a_k and the absolute next firing time
+ * tau_k = t + max(0, RN(RN(P_k - T_k) RN(1 / a_k))) (+inf if a_k = 0); the
+ * next event is the smallest tau_k, lowest k on ties; near-ties compare
+ * RN(tau_(2) - t) with RN(tau_(1) - t).  Same draws and law as RANDOM_TIME,
+ * its own rounding.  One wavefront per trajectory (stats.mapping =
+ * RTSSA_MAP_WAVE, block 64) with the tree in LDS; mapping must be AUTO or
+ * WAVE; no rate schedule; E_UNSUPPORTED when the tree does not fit LDS
+ * (about 13,000 channels). */
+enum { RTSSA_METHOD_RANDOM_TIME = 0, RTSSA_METHOD_DIRECT = 1, RTSSA_METHOD_LAZY = 2 };
 
 typedef struct {
     uint64_t max_firings;  /* per trajectory; 0 = 10^7; at most 2^32 - 1 */

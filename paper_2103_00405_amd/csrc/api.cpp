@@ -185,8 +185,19 @@ extern "C" int rtssa_simulate(const rtssa_network* net, const int32_t* x0, int32
     if (stats) memset(stats, 0, sizeof(*stats));
     int rc = rt_check_run(net, x0, x0_per_traj, t_end, sample_t, G, traj_offset, R, stream);
     if (rc) return rc;
-    if (o.method != RTSSA_METHOD_RANDOM_TIME && o.method != RTSSA_METHOD_DIRECT)
+    if (o.method != RTSSA_METHOD_RANDOM_TIME && o.method != RTSSA_METHOD_DIRECT &&
+        o.method != RTSSA_METHOD_LAZY)
         return rt_fail(RTSSA_E_INVALID, "unknown method");
+    if (o.method == RTSSA_METHOD_LAZY) {
+        if (net->dev.sched_B > 0)
+            return rt_fail(RTSSA_E_UNSUPPORTED, "the lazy form takes no rate schedule");
+        if (o.mapping != RTSSA_MAP_AUTO && o.mapping != RTSSA_MAP_WAVE)
+            return rt_fail(RTSSA_E_UNSUPPORTED, "the lazy form runs one wavefront per trajectory");
+        if (o.block != 0 && o.block != 64)
+            return rt_fail(RTSSA_E_INVALID, "the lazy form's block is 64 lanes");
+        if (net->max_nu > 64)
+            return rt_fail(RTSSA_E_UNSUPPORTED, "a reaction changes more than 64 species");
+    }
     if (o.method == RTSSA_METHOD_DIRECT) {
         if (net->dev.sched_B > 0)
             return rt_fail(RTSSA_E_UNSUPPORTED, "rate schedules run with the random-time method");
@@ -201,7 +212,9 @@ extern "C" int rtssa_simulate(const rtssa_network* net, const int32_t* x0, int32
     if (R == 0) return RTSSA_OK;
     int mapping = o.method == RTSSA_METHOD_DIRECT
                       ? RTSSA_MAP_THREAD
-                      : (o.mapping == RTSSA_MAP_AUTO ? rt_auto_mapping(net) : o.mapping);
+                      : (o.method == RTSSA_METHOD_LAZY
+                             ? RTSSA_MAP_WAVE
+                             : (o.mapping == RTSSA_MAP_AUTO ? rt_auto_mapping(net) : o.mapping));
 
     rt_run_scratch* sc = nullptr;
     rc = check_hip(hipMallocAsync((void**)&sc, sizeof(rt_run_scratch), stream), "scratch allocation");
@@ -231,9 +244,13 @@ extern "C" int rtssa_simulate(const rtssa_network* net, const int32_t* x0, int32
                          nullptr, &item, &sc->item, sc->unit_start, stream);
     if (!rc && stats) hipEventRecord(ev0, stream);
     int grid_used = 0, block_used = 0;
-    if (!rc)
+    if (!rc && o.method == RTSSA_METHOD_LAZY) {
+        block_used = 64;
+        rc = rt_launch_lazy(C, net->N, net->M, o.grid, R, stream, &grid_used);
+    } else if (!rc) {
         rc = rt_launch_class(mapping, net->M, net->N, net->max_nu, C, o.block, o.grid, R, stream,
                              &block_used, &grid_used, o.method);
+    }
     if (!rc && stats) {
         hipEventRecord(ev1, stream);
         rt_ws h{};

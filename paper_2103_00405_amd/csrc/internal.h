@@ -147,5 +147,10 @@ bool rt_group_supported(int M, int L);
 size_t rt_group_lds_bytes(int N, int M, int L);
 int rt_launch_subwave(int max_M, const rt_class_dev& C, int L, int grid, hipStream_t stream,
                       int* grid_used);
+// the lazy form (one wavefront per trajectory, LDS tree); allocates its
+// channel workspace stream-ordered
+int rt_launch_lazy(const rt_class_dev& C, int max_N, int max_M, int grid, int64_t units,
+                   hipStream_t stream, int* grid_used);
+size_t rt_lazy_lds_bytes(int N, int M);
 int rt_subwave_slots(int M, int L);
 int rt_subwave_lanes(int M);
