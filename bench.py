@@ -42,7 +42,8 @@ def alg_slots_group(M, deps=20):
     return 12 * M + 163 + 17 * deps
 
 
-PEAK_LANE_SLOTS = 256 * 4 * 16 * 2.4e9   # CUs x SIMDs x lanes x clock = 3.93e13 /s
+CLOCK_HZ = 2.4e9
+PEAK_LANE_SLOTS = 256 * 4 * 16 * CLOCK_HZ   # CUs x SIMDs x lanes x clock = 3.93e13 /s
 
 # HBM bytes per launch of rt_thread_kernel<3,2> on the Lotka-Volterra ensemble,
 # from two rocprofv3 counter passes (FETCH_SIZE, WRITE_SIZE) scaled by the same
@@ -222,6 +223,27 @@ def bench_large(api, W, steps, warmup, cpu_s=0.0):
             "roofline": {"bound": "alu", "achieved": ach / 1e12, "peak": PEAK_LANE_SLOTS / 1e12,
                          "unit": "Tslot/s", "frac": ach / PEAK_LANE_SLOTS,
                          "slots_per_firing": slots, "kernel_ms": r["kernel_s"] * 1e3}}
+
+
+def bench_large_lazy(api, W, steps, warmup, eager_value=None):
+    """The large random network with the lazy form (dependency-graph updates,
+    minimum tree in LDS, one wavefront per trajectory).  With 512 trajectories
+    at most one wavefront runs per SIMD, so a firing costs its full latency:
+    cycles_per_firing is that latency per wavefront (kernel time x clock x
+    resident wavefronts / firings)."""
+    w = W.large_random()
+    r = run_ensemble(api, w, steps, warmup, method=api.METHOD_LAZY)
+    grid = r["stats"]["grid"]
+    out = {"workload": "large_random_network", "method": "lazy", "N": w.net.N, "M": w.net.M,
+           "trajectories": w.R, "t_end": w.t_end, "value": r["firings"] / r["wall"],
+           "unit": "firings/s", "ms_per_step": r["wall"] / steps * 1e3,
+           "firings_per_step": r["firings_per_step"], "mapping": "wave", "block": 64,
+           "grid": grid, "kernel_ms": r["kernel_s"] * 1e3,
+           "cycles_per_firing": r["kernel_s"] * CLOCK_HZ * min(grid, w.R) /
+           r["firings_per_step"]}
+    if eager_value:
+        out["vs_eager"] = out["value"] / eager_value
+    return out
 
 
 def bench_gradient(api, W, reps=3):
@@ -405,6 +427,7 @@ def main():
             out = bench_direct(api, W, args.steps, args.warmup)
         elif args.workload == "large_random":
             out = bench_large(api, W, args.steps, args.warmup)
+            out["lazy"] = bench_large_lazy(api, W, args.steps, args.warmup, out["value"])
         elif args.workload == "gradient":
             out = bench_gradient(api, W)
         else:
@@ -456,9 +479,11 @@ def main():
         cs = 0.0 if args.no_cpu_baseline else 5.0
         direct = bench_direct(api, W)
         direct["vs_random_time"] = direct["value"] / value
+        large = bench_large(api, W, 2, 1, cpu_s=cs)
         res["secondary"] = {"lv_small": bench_lv_small(api, W),
                             "direct_method": direct,
-                            "large_random": bench_large(api, W, 2, 1, cpu_s=cs),
+                            "large_random": large,
+                            "large_random_lazy": bench_large_lazy(api, W, 2, 1, large["value"]),
                             "gradient": bench_gradient(api, W),
                             "batched": bench_batched(api, W, 2, cpu_s=cs)}
     if not args.no_cpu_baseline:

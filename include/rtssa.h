@@ -108,7 +108,12 @@ typedef struct {
  * its own rounding.  One wavefront per trajectory (stats.mapping =
  * RTSSA_MAP_WAVE, block 64) with the tree in LDS; mapping must be AUTO or
  * WAVE; no rate schedule; E_UNSUPPORTED when the tree does not fit LDS
- * (about 13,000 channels). */
+ * (about 13,000 channels).  The first LAZY run of a network builds its
+ * fixed-stride rows (about 270 bytes per channel of device memory, kept
+ * until the network is destroyed); that first run must not overlap another
+ * call on the same network from a second host thread.  Its channel workspace
+ * (36 bytes per channel per resident wavefront) is allocated stream-ordered
+ * by the call. */
 enum { RTSSA_METHOD_RANDOM_TIME = 0, RTSSA_METHOD_DIRECT = 1, RTSSA_METHOD_LAZY = 2 };
 
 typedef struct {

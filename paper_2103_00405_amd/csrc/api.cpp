@@ -197,6 +197,10 @@ extern "C" int rtssa_simulate(const rtssa_network* net, const int32_t* x0, int32
             return rt_fail(RTSSA_E_INVALID, "the lazy form's block is 64 lanes");
         if (net->max_nu > 64)
             return rt_fail(RTSSA_E_UNSUPPORTED, "a reaction changes more than 64 species");
+        if (R > 0) {
+            rc = rt_lazy_prepare(const_cast<rtssa_network*>(net));
+            if (rc) return rc;
+        }
     }
     if (o.method == RTSSA_METHOD_DIRECT) {
         if (net->dev.sched_B > 0)

@@ -37,6 +37,15 @@ struct rt_net_dev {
     int32_t sched_B;
     const double* sched_t;
     const double* sched_c;
+    // lazy form, fixed-stride rows (built on first use): touch[mu*64] = the
+    // number of channels of D(mu) other than mu, touch[mu*64 + q] (q = 1..63)
+    // the q-th of them or -1; touch_more[mu] = the CSR position of the 64th
+    // (dep_ptr[mu+1] if none); nu_fixed[mu*nu_stride + i] = (species, change)
+    // of the jump v_mu, (-1, 0) past its end
+    const int32_t* touch;
+    const int32_t* touch_more;
+    const int2* nu_fixed;
+    int32_t nu_stride;
 };
 
 struct rtssa_network {
@@ -49,6 +58,7 @@ struct rtssa_network {
     int device = -1;
     void* dev_block = nullptr;  // one allocation holding every device table
     void* sched_block = nullptr;  // device copy of the rate schedule (times, rates)
+    void* lazy_block = nullptr;   // the lazy form's fixed-stride rows
     int32_t batch_refs = 0;       // batch items holding this network's device pointers
     rt_net_dev dev{};
 };
@@ -152,5 +162,7 @@ int rt_launch_subwave(int max_M, const rt_class_dev& C, int L, int grid, hipStre
 int rt_launch_lazy(const rt_class_dev& C, int max_N, int max_M, int grid, int64_t units,
                    hipStream_t stream, int* grid_used);
 size_t rt_lazy_lds_bytes(int N, int M);
+// builds and uploads the lazy form's rows of a network once (network.cpp)
+int rt_lazy_prepare(rtssa_network* net);
 int rt_subwave_slots(int M, int L);
 int rt_subwave_lanes(int M);

@@ -1,5 +1,5 @@
 // kernels_lazy.hip -- the lazy form for large networks: one wavefront per
-// trajectory, an 8-ary minimum tree in LDS.
+// trajectory, a minimum tree of fan-out 8 in LDS.
 //
 // The lazy form follows section 5's dependency graph in internal times
 // (Eq. 14-16): after a firing of mu only the channels of D(mu) (those whose
@@ -14,18 +14,24 @@
 //
 // Layout.  The wavefront's LDS region holds the species counts X and the
 // tree: the leaves are tau_k (M doubles); a node of level l >= 1 holds the
-// smallest and second smallest tau and the smallest's channel over its 8
-// children of level l - 1; the last level is the root.  Each level is stored
-// as separate arrays (smallest, second smallest, channel) padded to a multiple
-// of 8 entries with empty values, so that a node's 8 children are read with a
-// few 16-byte loads and no bounds tests; merges use selects, not branches.  The channels' T_k,
+// smallest tau over its kFan children of level l - 1 and that tau's channel;
+// the last level is the root, which every lane also keeps in registers.
+// Each level is stored as two arrays (tau, channel) padded to a multiple of
+// kFan entries with empty values, so that a node's children are read with a
+// few 16-byte loads and no bounds tests; merges use selects, not branches.
+// Fan-out 8 measured faster than 16 on 4000 channels (4 levels against 3, but
+// a shallower merge per level).  The second smallest tau (for the near-tie count
+// only) is the smallest over the siblings of mu's leaf and of each of its
+// ancestors below the root: one LDS read per lane and a wavefront minimum,
+// done while the firing's global loads are in flight.  The channels' T_k,
 // s_k, P_k, a_k (32 bytes) and n_k live in a global workspace, one slice per
-// wavefront of the grid.  A firing: the root gives mu; wavefront loads mu's
-// jump and dependency lists, checks and applies the jump, draws mu's next
-// Exp(1) with all lanes, then one lane per touched channel updates it and
-// writes its leaf; the touched leaves' ancestors are recomputed level by
-// level, one lane per touched channel (lanes that share an ancestor compute
-// the same node).  No workgroup barrier is used: a wavefront's LDS accesses
+// wavefront of the grid.  A firing: the root gives mu; the wavefront loads
+// mu's fixed-stride rows (its jump and the channels it touches, so that one
+// load round trip suffices before the records), checks and applies the jump,
+// draws mu's next Exp(1) with all lanes, then one lane per touched channel
+// updates it and writes its leaf; the touched leaves' ancestors are recomputed
+// level by level, one lane per touched channel (lanes that share an ancestor
+// compute the same node).  No workgroup barrier is used: a wavefront's LDS accesses
 // complete in program order.
 #include <hip/hip_runtime.h>
 
@@ -38,7 +44,9 @@ namespace {
 constexpr uint32_t kTieNone = 0xFFFFFFFFu;
 constexpr unsigned long long kFnvOffset = 0xcbf29ce484222325ull;
 constexpr unsigned long long kFnvPrime = 0x100000001b3ull;
-constexpr int kMaxLevels = 6;            // 8^6 leaves would need 2 MB of LDS
+constexpr int kFanLog = 3;               // children per node: 2^kFanLog
+constexpr int kFan = 1 << kFanLog;
+constexpr int kMaxLevels = 64 / kFan;    // one lane per sibling in lazy_second
 
 struct rt_lazy_rec {                     // a channel's state in the workspace
     double T, s, P, a;
@@ -93,80 +101,103 @@ __device__ __forceinline__ double lazy_tau(double t, double T, double P, double 
     return a == 0.0 ? __builtin_inf() : t + fmax(raw, 0.0);
 }
 
-// The tree of one trajectory: level 0 holds the leaves (d1 = tau, channel =
+// The tree of one trajectory: level 0 holds the leaves (tau; channel =
 // index), levels 1 .. top the nodes; cnt = entries in use, every array padded
-// to a multiple of 8 entries (+inf, +inf, INT_MAX).  Times are never -0 (t
-// starts at +0 and only grows), so selects on '<' order them exactly.
+// to a multiple of kFan entries (+inf, INT_MAX).  Times are never -0 (t starts
+// at +0 and only grows), so selects on '<' order them exactly.
 struct lazy_tree {
-    double* d1[kMaxLevels + 1];
-    double* d2[kMaxLevels + 1];
+    double* d[kMaxLevels + 1];
     int32_t* kk[kMaxLevels + 1];
     int cnt[kMaxLevels + 1];
     int top;
 };
 
-__device__ __forceinline__ int pad8(int n) { return (n + 7) & ~7; }
+struct lazy_min {                        // smallest tau of a subtree and its channel
+    double d;
+    int32_t k;
+};
 
-// Smallest, second smallest and the smallest's channel of two entries; on
-// equal smallest values the lower channel wins.
-__device__ __forceinline__ rt_min2 lazy_merge(const rt_min2& a, const rt_min2& b)
+__device__ __forceinline__ int padf(int n) { return (n + kFan - 1) & ~(kFan - 1); }
+
+// The smaller of two entries, a covering lower channels than b (siblings in
+// channel order): on equal values a, and so the lower channel, wins.
+__device__ __forceinline__ lazy_min lazy_merge(const lazy_min& a, const lazy_min& b)
 {
-    const bool blt = b.d1 < a.d1, alt = a.d1 < b.d1;
-    const double hi = blt ? a.d1 : b.d1;                 // the larger of the two minima
-    const double m2 = b.d2 < a.d2 ? b.d2 : a.d2;
-    rt_min2 r;
-    r.d1 = blt ? b.d1 : a.d1;
-    r.d2 = m2 < hi ? m2 : hi;
-    // blt: b.k; a.d1 < b.d1: a.k; equal: the lower channel.  Written so that
-    // both channels feed both selects (no branch, no load sunk into one)
-    r.k = min(blt ? b.k : a.k, alt ? a.k : b.k);
-    return r;
+    const bool blt = b.d < a.d;
+    return lazy_min{blt ? b.d : a.d, blt ? b.k : a.k};
 }
 
-// Two leaves a (channel ka) and b (channel kb > ka).
-__device__ __forceinline__ rt_min2 lazy_pair(double a, int ka, double b, int kb)
+// Node j of level l (1 <= l) from its kFan children, loaded together (the padded
+// arrays make every child present) and merged pairwise, always left with
+// right, so that ties go to the lower channel.
+__device__ __forceinline__ lazy_min lazy_node(const lazy_tree& tr, int l, int j)
 {
-    const bool blt = b < a;
-    rt_min2 r;
-    r.d1 = blt ? b : a;
-    r.d2 = blt ? a : b;
-    r.k = blt ? kb : ka;
-    return r;
-}
-
-// Node j of level l (1 <= l) from its 8 children, loaded together (the padded
-// arrays make every child present) and merged pairwise; minimum, second
-// minimum and the lowest-channel tie-break do not depend on the merge order.
-__device__ __forceinline__ rt_min2 lazy_node(const lazy_tree& tr, int l, int j)
-{
-    const int c0 = j << 3;
-    const double2* v1 = (const double2*)(tr.d1[l - 1] + c0);
-    const double2 a01 = v1[0], a23 = v1[1], a45 = v1[2], a67 = v1[3];
-    if (l == 1) {
-        const rt_min2 a = lazy_merge(lazy_pair(a01.x, c0, a01.y, c0 + 1),
-                                     lazy_pair(a23.x, c0 + 2, a23.y, c0 + 3));
-        const rt_min2 b = lazy_merge(lazy_pair(a45.x, c0 + 4, a45.y, c0 + 5),
-                                     lazy_pair(a67.x, c0 + 6, a67.y, c0 + 7));
-        return lazy_merge(a, b);
+    const int c0 = j << kFanLog;
+    lazy_min v[kFan];
+    const double2* vd = (const double2*)(tr.d[l - 1] + c0);
+#pragma unroll
+    for (int i = 0; i < kFan / 2; ++i) {
+        const double2 x = vd[i];
+        v[2 * i].d = x.x;
+        v[2 * i + 1].d = x.y;
     }
-    const double2* v2 = (const double2*)(tr.d2[l - 1] + c0);
-    const double2 b01 = v2[0], b23 = v2[1], b45 = v2[2], b67 = v2[3];
-    const int4* vk = (const int4*)(tr.kk[l - 1] + c0);
-    const int4 k03 = vk[0], k47 = vk[1];
-    const rt_min2 n0{a01.x, b01.x, k03.x}, n1{a01.y, b01.y, k03.y};
-    const rt_min2 n2{a23.x, b23.x, k03.z}, n3{a23.y, b23.y, k03.w};
-    const rt_min2 n4{a45.x, b45.x, k47.x}, n5{a45.y, b45.y, k47.y};
-    const rt_min2 n6{a67.x, b67.x, k47.z}, n7{a67.y, b67.y, k47.w};
-    const rt_min2 a = lazy_merge(lazy_merge(n0, n1), lazy_merge(n2, n3));
-    const rt_min2 b = lazy_merge(lazy_merge(n4, n5), lazy_merge(n6, n7));
-    return lazy_merge(a, b);
+    if (l == 1) {
+#pragma unroll
+        for (int i = 0; i < kFan; ++i) v[i].k = c0 + i;
+    } else {
+        const int4* vk = (const int4*)(tr.kk[l - 1] + c0);
+#pragma unroll
+        for (int i = 0; i < kFan / 4; ++i) {
+            const int4 x = vk[i];
+            v[4 * i].k = x.x;
+            v[4 * i + 1].k = x.y;
+            v[4 * i + 2].k = x.z;
+            v[4 * i + 3].k = x.w;
+        }
+    }
+#pragma unroll
+    for (int w = kFan / 2; w >= 1; w >>= 1)
+#pragma unroll
+        for (int i = 0; i < w; ++i) v[i] = lazy_merge(v[2 * i], v[2 * i + 1]);
+    return v[0];
 }
 
-__device__ __forceinline__ void lazy_store(const lazy_tree& tr, int l, int j, const rt_min2& v)
+__device__ __forceinline__ void lazy_store(const lazy_tree& tr, int l, int j, const lazy_min& v)
 {
-    tr.d1[l][j] = v.d1;
-    tr.d2[l][j] = v.d2;
+    tr.d[l][j] = v.d;
     tr.kk[l][j] = v.k;
+}
+
+__device__ __forceinline__ double lazy_min_f64(double a, double b) { return b < a ? b : a; }
+
+// Smallest value over the wavefront.
+__device__ __forceinline__ double lazy_wave_min(double v)
+{
+    v = lazy_min_f64(v, rt_dpp_f64<0xB1>(v));            // quad_perm [1,0,3,2]
+    v = lazy_min_f64(v, rt_dpp_f64<0x4E>(v));            // quad_perm [2,3,0,1]
+    v = lazy_min_f64(v, rt_dpp_f64<0x141>(v));           // row_half_mirror
+    v = lazy_min_f64(v, rt_dpp_f64<0x140>(v));           // row_mirror
+    double q;
+    double p = rt_swap_f64<16>(v, q);
+    v = lazy_min_f64(p, q);
+    p = rt_swap_f64<32>(v, q);
+    return lazy_min_f64(p, q);
+}
+
+// The second smallest tau over all leaves: every leaf but mu lies in the
+// group of mu's leaf or below a sibling of one of mu's ancestors, so it is the
+// smallest of those siblings' values (lane kFan l + i reads sibling i at level
+// l; level_off holds each level's tau array as a byte offset into the LDS
+// region, a table in LDS so that the per-lane level index does not turn into
+// a private-memory array).
+__device__ __forceinline__ double lazy_second(const char* region, const uint32_t* level_off,
+                                              int top, int mu, int lane)
+{
+    const int lev = min(lane >> kFanLog, top - 1), i = lane & (kFan - 1);
+    const int jl = mu >> (kFanLog * lev);
+    const double x = ((const double*)(region + level_off[lev]))[(jl & ~(kFan - 1)) + i];
+    return lazy_wave_min((lane >> kFanLog) < top && i != (jl & (kFan - 1)) ? x
+                                                                          : __builtin_inf());
 }
 
 // A touched channel's update (mu: fresh = true, T_mu = P_mu, P_mu += E;
@@ -195,6 +226,7 @@ __global__ __launch_bounds__(64) void rt_lazy_kernel(rt_class_dev C, rt_lazy_rec
 {
     extern __shared__ int32_t dyn_lds[];
     __shared__ uint32_t log_scratch[RT_LOG_SCRATCH];
+    __shared__ uint32_t level_off[kMaxLevels + 1];
     rt_ws* const ws = C.ws;
     const uint32_t key0 = ws->key0, key1 = ws->key1;
     const int lane = threadIdx.x;
@@ -214,9 +246,10 @@ __global__ __launch_bounds__(64) void rt_lazy_kernel(rt_class_dev C, rt_lazy_rec
         const int N = net.N, M = net.M;
         const rt_cptr<int2> react = rt_const(net.react);
         const rt_cptr<double> cc = rt_const(net.c);
-        const rt_cptr<int32_t> nu_ptr = rt_const(net.nu_ptr), nu_sp = rt_const(net.nu_sp);
-        const rt_cptr<int32_t> nu_dl = rt_const(net.nu_dl), dep_ptr = rt_const(net.dep_ptr);
-        const rt_cptr<int32_t> dep_idx = rt_const(net.dep_idx);
+        const rt_cptr<int32_t> dep_ptr = rt_const(net.dep_ptr), dep_idx = rt_const(net.dep_idx);
+        const rt_cptr<int32_t> touch = rt_const(net.touch), touch_more = rt_const(net.touch_more);
+        const rt_cptr<int2> nu_fixed = rt_const(net.nu_fixed);
+        const int nu_stride = net.nu_stride;
         const int64_t r = (int64_t)u - unit_start[item];
         const uint32_t traj = it->traj_offset + (uint32_t)r;
         const uint32_t net_id = it->net_id;
@@ -230,31 +263,30 @@ __global__ __launch_bounds__(64) void rt_lazy_kernel(rt_class_dev C, rt_lazy_rec
         {
             char* p = (char*)(dyn_lds + ((N + 3) & ~3));
             tr.cnt[0] = M > 0 ? M : 1;
-            tr.d1[0] = (double*)p;
-            tr.d2[0] = nullptr;
+            tr.d[0] = (double*)p;
             tr.kk[0] = nullptr;
-            p += 8 * pad8(tr.cnt[0]);
+            p += 8 * padf(tr.cnt[0]);
             tr.top = 0;
 #pragma unroll
             for (int l = 1; l <= kMaxLevels; ++l) {
-                tr.cnt[l] = (tr.cnt[l - 1] + 7) >> 3;
-                const int P = tr.top == 0 ? pad8(tr.cnt[l]) : 0;
-                tr.d1[l] = (double*)p;
-                tr.d2[l] = (double*)(p + 8 * P);
-                tr.kk[l] = (int32_t*)(p + 16 * P);
-                p += 20 * P;
+                tr.cnt[l] = (tr.cnt[l - 1] + kFan - 1) >> kFanLog;
+                const int P = tr.top == 0 ? padf(tr.cnt[l]) : 0;
+                tr.d[l] = (double*)p;
+                tr.kk[l] = (int32_t*)(p + 8 * P);
+                p += 12 * P;
                 if (tr.top == 0 && tr.cnt[l] == 1) tr.top = l;
             }
         }
         const int top = tr.top;
-        double* const leaves = tr.d1[0];
-        double* root_d1 = tr.d1[1];
-        double* root_d2 = tr.d2[1];
+        double* const leaves = tr.d[0];
+#pragma unroll
+        for (int l = 0; l <= kMaxLevels; ++l)
+            if (lane == l) level_off[l] = (uint32_t)((char*)tr.d[l] - (char*)dyn_lds);
+        double* root_d = tr.d[1];
         int32_t* root_k = tr.kk[1];
 #pragma unroll
         for (int l = 2; l <= kMaxLevels; ++l) {
-            root_d1 = l == top ? tr.d1[l] : root_d1;
-            root_d2 = l == top ? tr.d2[l] : root_d2;
+            root_d = l == top ? tr.d[l] : root_d;
             root_k = l == top ? tr.kk[l] : root_k;
         }
 
@@ -262,12 +294,12 @@ __global__ __launch_bounds__(64) void rt_lazy_kernel(rt_class_dev C, rt_lazy_rec
         const int32_t* x0 = it->x0 + (it->x0_per_traj ? r * N : 0);
         for (int j = lane; j < N; j += 64) X[j] = x0[j];
         // padding entries (and the single leaf of an empty network) are empty
-        for (int k = M + lane; k < pad8(tr.cnt[0]); k += 64) leaves[k] = __builtin_inf();
+        for (int k = M + lane; k < padf(tr.cnt[0]); k += 64) leaves[k] = __builtin_inf();
 #pragma unroll
         for (int l = 1; l <= kMaxLevels; ++l) {
             if (l > top) break;
-            for (int j = tr.cnt[l] + lane; j < pad8(tr.cnt[l]); j += 64)
-                lazy_store(tr, l, j, rt_min2_empty());
+            for (int j = tr.cnt[l] + lane; j < padf(tr.cnt[l]); j += 64)
+                lazy_store(tr, l, j, lazy_min{__builtin_inf(), 0x7FFFFFFF});
         }
         wave_lds_fence();
         for (int k = lane; k < M; k += 64) {
@@ -287,6 +319,10 @@ __global__ __launch_bounds__(64) void rt_lazy_kernel(rt_class_dev C, rt_lazy_rec
             wave_lds_fence();
         }
 
+        // the root: read once here, then kept in registers (every lane
+        // computes it at the top level of each tree update)
+        double root_tau = *root_d;
+        int root_ch = *root_k;
         double t = 0.0, s_next = it->G > 0 ? rt_const(it->s)[0] : __builtin_inf();
         int32_t g = 0;
         uint32_t fired = 0, tie = kTieNone;
@@ -295,16 +331,11 @@ __global__ __launch_bounds__(64) void rt_lazy_kernel(rt_class_dev C, rt_lazy_rec
 
         for (;;) {
             // ---- the next event: the root of the tree
-            const double tau1 = *root_d1, tau2 = *root_d2;
-            const int mu = __builtin_amdgcn_readfirstlane(*root_k);
+            const double tau1 = root_tau;
+            const int mu = __builtin_amdgcn_readfirstlane(root_ch);
             if (tau1 == __builtin_inf()) { st = RTSSA_TRAJ_ABSORBED; break; }
             const double t_new = tau1;
             if (t_new > t_end) break;
-            const double d1 = t_new - t, d2 = tau2 - t;
-            if (d2 - d1 <= 1e-12 * d1) {
-                if (lane == 0) atomicAdd(&ws->near_ties, 1ull);
-                tie = tie == kTieNone ? fired : tie;
-            }
             while (s_next < t_new) {
                 if (it->samples) {
                     int32_t* dst = it->samples + r * it->ss_r + (int64_t)g * it->ss_g;
@@ -314,32 +345,38 @@ __global__ __launch_bounds__(64) void rt_lazy_kernel(rt_class_dev C, rt_lazy_rec
                 s_next = g < it->G ? rt_const(it->s)[g] : __builtin_inf();
             }
             // ---- every load of the firing is issued before any is used:
-            // mu's jump, the touched channels of the first round (lane 0: mu,
-            // lane q: entry q - 1 of D(mu), mu itself skipped there), their
-            // records and reaction data, and mu's firing count.  Indices are
-            // clamped so that every lane loads a valid entry (the lists end
-            // with a padding entry); unused loads are discarded.
-            const int nb = nu_ptr[mu], ne = nu_ptr[mu + 1];
-            const int db = dep_ptr[mu], de = dep_ptr[mu + 1];
-            const int n_nu = ne - nb, n_dep = de - db;
-            const int qs = nb + max(0, min(lane, n_nu - 1));
-            const int sp = nu_sp[qs], dl = nu_dl[qs];
-            const int kq = dep_idx[db + max(0, min(lane - 1, n_dep - 1))];
-            const bool act = lane == 0 || (lane <= n_dep && kq != mu);
-            const int k = lane == 0 || !act ? mu : kq;
+            // mu's fixed-stride rows (the jump; the touched channels of the
+            // first round: lane 0 takes mu, lane q the q-th other channel of
+            // D(mu)), then their records and reaction data, and mu's firing
+            // count; lanes without a channel load mu's (valid, unused)
+            const int n_other = touch[mu * 64];
+            const int tv = touch[mu * 64 + lane];
+            const int2 nv = nu_fixed[mu * nu_stride + min(lane, nu_stride - 1)];
+            const bool has_nu = lane < nu_stride && nv.x >= 0;
+            const int sp = max(nv.x, 0), dl = nv.y;
+            const bool act = lane == 0 || tv >= 0;
+            const int k = lane == 0 || !act ? mu : tv;
             const rt_lazy_rec rc0 = recs[k];
             const int2 rr0 = react[k];
             const double c0 = cc[k];
             const uint32_t nm = nks[mu];
+            // near-tie test (statistics only) while the loads are in flight
+            {
+                const double d1 = t_new - t, d2 = lazy_second((const char*)dyn_lds, level_off, top, mu, lane) - t;
+                if (d2 - d1 <= 1e-12 * d1) {
+                    if (lane == 0) atomicAdd(&ws->near_ties, 1ull);
+                    tie = tie == kTieNone ? fired : tie;
+                }
+            }
             // the fired channel's next Exp(1) (Eq. 26), drawn by every lane
             // while the loads are in flight
             const double E = rt_exp1_uniform(key0, key1, traj, net_id, (uint32_t)mu, nm + 1u,
                                              &ws->slow_logs, log_scratch);
             // ---- the jump v_mu, checked against [0, 2^31 - 1]
             const int64_t xv = (int64_t)X[sp] + dl;
-            const bool okl = lane >= n_nu || (xv >= 0 && xv <= 0x7FFFFFFF);
+            const bool okl = !has_nu || (xv >= 0 && xv <= 0x7FFFFFFF);
             if (__ballot(!okl) != 0ull) { st = RTSSA_TRAJ_OVERFLOW; break; }
-            if (lane < n_nu) X[sp] = (int32_t)xv;
+            if (has_nu) X[sp] = (int32_t)xv;
             wave_lds_fence();
             // ---- first round of touched channels, then their ancestors
             if (act) recs[k] = lazy_touch(rc0, lane == 0, E, t_new, rr0, c0, X, &leaves[k],
@@ -350,25 +387,35 @@ __global__ __launch_bounds__(64) void rt_lazy_kernel(rt_class_dev C, rt_lazy_rec
 #pragma unroll
             for (int l = 1; l <= kMaxLevels; ++l) {
                 if (l > top) break;
-                const int j = k >> (3 * l);
-                lazy_store(tr, l, j, lazy_node(tr, l, j));
+                const int j = k >> (kFanLog * l);
+                const lazy_min nv = lazy_node(tr, l, j);
+                lazy_store(tr, l, j, nv);
+                root_tau = l == top ? nv.d : root_tau;
+                root_ch = l == top ? nv.k : root_ch;
                 wave_lds_fence();
             }
-            // ---- more than 63 dependents: further rounds of 64
-            for (int q0 = 63; q0 < n_dep; q0 += 64) {
-                const int q = q0 + lane;
-                int k2 = q < n_dep ? dep_idx[db + q] : -1;
-                if (k2 == mu) k2 = -1;
-                if (k2 >= 0)
-                    recs[k2] = lazy_touch(recs[k2], false, E, t_new, react[k2], cc[k2], X,
-                                          &leaves[k2], &ws->clamps);
-                wave_lds_fence();
-#pragma unroll
-                for (int l = 1; l <= kMaxLevels; ++l) {
-                    if (l > top) break;
-                    const int j = (k2 >= 0 ? k2 : mu) >> (3 * l);
-                    lazy_store(tr, l, j, lazy_node(tr, l, j));
+            // ---- more than 63 other dependents: the rest of the CSR list
+            // D(mu) from the 64th on, 64 per round (mu itself skipped)
+            if (n_other > 63) {
+                const int de = dep_ptr[mu + 1];
+                for (int q0 = touch_more[mu]; q0 < de; q0 += 64) {
+                    const int q = q0 + lane;
+                    int k2 = q < de ? dep_idx[q] : -1;
+                    if (k2 == mu) k2 = -1;
+                    if (k2 >= 0)
+                        recs[k2] = lazy_touch(recs[k2], false, E, t_new, react[k2], cc[k2], X,
+                                              &leaves[k2], &ws->clamps);
                     wave_lds_fence();
+#pragma unroll
+                    for (int l = 1; l <= kMaxLevels; ++l) {
+                        if (l > top) break;
+                        const int j = (k2 >= 0 ? k2 : mu) >> (kFanLog * l);
+                        const lazy_min nv = lazy_node(tr, l, j);
+                        lazy_store(tr, l, j, nv);
+                        root_tau = l == top ? nv.d : root_tau;
+                root_ch = l == top ? nv.k : root_ch;
+                        wave_lds_fence();
+                    }
                 }
             }
             if (lane == 0) nks[mu] = nm + 1u;
@@ -410,15 +457,16 @@ __global__ __launch_bounds__(64) void rt_lazy_kernel(rt_class_dev C, rt_lazy_rec
 }  // namespace
 
 // LDS bytes of one trajectory: X, the leaves and every node level (arrays
-// padded to 8 entries); 0 when the tree would need more than kMaxLevels levels.
+// padded to kFan entries); 0 when the tree would need more than kMaxLevels
+// levels.
 size_t rt_lazy_lds_bytes(int N, int M)
 {
     size_t n = (size_t)((N + 3) & ~3) * 4;
     int c = M > 0 ? M : 1;
-    n += (size_t)((c + 7) & ~7) * 8;
+    n += (size_t)((c + kFan - 1) & ~(kFan - 1)) * 8;
     for (int l = 1; l <= kMaxLevels; ++l) {
-        c = (c + 7) >> 3;
-        n += (size_t)((c + 7) & ~7) * 20;
+        c = (c + kFan - 1) >> kFanLog;
+        n += (size_t)((c + kFan - 1) & ~(kFan - 1)) * 12;
         if (c == 1) return n;
     }
     return 0;

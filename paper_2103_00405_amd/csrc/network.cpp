@@ -180,15 +180,70 @@ extern "C" int rtssa_network_create(int32_t N, int32_t M, const int32_t* react_p
 extern "C" int rtssa_network_destroy(rtssa_network* net)
 {
     if (!net) return RTSSA_OK;
-    if (net->dev_block || net->sched_block) {
+    if (net->dev_block || net->sched_block || net->lazy_block) {
         int cur = -1;
         hipGetDevice(&cur);
         if (net->device >= 0 && cur != net->device) hipSetDevice(net->device);
         if (net->dev_block) hipFree(net->dev_block);
         if (net->sched_block) hipFree(net->sched_block);
+        if (net->lazy_block) hipFree(net->lazy_block);
         if (cur >= 0 && cur != net->device) hipSetDevice(cur);
     }
     delete net;
+    return RTSSA_OK;
+}
+
+int rt_lazy_prepare(rtssa_network* net)
+{
+    if (net->lazy_block) return RTSSA_OK;
+    const int M = net->M;
+    int S = 1;
+    while (S < net->max_nu) S <<= 1;
+    if (S > 64) return rt_fail(RTSSA_E_UNSUPPORTED, "a reaction changes more than 64 species");
+    const size_t rows = (size_t)std::max(M, 1);
+    std::vector<int32_t> touch(rows * 64, -1), more(rows, 0);
+    std::vector<int2> nu(rows * S, make_int2(-1, 0));
+    for (int mu = 0; mu < M; ++mu) {
+        int n_other = 0;
+        more[mu] = net->dep_ptr[mu + 1];
+        for (int q = net->dep_ptr[mu]; q < net->dep_ptr[mu + 1]; ++q) {
+            const int k = net->dep_idx[q];
+            if (k == mu) continue;
+            if (n_other < 63) touch[(size_t)mu * 64 + 1 + n_other] = k;
+            else if (n_other == 63) more[mu] = q;
+            ++n_other;
+        }
+        touch[(size_t)mu * 64] = n_other;
+        for (int e = net->nu_ptr[mu]; e < net->nu_ptr[mu + 1]; ++e)
+            nu[(size_t)mu * S + (e - net->nu_ptr[mu])] = make_int2(net->nu_sp[e], net->nu_dl[e]);
+    }
+    const size_t tb = touch.size() * 4, mb = (more.size() * 4 + 255) / 256 * 256;
+    const size_t nb = nu.size() * sizeof(int2);
+    const size_t moff = (tb + 255) / 256 * 256, noff = moff + mb;
+    struct device_guard {
+        int prev = -1;
+        explicit device_guard(int d)
+        {
+            if (d >= 0 && hipGetDevice(&prev) == hipSuccess && prev != d) hipSetDevice(d);
+            else prev = -1;
+        }
+        ~device_guard() { if (prev >= 0) hipSetDevice(prev); }
+    } guard(net->device);
+    void* blk = nullptr;
+    if (hipMalloc(&blk, noff + nb) != hipSuccess)
+        return rt_fail(RTSSA_E_NOMEM, "device allocation of the lazy form's rows failed");
+    if (hipMemcpy(blk, touch.data(), tb, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy((char*)blk + moff, more.data(), more.size() * 4, hipMemcpyHostToDevice) !=
+            hipSuccess ||
+        hipMemcpy((char*)blk + noff, nu.data(), nb, hipMemcpyHostToDevice) != hipSuccess) {
+        hipFree(blk);
+        return rt_fail(RTSSA_E_HIP, "copy of the lazy form's rows failed");
+    }
+    net->lazy_block = blk;
+    net->dev.touch = (const int32_t*)blk;
+    net->dev.touch_more = (const int32_t*)((char*)blk + moff);
+    net->dev.nu_fixed = (const int2*)((char*)blk + noff);
+    net->dev.nu_stride = S;
     return RTSSA_OK;
 }
 
