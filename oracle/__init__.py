@@ -82,6 +82,8 @@ def _configure(L):
                                       C.c_void_p, C.c_void_p, C.c_void_p,
                                       C.c_void_p, C.c_void_p, C.c_void_p,
                                       C.c_int32, C.POINTER(_Stats)]
+    L.rto_direct_tree_simulate.restype = C.c_int
+    L.rto_direct_tree_simulate.argtypes = L.rto_direct_simulate.argtypes
     L.rto_dm_simulate.restype = C.c_int
     L.rto_dm_simulate.argtypes = [C.POINTER(_Net), C.c_void_p, C.c_double, C.c_void_p,
                                   C.c_int32, C.c_uint64, C.c_int64, C.c_uint64,
@@ -180,10 +182,11 @@ def simulate(net, x0, t_end, sample_t, seed, R, net_id=0, traj_offset=0,
 
 
 def direct_simulate(net, x0, t_end, sample_t, seed, R, net_id=0, traj_offset=0,
-                    max_firings=10_000_000, threads=0, _lib=None):
+                    max_firings=10_000_000, threads=0, _lib=None, tree=False):
     """Run R trajectories of Gillespie's direct method with keyed draws (one
     Philox block per firing); returns a dict of arrays like simulate, without
-    T and tie_step."""
+    T and tie_step.  tree = True sums and searches on the fixed sum tree of
+    fan-out 8 instead of in channel order."""
     N, M = int(net.N), int(net.M)
     x0 = np.ascontiguousarray(x0, dtype=np.int32)
     per_traj = 1 if x0.ndim == 2 else 0
@@ -200,7 +203,9 @@ def direct_simulate(net, x0, t_end, sample_t, seed, R, net_id=0, traj_offset=0,
     )
     ns, keep = _net_struct(net)
     st = _Stats()
-    rc = (_lib or lib()).rto_direct_simulate(C.byref(ns), _ptr(x0), per_traj, float(t_end),
+    L = _lib or lib()
+    fn = L.rto_direct_tree_simulate if tree else L.rto_direct_simulate
+    rc = fn(C.byref(ns), _ptr(x0), per_traj, float(t_end),
                                              _ptr(s), G,
                                    int(seed), int(net_id), int(traj_offset), R,
                                    int(max_firings), _ptr(out["samples"]), _ptr(out["n"]),

@@ -160,7 +160,8 @@ typedef struct {
     uint8_t* status;
     uint64_t* seq_hash;
     int64_t r_begin, r_end;
-    int32_t method;             /* 0: random time (Table 2), 1: direct method, 2: lazy form */
+    int32_t method;             /* 0: random time (Table 2), 1: direct method, 2: lazy form,
+                                   3: direct method on a sum tree */
     const int32_t* dep_ptr;     /* D(mu) lists (lazy form) */
     const int32_t* dep_idx;
     int32_t B;                  /* rate breakpoints (0: constant rates) */
@@ -512,6 +513,124 @@ static void simulate_path_direct(job_t* jb, int64_t r, int32_t* X, double* a, ui
     jb->stats.status_count[st]++;
 }
 
+/* ------------------------------------------------ the direct method on a sum tree */
+/* The direct method with the total rate and the channel search taken on a
+ * fixed tree of fan-out 8 over the channels, the form in which a wavefront
+ * sums and searches in parallel.  Level 0 holds a_k (entries past M are 0);
+ * a node of level l is the sum of its 8 children of level l - 1 added
+ * pairwise, ((v0 + v1) + (v2 + v3)) + ((v4 + v5) + (v6 + v7)); the top level
+ * has one node, a_0.  The waiting time is RN(E / a_0) with E and u2 drawn as
+ * in simulate_path_direct.  The search starts at the root with r = RN(u2 a_0)
+ * and, at each node, scans its children in order: it takes the first child
+ * with v_i > 0 and r <= v_i, or the last child with v_i > 0 if r passes them
+ * all, and subtracts each child it passes, r = RN(r - v_i); at level 1 the
+ * child taken is the channel.  Same draws as simulate_path_direct, its own
+ * rounding. */
+#define DT_FAN 8
+
+/* level sizes of the tree over M leaves; returns the top level */
+static int dt_levels(int M, int* cnt)
+{
+    int L = 0;
+    cnt[0] = M > 0 ? M : 1;
+    while (cnt[L] > 1 || L == 0) {
+        cnt[L + 1] = (cnt[L] + DT_FAN - 1) / DT_FAN;
+        L++;
+    }
+    return L;
+}
+
+static double dt_node(const double* child, int n, int j)
+{
+    double v[DT_FAN];
+    for (int i = 0; i < DT_FAN; i++) v[i] = j * DT_FAN + i < n ? child[j * DT_FAN + i] : 0.0;
+    return ((v[0] + v[1]) + (v[2] + v[3])) + ((v[4] + v[5]) + (v[6] + v[7]));
+}
+
+static void simulate_path_direct_tree(job_t* jb, int64_t r, int32_t* X, double* a, uint32_t* n)
+{
+    const rto_network* net = jb->net;
+    const int N = net->N, M = net->M;
+    const uint32_t traj = (uint32_t)(jb->traj_offset + (uint64_t)r);
+    const uint32_t key[2] = { (uint32_t)jb->seed, (uint32_t)(jb->seed >> 32) };
+    int cnt[40];
+    const int top = dt_levels(M, cnt);
+    double* lev[40];
+    for (int l = 1; l <= top; l++) lev[l] = (double*)malloc(sizeof(double) * cnt[l]);
+
+    const int32_t* x0 = jb->x0 + (jb->x0_per_traj ? (size_t)r * N : 0);
+    for (int j = 0; j < N; j++) X[j] = x0[j];
+    for (int k = 0; k < M; k++) n[k] = 0;
+    double t = 0.0;
+    int32_t g = 0;
+    uint64_t fired = 0;
+    uint8_t st = RTO_OK;
+    uint64_t hash = 0xcbf29ce484222325ull;
+
+    for (;;) {
+        /* every propensity and every node again (the tree is a function of X) */
+        for (int k = 0; k < M; k++) a[k] = propensity(net, X, k);
+        if (M == 0) a[0] = 0.0;
+        for (int l = 1; l <= top; l++) {
+            const double* child = l == 1 ? a : lev[l - 1];
+            for (int j = 0; j < cnt[l]; j++) lev[l][j] = dt_node(child, cnt[l - 1], j);
+        }
+        const double a0 = lev[top][0];
+        if (a0 == 0.0) { st = RTO_ABSORBED; break; }
+        uint32_t ctr[4] = { (uint32_t)fired, 0xFFFFFFFFu, traj, jb->net_id };
+        uint32_t w[4];
+        rto_philox4x32_10(ctr, key, w);
+        uint64_t m1 = ((((uint64_t)w[1] << 32) | w[0]) >> 11);
+        uint64_t m2 = ((((uint64_t)w[3] << 32) | w[2]) >> 11);
+        double E = rto_neglog_u53(m1);
+        if (E < 0) jb->stats.hard_cases++;
+        double t_new = t + E / a0;
+        if (t_new > jb->t_end) break;
+        while (g < jb->G && jb->s[g] < t_new) { write_sample(jb, r, g, X, 0); g++; }
+        /* the search, from the root down */
+        double rem = (double)(m2 + 1) * 0x1p-53 * a0;
+        int j = 0;
+        for (int l = top; l >= 1; l--) {
+            const double* child = l == 1 ? a : lev[l - 1];
+            int last = -1;
+            for (int i = 0; i < DT_FAN; i++)
+                if (j * DT_FAN + i < cnt[l - 1] && child[j * DT_FAN + i] > 0.0) last = i;
+            int take = last;
+            for (int i = 0; i < last; i++) {
+                const double v = child[j * DT_FAN + i];
+                if (v > 0.0 && rem <= v) { take = i; break; }
+                rem = rem - v;
+            }
+            j = j * DT_FAN + take;
+        }
+        const int mu = j;
+        int ok = 1;
+        for (int e = jb->nu_ptr[mu]; e < jb->nu_ptr[mu + 1]; e++) {
+            int64_t v = (int64_t)X[jb->nu_species[e]] + jb->nu_delta[e];
+            if (v < 0 || v > INT32_MAX) ok = 0;
+        }
+        if (!ok) { st = RTO_OVERFLOW; break; }
+        t = t_new;
+        for (int e = jb->nu_ptr[mu]; e < jb->nu_ptr[mu + 1]; e++)
+            X[jb->nu_species[e]] += jb->nu_delta[e];
+        n[mu] += 1;
+        fired += 1;
+        hash = (hash ^ (uint64_t)(uint32_t)mu) * 0x100000001b3ull;
+        if (fired >= jb->max_firings) { st = RTO_MAX_FIRINGS; break; }
+    }
+
+    int bad = !(st == RTO_OK || st == RTO_ABSORBED);
+    while (g < jb->G) { write_sample(jb, r, g, X, bad); g++; }
+    for (int k = 0; k < M; k++) jb->n_out[(size_t)r * M + k] = n[k];
+    for (int j2 = 0; j2 < N; j2++) jb->x_final[(size_t)r * N + j2] = X[j2];
+    jb->t_last[r] = t;
+    jb->status[r] = st;
+    jb->seq_hash[r] = hash;
+    jb->stats.firings += fired;
+    jb->stats.status_count[st]++;
+    for (int l = 1; l <= top; l++) free(lev[l]);
+}
+
 static void* run_job(void* arg)
 {
     job_t* jb = (job_t*)arg;
@@ -526,6 +645,7 @@ static void* run_job(void* arg)
     double* tau = (double*)malloc(sizeof(double) * (M > 0 ? M : 1));
     for (int64_t r = jb->r_begin; r < jb->r_end; r++) {
         if (jb->method == 1) simulate_path_direct(jb, r, X, a, n);
+        else if (jb->method == 3) simulate_path_direct_tree(jb, r, X, a, n);
         else if (jb->method == 2) simulate_path_lazy(jb, r, X, T, P, a, inv, n, s_up, tau);
         else simulate_path(jb, r, X, T, P, a, inv, n);
     }
@@ -701,4 +821,17 @@ int rto_direct_simulate(const rto_network* net, const int32_t* x0, int32_t x0_pe
     return run_all(net, x0, x0_per_traj, t_end, sample_t, G, seed, net_id, traj_offset, R,
                    max_firings, samples, n_out, NULL, x_final, t_last, status, seq_hash,
                    NULL, nthreads, stats, 1, 0, NULL, NULL);
+}
+
+int rto_direct_tree_simulate(const rto_network* net, const int32_t* x0, int32_t x0_per_traj,
+                             double t_end, const double* sample_t, int32_t G,
+                             uint64_t seed, uint32_t net_id, uint64_t traj_offset, int64_t R,
+                             uint64_t max_firings,
+                             int32_t* samples, uint32_t* n_out, int32_t* x_final,
+                             double* t_last, uint8_t* status, uint64_t* seq_hash,
+                             int32_t nthreads, rto_stats* stats)
+{
+    return run_all(net, x0, x0_per_traj, t_end, sample_t, G, seed, net_id, traj_offset, R,
+                   max_firings, samples, n_out, NULL, x_final, t_last, status, seq_hash,
+                   NULL, nthreads, stats, 3, 0, NULL, NULL);
 }

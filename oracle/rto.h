@@ -101,6 +101,19 @@ int rto_direct_simulate(const rto_network* net, const int32_t* x0, int32_t x0_pe
                         double* t_last, uint8_t* status, uint64_t* seq_hash,
                         int32_t nthreads, rto_stats* stats);
 
+/* The direct method with a_0 and the channel search on a fixed sum tree of
+ * fan-out 8 (nodes add their children pairwise; the search scans a node's
+ * children in order, taking the first positive child with r <= v_i, else the
+ * last positive one, and subtracts the children it passes).  Same draws and
+ * arrays as rto_direct_simulate. */
+int rto_direct_tree_simulate(const rto_network* net, const int32_t* x0, int32_t x0_per_traj,
+                             double t_end, const double* sample_t, int32_t G,
+                             uint64_t seed, uint32_t net_id, uint64_t traj_offset, int64_t R,
+                             uint64_t max_firings,
+                             int32_t* samples, uint32_t* n_out, int32_t* x_final,
+                             double* t_last, uint8_t* status, uint64_t* seq_hash,
+                             int32_t nthreads, rto_stats* stats);
+
 /* Gillespie direct method with its own SplitMix64 stream: an independent
  * sampler of the same Markov jump law, used only for two-sample law tests. */
 int rto_dm_simulate(const rto_network* net, const int32_t* x0, double t_end,

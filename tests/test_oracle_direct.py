@@ -8,7 +8,13 @@ forms and exact identities, not to its own code:
   - 2A <-> B against the chemical master equation (matrix exponential);
   - Eq. 5 on every path; a two-sample test against the random-time oracle on
     Lotka-Volterra (same law, different draws);
-  - absorption, overflow, the firing cap and schedule independence."""
+  - absorption, overflow, the firing cap and schedule independence.
+Every test runs both forms: the sums and running-sum search in channel order,
+and the fixed sum tree of fan-out 8 (tree = True).  The tree form is pinned
+further by 100 independent births (each channel's count is Poisson(c_i t),
+so any bias of the tree search shows), bit equality with the channel-order
+form on one channel, and firing sequences equal to that form's on nearly
+every trajectory (the two differ only in rounding)."""
 import math
 
 import numpy as np
@@ -21,7 +27,20 @@ from paper_2103_00405_amd import workloads as W
 P_MIN = 1e-4
 
 
+TREE = False
+
+
+@pytest.fixture(params=[False, True], ids=["channel_order", "tree"], autouse=True)
+def tree(request):
+    """Runs every test of this file for both forms of the direct method."""
+    global TREE
+    TREE = request.param
+    yield request.param
+    TREE = False
+
+
 def _dm(net, x0, t_end, grid, R, seed=1, **kw):
+    kw.setdefault("tree", TREE)
     return oracle.direct_simulate(net, np.asarray(x0, np.int32), t_end,
                                   np.asarray(grid, float), seed, R, **kw)
 
@@ -135,3 +154,35 @@ def test_absorbing_overflow_cap_and_schedule():
     # the direct method's stream differs from the random-time one
     c = oracle.simulate(w.net, w.x0, 3.0, [1.0, 3.0], 1, 24)
     assert not np.array_equal(a["n"], c["n"])
+
+
+def test_independent_births_selection_law():
+    """100 pure-birth channels of different species and rates: each count is
+    Poisson(c_i t) on its own, so the channel search must pick channel i with
+    probability c_i / a_0 whatever the tree shape."""
+    M, t = 100, 2.0
+    c = 0.5 + (np.arange(M) % 13) * 0.37
+    spec = W.from_reactions(M, [({}, {i: 1}, float(c[i])) for i in range(M)])
+    o = _dm(spec, np.zeros(M, np.int32), t, [t], 3000, seed=21)
+    X = o["x_final"].astype(float)
+    m = c * t
+    z = (X.mean(axis=0) - m) / np.sqrt(m / X.shape[0])
+    assert np.abs(z).max() < 4.5, np.abs(z).max()
+    assert stats.chi2.sf(float((z ** 2).sum()), M) > P_MIN
+
+
+def test_tree_form_against_channel_order():
+    # one channel: the same arithmetic, the same bits
+    for spec, x0 in ((W.pure_birth(3.0), [0]), (W.pure_death(2.0), [30])):
+        a = _dm(spec, x0, 2.0, [1.0, 2.0], 300, seed=3, tree=False)
+        b = _dm(spec, x0, 2.0, [1.0, 2.0], 300, seed=3, tree=True)
+        for k in ("n", "samples", "seq_hash", "t_last", "status"):
+            assert np.array_equal(a[k], b[k]), k
+    # many channels: the same firing sequence on nearly every trajectory
+    rng = np.random.default_rng(11)
+    net = W.random_network(20, 60, rng, logc=(-1.0, 1.0), bimol_scale=0.05)
+    x0 = rng.integers(0, 80, size=20).astype(np.int32)
+    t_end = float(2000 / W.initial_total_rate(net, x0))
+    a = _dm(net, x0, t_end, [t_end], 128, seed=5, tree=False)
+    b = _dm(net, x0, t_end, [t_end], 128, seed=5, tree=True)
+    assert (a["seq_hash"] == b["seq_hash"]).mean() >= 0.95

@@ -90,9 +90,21 @@ LAZY_MUTANTS = {
 }
 
 
+# mistakes in the direct method on the sum tree
+TREE_DM_MUTANTS = {
+    "dt_search_no_subtract": ("                rem = rem - v;", "                rem = rem;"),
+    "dt_search_takes_last": ("if (v > 0.0 && rem <= v) { take = i; break; }",
+                             "if (0) { take = i; break; }"),
+    "dt_node_drops_child": ("return ((v[0] + v[1]) + (v[2] + v[3])) + ((v[4] + v[5]) + (v[6] + v[7]));",
+                            "return ((v[0] + v[1]) + (v[2] + v[3])) + ((v[4] + v[5]) + v[6]);"),
+    "dt_total_from_one_child": ("const double a0 = lev[top][0];",
+                                "const double a0 = top > 1 ? lev[top - 1][0] : lev[top][0];"),
+}
+
+
 def _build_mutant(tmp, name):
     old, new = (MUTANTS.get(name) or DIRECT_MUTANTS.get(name) or SCHEDULE_MUTANTS.get(name)
-                or LAZY_MUTANTS[name])
+                or LAZY_MUTANTS.get(name) or TREE_DM_MUTANTS[name])
     src = open(os.path.join(ORACLE_DIR, "rto.c")).read()
     assert src.count(old) == 1, name
     for f in ("rto.h", "dm.c"):
@@ -349,3 +361,46 @@ def test_lazy_pins_catch_planted_mistake(name):
 
 def test_lazy_pins_pass_on_the_real_oracle():
     assert _lazy_pin_failures(oracle.lib()) == []
+
+
+def _tree_dm_pin_failures(L):
+    """A quick subset of the tree direct method's pins."""
+    failed = []
+
+    def dm(net, x0, t_end, grid, R, seed=1):
+        try:
+            return oracle.direct_simulate(net, np.asarray(x0, np.int32), t_end,
+                                          np.asarray(grid, float), seed, R, _lib=L, tree=True,
+                                          max_firings=200000)
+        except RuntimeError:
+            return None
+
+    k1, k2, T = 50.0, 1.0, 2.0
+    o = dm(W.birth_death(k1, k2), [0], T, [T], 8000, seed=5)
+    m = k1 / k2 * (1 - math.exp(-k2 * T))
+    if o is None or abs(o["x_final"][:, 0].mean() - m) > 4.5 * math.sqrt(m / 8000):
+        failed.append("bd_law")
+    M, t = 100, 2.0
+    c = 0.5 + (np.arange(M) % 13) * 0.37
+    spec = W.from_reactions(M, [({}, {i: 1}, float(c[i])) for i in range(M)])
+    o = dm(spec, np.zeros(M, np.int32), t, [t], 3000, seed=21)
+    if o is None:
+        failed.append("births_run")
+    else:
+        z = (o["x_final"].mean(axis=0) - c * t) / np.sqrt(c * t / 3000)
+        if np.abs(z).max() >= 4.5 or stats.chi2.sf(float((z ** 2).sum()), M) <= 1e-4:
+            failed.append("births_selection")
+    return failed
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("name", sorted(TREE_DM_MUTANTS))
+def test_tree_dm_pins_catch_planted_mistake(name):
+    with tempfile.TemporaryDirectory() as tmp:
+        L = _build_mutant(tmp, name)
+        failed = _tree_dm_pin_failures(L)
+    assert failed, "mutant %s passed every pin" % name
+
+
+def test_tree_dm_pins_pass_on_the_real_oracle():
+    assert _tree_dm_pin_failures(oracle.lib()) == []
