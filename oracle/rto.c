@@ -445,12 +445,25 @@ static void simulate_path_lazy(job_t* jb, int64_t r, int32_t* X, double* T, doub
  * time's u, words 3:2 the search's u, each u = (m + 1) 2^-53 with m the top
  * 53 bits.  The second counter word is never a channel index of the random
  * time draws, so the two methods' streams do not overlap. */
+/* The two numbers of one direct-method firing from its Philox block: returns
+ * E = RN(-ln u1) (-1 for a hard case) and sets *m2, the search's 53 bits. */
+static double direct_draws(const job_t* jb, uint32_t traj, uint64_t fired, uint64_t* m2_out)
+{
+    const uint32_t key[2] = { (uint32_t)jb->seed, (uint32_t)(jb->seed >> 32) };
+    uint32_t ctr[4] = { (uint32_t)fired, 0xFFFFFFFFu, traj, jb->net_id };
+    uint32_t w[4];
+    rto_philox4x32_10(ctr, key, w);
+    uint64_t m1 = ((((uint64_t)w[1] << 32) | w[0]) >> 11);
+    uint64_t m2 = ((((uint64_t)w[3] << 32) | w[2]) >> 11);
+    *m2_out = m2;
+    return rto_neglog_u53(m1);
+}
+
 static void simulate_path_direct(job_t* jb, int64_t r, int32_t* X, double* a, uint32_t* n)
 {
     const rto_network* net = jb->net;
     const int N = net->N, M = net->M;
     const uint32_t traj = (uint32_t)(jb->traj_offset + (uint64_t)r);
-    const uint32_t key[2] = { (uint32_t)jb->seed, (uint32_t)(jb->seed >> 32) };
 
     const int32_t* x0 = jb->x0 + (jb->x0_per_traj ? (size_t)r * N : 0);
     for (int j = 0; j < N; j++) X[j] = x0[j];
@@ -468,12 +481,8 @@ static void simulate_path_direct(job_t* jb, int64_t r, int32_t* X, double* a, ui
             a0 += a[k];
         }
         if (a0 == 0.0) { st = RTO_ABSORBED; break; }
-        uint32_t ctr[4] = { (uint32_t)fired, 0xFFFFFFFFu, traj, jb->net_id };
-        uint32_t w[4];
-        rto_philox4x32_10(ctr, key, w);
-        uint64_t m1 = ((((uint64_t)w[1] << 32) | w[0]) >> 11);
-        uint64_t m2 = ((((uint64_t)w[3] << 32) | w[2]) >> 11);
-        double E = rto_neglog_u53(m1);
+        uint64_t m2;
+        double E = direct_draws(jb, traj, fired, &m2);
         if (E < 0) jb->stats.hard_cases++;
         double tau = E / a0;
         double t_new = t + tau;
@@ -552,7 +561,6 @@ static void simulate_path_direct_tree(job_t* jb, int64_t r, int32_t* X, double* 
     const rto_network* net = jb->net;
     const int N = net->N, M = net->M;
     const uint32_t traj = (uint32_t)(jb->traj_offset + (uint64_t)r);
-    const uint32_t key[2] = { (uint32_t)jb->seed, (uint32_t)(jb->seed >> 32) };
     int cnt[40];
     const int top = dt_levels(M, cnt);
     double* lev[40];
@@ -577,12 +585,8 @@ static void simulate_path_direct_tree(job_t* jb, int64_t r, int32_t* X, double* 
         }
         const double a0 = lev[top][0];
         if (a0 == 0.0) { st = RTO_ABSORBED; break; }
-        uint32_t ctr[4] = { (uint32_t)fired, 0xFFFFFFFFu, traj, jb->net_id };
-        uint32_t w[4];
-        rto_philox4x32_10(ctr, key, w);
-        uint64_t m1 = ((((uint64_t)w[1] << 32) | w[0]) >> 11);
-        uint64_t m2 = ((((uint64_t)w[3] << 32) | w[2]) >> 11);
-        double E = rto_neglog_u53(m1);
+        uint64_t m2;
+        double E = direct_draws(jb, traj, fired, &m2);
         if (E < 0) jb->stats.hard_cases++;
         double t_new = t + E / a0;
         if (t_new > jb->t_end) break;
