@@ -114,7 +114,22 @@ typedef struct {
  * call on the same network from a second host thread.  Its channel workspace
  * (36 bytes per channel per resident wavefront) is allocated stream-ordered
  * by the call. */
-enum { RTSSA_METHOD_RANDOM_TIME = 0, RTSSA_METHOD_DIRECT = 1, RTSSA_METHOD_LAZY = 2 };
+/* DIRECT_TREE is the direct method with a_0 and the channel search on a
+ * fixed sum tree of fan-out 8 over the channels (entries past M are 0; a
+ * node adds its children pairwise, ((v0 + v1) + (v2 + v3)) + ((v4 + v5) +
+ * (v6 + v7))), run like LAZY with one wavefront per trajectory for large
+ * networks: tau = RN(E / a_0) with DIRECT's draws; the search starts at the
+ * root with r = RN(u2 a_0) and at each node takes the first child with
+ * v_i > 0 and r <= v_i (the last positive child if none), subtracting each
+ * child it passes, r = RN(r - v_i).  Same law as DIRECT, its own rounding.
+ * As DIRECT: T_out and tie_step must be NULL; as LAZY: mapping AUTO or
+ * WAVE, no rate schedule, the same LDS limit and first-run rows. */
+enum {
+    RTSSA_METHOD_RANDOM_TIME = 0,
+    RTSSA_METHOD_DIRECT = 1,
+    RTSSA_METHOD_LAZY = 2,
+    RTSSA_METHOD_DIRECT_TREE = 3
+};
 
 typedef struct {
     uint64_t max_firings;  /* per trajectory; 0 = 10^7; at most 2^32 - 1 */

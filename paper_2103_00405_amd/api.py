@@ -16,7 +16,7 @@ from . import _lib
 from ._lib import Options, Stats, check, lib
 
 MAP_AUTO, MAP_THREAD, MAP_WAVE, MAP_WORKGROUP = 0, 1, 2, 3
-METHOD_RANDOM_TIME, METHOD_DIRECT, METHOD_LAZY = 0, 1, 2
+METHOD_RANDOM_TIME, METHOD_DIRECT, METHOD_LAZY, METHOD_DIRECT_TREE = 0, 1, 2, 3
 TRAJ_OK, TRAJ_ABSORBED, TRAJ_OVERFLOW, TRAJ_MAX_FIRINGS = 0, 1, 2, 3
 TIE_NONE = 0xFFFFFFFF
 
@@ -117,8 +117,9 @@ def simulate(net: Network, x0, t_end: float, sample_t, R: int, seed: int = 1, ne
     mapping only; it has no T or tie_step outputs, which are then dropped from
     ``want``); METHOD_LAZY runs the lazy form for large networks (one
     wavefront per trajectory, dependency-graph updates, a minimum tree in
-    LDS)."""
-    if method == METHOD_DIRECT:
+    LDS); METHOD_DIRECT_TREE the direct method on a sum tree in the same
+    mapping (no T or tie_step either)."""
+    if method in (METHOD_DIRECT, METHOD_DIRECT_TREE):
         want = tuple(k for k in want if k not in ("T", "tie_step"))
     dev = net.device
     N, M, R = net.N, net.M, int(R)

@@ -186,15 +186,19 @@ extern "C" int rtssa_simulate(const rtssa_network* net, const int32_t* x0, int32
     int rc = rt_check_run(net, x0, x0_per_traj, t_end, sample_t, G, traj_offset, R, stream);
     if (rc) return rc;
     if (o.method != RTSSA_METHOD_RANDOM_TIME && o.method != RTSSA_METHOD_DIRECT &&
-        o.method != RTSSA_METHOD_LAZY)
+        o.method != RTSSA_METHOD_LAZY && o.method != RTSSA_METHOD_DIRECT_TREE)
         return rt_fail(RTSSA_E_INVALID, "unknown method");
-    if (o.method == RTSSA_METHOD_LAZY) {
+    const bool wave_tree = o.method == RTSSA_METHOD_LAZY || o.method == RTSSA_METHOD_DIRECT_TREE;
+    if (o.method == RTSSA_METHOD_DIRECT_TREE && (T_out || tie_step))
+        return rt_fail(RTSSA_E_INVALID, "the direct method has no internal times or near-ties: "
+                                        "T_out and tie_step must be NULL");
+    if (wave_tree) {
         if (net->dev.sched_B > 0)
-            return rt_fail(RTSSA_E_UNSUPPORTED, "the lazy form takes no rate schedule");
+            return rt_fail(RTSSA_E_UNSUPPORTED, "the tree methods take no rate schedule");
         if (o.mapping != RTSSA_MAP_AUTO && o.mapping != RTSSA_MAP_WAVE)
-            return rt_fail(RTSSA_E_UNSUPPORTED, "the lazy form runs one wavefront per trajectory");
+            return rt_fail(RTSSA_E_UNSUPPORTED, "the tree methods run one wavefront per trajectory");
         if (o.block != 0 && o.block != 64)
-            return rt_fail(RTSSA_E_INVALID, "the lazy form's block is 64 lanes");
+            return rt_fail(RTSSA_E_INVALID, "the tree methods' block is 64 lanes");
         if (net->max_nu > 64)
             return rt_fail(RTSSA_E_UNSUPPORTED, "a reaction changes more than 64 species");
         if (R > 0) {
@@ -210,13 +214,14 @@ extern "C" int rtssa_simulate(const rtssa_network* net, const int32_t* x0, int32
                                             "T_out and tie_step must be NULL");
         if (!rt_thread_supported(net->M, net->N) ||
             (o.mapping != RTSSA_MAP_AUTO && o.mapping != RTSSA_MAP_THREAD))
-            return rt_fail(RTSSA_E_UNSUPPORTED, "the direct method runs only in the thread mapping "
-                                                "(M, N <= 8)");
+            return rt_fail(RTSSA_E_UNSUPPORTED, "the channel-order direct method runs only in the "
+                                                "thread mapping (M, N <= 8); "
+                                                "RTSSA_METHOD_DIRECT_TREE runs larger networks");
     }
     if (R == 0) return RTSSA_OK;
     int mapping = o.method == RTSSA_METHOD_DIRECT
                       ? RTSSA_MAP_THREAD
-                      : (o.method == RTSSA_METHOD_LAZY
+                      : (wave_tree
                              ? RTSSA_MAP_WAVE
                              : (o.mapping == RTSSA_MAP_AUTO ? rt_auto_mapping(net) : o.mapping));
 
@@ -251,6 +256,9 @@ extern "C" int rtssa_simulate(const rtssa_network* net, const int32_t* x0, int32
     if (!rc && o.method == RTSSA_METHOD_LAZY) {
         block_used = 64;
         rc = rt_launch_lazy(C, net->N, net->M, o.grid, R, stream, &grid_used);
+    } else if (!rc && o.method == RTSSA_METHOD_DIRECT_TREE) {
+        block_used = 64;
+        rc = rt_launch_dmtree(C, net->N, net->M, o.grid, R, stream, &grid_used);
     } else if (!rc) {
         rc = rt_launch_class(mapping, net->M, net->N, net->max_nu, C, o.block, o.grid, R, stream,
                              &block_used, &grid_used, o.method);

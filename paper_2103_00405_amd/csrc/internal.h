@@ -162,6 +162,9 @@ int rt_launch_subwave(int max_M, const rt_class_dev& C, int L, int grid, hipStre
 int rt_launch_lazy(const rt_class_dev& C, int max_N, int max_M, int grid, int64_t units,
                    hipStream_t stream, int* grid_used);
 size_t rt_lazy_lds_bytes(int N, int M);
+// the direct method on a sum tree (same mapping and layout as the lazy form)
+int rt_launch_dmtree(const rt_class_dev& C, int max_N, int max_M, int grid, int64_t units,
+                     hipStream_t stream, int* grid_used);
 // builds and uploads the lazy form's rows of a network once (network.cpp)
 int rt_lazy_prepare(rtssa_network* net);
 int rt_subwave_slots(int M, int L);

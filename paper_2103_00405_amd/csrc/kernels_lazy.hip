@@ -454,6 +454,251 @@ __global__ __launch_bounds__(64) void rt_lazy_kernel(rt_class_dev C, rt_lazy_rec
     }
 }
 
+// ---------------------------------------------------------------------------
+// The direct method on a sum tree (Gillespie's method, section 3, Eq. 17-22,
+// with a_0 and the channel search on a fixed tree of fan-out 8), in the same
+// mapping as the lazy form: one wavefront per trajectory, the tree in LDS
+// (leaves a_k, padding 0; a node adds its 8 children pairwise,
+// ((v0 + v1) + (v2 + v3)) + ((v4 + v5) + (v6 + v7)); the root is a_0).  A
+// firing: tau = RN(E / a_0) from the firing's Philox block (counter (firing
+// index, 0xFFFFFFFF, trajectory, net_id)); the search walks down from the
+// root with r = RN(u2 a_0), taking at each node the first positive child with
+// r <= v_i (the last positive child if r passes them all) and subtracting the
+// children it passes; then mu's jump, the new propensities of mu and D(mu),
+// and their ancestors' sums.  A firing's draws do not depend on the state, so
+// the next firing's block and logarithm are computed while this firing's
+// loads are in flight.
+
+static_assert(kFan == 8, "the sum tree adds 8 children pairwise");
+
+__device__ __forceinline__ double dt_sum_node(const lazy_tree& tr, int l, int j)
+{
+    const double2* v = (const double2*)(tr.d[l - 1] + (j << 3));
+    const double2 a = v[0], b = v[1], c = v[2], d = v[3];
+    return ((a.x + a.y) + (b.x + b.y)) + ((c.x + c.y) + (d.x + d.y));
+}
+
+// E = RN(-ln u1) and the search's 53 bits of firing `fired`, every lane alike.
+__device__ __forceinline__ double dt_draw(uint32_t key0, uint32_t key1, uint32_t traj,
+                                          uint32_t net_id, uint32_t fired, uint64_t* m2,
+                                          unsigned long long* slow, uint32_t* sc)
+{
+    const rt_u4 w = rt_philox4x32_10(rt_u4{fired, 0xFFFFFFFFu, traj, net_id}, key0, key1);
+    *m2 = (((uint64_t)w.w << 32) | w.z) >> 11;
+    return rt_neglog_uniform((((uint64_t)w.y << 32) | w.x) >> 11, slow, sc);
+}
+
+__global__ __launch_bounds__(64) void rt_dmtree_kernel(rt_class_dev C)
+{
+    extern __shared__ int32_t dyn_lds[];
+    __shared__ uint32_t log_scratch[RT_LOG_SCRATCH];
+    rt_ws* const ws = C.ws;
+    const uint32_t key0 = ws->key0, key1 = ws->key1;
+    const int lane = threadIdx.x;
+    const rt_cptr<int64_t> unit_start = rt_const(C.unit_start);
+    const int64_t total = unit_start[C.count];
+
+    for (;;) {
+        unsigned long long u = 0;
+        if (lane == 0) u = atomicAdd(&ws->next_unit, 1ull);
+        u = __shfl(u, 0, 64);
+        if ((int64_t)u >= total) break;
+        const int item = __builtin_amdgcn_readfirstlane(find_item(unit_start, C.count, (int64_t)u));
+        const rt_cptr<rt_item_dev> it = rt_const(C.items) + item;
+        const rt_net_dev net = it->net;
+        const int N = net.N, M = net.M;
+        const rt_cptr<int2> react = rt_const(net.react);
+        const rt_cptr<double> cc = rt_const(net.c);
+        const rt_cptr<int32_t> dep_ptr = rt_const(net.dep_ptr), dep_idx = rt_const(net.dep_idx);
+        const rt_cptr<int32_t> touch = rt_const(net.touch), touch_more = rt_const(net.touch_more);
+        const rt_cptr<int2> nu_fixed = rt_const(net.nu_fixed);
+        const int nu_stride = net.nu_stride;
+        const int64_t r = (int64_t)u - unit_start[item];
+        const uint32_t traj = it->traj_offset + (uint32_t)r;
+        const uint32_t net_id = it->net_id;
+        const double t_end = it->t_end;
+        uint32_t* const n_row = it->n_out ? it->n_out + r * M : nullptr;
+
+        // LDS: X, the leaves a_k, the node levels (the lazy form's layout;
+        // the channel arrays are unused)
+        lazy_tree tr;
+        int32_t* X = dyn_lds;
+        {
+            char* p = (char*)(dyn_lds + ((N + 3) & ~3));
+            tr.cnt[0] = M > 0 ? M : 1;
+            tr.d[0] = (double*)p;
+            tr.kk[0] = nullptr;
+            p += 8 * padf(tr.cnt[0]);
+            tr.top = 0;
+#pragma unroll
+            for (int l = 1; l <= kMaxLevels; ++l) {
+                tr.cnt[l] = (tr.cnt[l - 1] + kFan - 1) >> kFanLog;
+                const int P = tr.top == 0 ? padf(tr.cnt[l]) : 0;
+                tr.d[l] = (double*)p;
+                tr.kk[l] = (int32_t*)(p + 8 * P);
+                p += 12 * P;
+                if (tr.top == 0 && tr.cnt[l] == 1) tr.top = l;
+            }
+        }
+        const int top = tr.top;
+        double* const leaves = tr.d[0];
+        double* root_d = tr.d[1];
+#pragma unroll
+        for (int l = 2; l <= kMaxLevels; ++l) root_d = l == top ? tr.d[l] : root_d;
+
+        // ---- initial state: X, the propensities, every node, zero counts
+        const int32_t* x0 = it->x0 + (it->x0_per_traj ? r * N : 0);
+        for (int j = lane; j < N; j += 64) X[j] = x0[j];
+        wave_lds_fence();
+        for (int k = lane; k < padf(tr.cnt[0]); k += 64)
+            leaves[k] = k < M ? lazy_propensity(react[k], cc[k], X) : 0.0;
+#pragma unroll
+        for (int l = 1; l <= kMaxLevels; ++l) {
+            if (l > top) break;
+            for (int j = tr.cnt[l] + lane; j < padf(tr.cnt[l]); j += 64) tr.d[l][j] = 0.0;
+        }
+        wave_lds_fence();
+#pragma unroll
+        for (int l = 1; l <= kMaxLevels; ++l) {
+            if (l > top) break;
+            for (int j = lane; j < tr.cnt[l]; j += 64) tr.d[l][j] = dt_sum_node(tr, l, j);
+            wave_lds_fence();
+        }
+        if (n_row) {
+            for (int k = lane; k < M; k += 64) n_row[k] = 0u;
+            __threadfence();                               // before the counts' atomics
+        }
+        double a0 = *root_d;
+        uint64_t m2 = 0;
+        double E1 = dt_draw(key0, key1, traj, net_id, 0u, &m2, &ws->slow_logs, log_scratch);
+
+        double t = 0.0, s_next = it->G > 0 ? rt_const(it->s)[0] : __builtin_inf();
+        int32_t g = 0;
+        uint32_t fired = 0;
+        unsigned long long hash = kFnvOffset;
+        int st = RTSSA_TRAJ_OK;
+
+        for (;;) {
+            if (a0 == 0.0) { st = RTSSA_TRAJ_ABSORBED; break; }
+            const double t_new = t + E1 / a0;
+            if (t_new > t_end) break;
+            while (s_next < t_new) {
+                if (it->samples) {
+                    int32_t* dst = it->samples + r * it->ss_r + (int64_t)g * it->ss_g;
+                    for (int j = lane; j < N; j += 64) dst[j * it->ss_n] = X[j];
+                }
+                ++g;
+                s_next = g < it->G ? rt_const(it->s)[g] : __builtin_inf();
+            }
+            // ---- the search, from the root down (every lane alike)
+            double rem = (double)(m2 + 1) * 0x1p-53 * a0;
+            int j = 0;
+#pragma unroll
+            for (int l = kMaxLevels; l >= 1; --l) {
+                if (l > top) continue;
+                const double2* vd = (const double2*)(tr.d[l - 1] + (j << 3));
+                double v[8];
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    const double2 x = vd[i];
+                    v[2 * i] = x.x;
+                    v[2 * i + 1] = x.y;
+                }
+                int last = 0;
+#pragma unroll
+                for (int i = 0; i < 8; ++i) last = v[i] > 0.0 ? i : last;
+                int take = last;
+                bool found = false;
+#pragma unroll
+                for (int i = 0; i < 8; ++i) {
+                    const bool hit = !found && v[i] > 0.0 && (rem <= v[i] || i == last);
+                    take = hit ? i : take;
+                    rem = found || hit ? rem : rem - v[i];
+                    found = found || hit;
+                }
+                j = __builtin_amdgcn_readfirstlane((j << 3) + take);
+            }
+            const int mu = j;
+            // ---- mu's fixed-stride rows, then the touched channels' data
+            const int n_other = touch[mu * 64];
+            const int tv = touch[mu * 64 + lane];
+            const int2 nv = nu_fixed[mu * nu_stride + min(lane, nu_stride - 1)];
+            const bool has_nu = lane < nu_stride && nv.x >= 0;
+            const int sp = max(nv.x, 0), dl = nv.y;
+            const bool act = lane == 0 || tv >= 0;
+            const int k = lane == 0 || !act ? mu : tv;
+            const int2 rr0 = react[k];
+            const double c0 = cc[k];
+            // the next firing's draws while the loads are in flight
+            uint64_t m2n;
+            const double E1n = dt_draw(key0, key1, traj, net_id, fired + 1u, &m2n,
+                                       &ws->slow_logs, log_scratch);
+            // ---- the jump v_mu, checked against [0, 2^31 - 1]
+            const int64_t xv = (int64_t)X[sp] + dl;
+            const bool okl = !has_nu || (xv >= 0 && xv <= 0x7FFFFFFF);
+            if (__ballot(!okl) != 0ull) { st = RTSSA_TRAJ_OVERFLOW; break; }
+            if (has_nu) X[sp] = (int32_t)xv;
+            wave_lds_fence();
+            // ---- new propensities (mu and D(mu)) and their ancestors' sums
+            if (act) leaves[k] = lazy_propensity(rr0, c0, X);
+            wave_lds_fence();
+#pragma unroll
+            for (int l = 1; l <= kMaxLevels; ++l) {
+                if (l > top) break;
+                const int jn = k >> (kFanLog * l);
+                const double v = dt_sum_node(tr, l, jn);
+                tr.d[l][jn] = v;
+                a0 = l == top ? v : a0;
+                wave_lds_fence();
+            }
+            if (n_other > 63) {
+                const int de = dep_ptr[mu + 1];
+                for (int q0 = touch_more[mu]; q0 < de; q0 += 64) {
+                    const int q = q0 + lane;
+                    int k2 = q < de ? dep_idx[q] : -1;
+                    if (k2 == mu) k2 = -1;
+                    if (k2 >= 0) leaves[k2] = lazy_propensity(react[k2], cc[k2], X);
+                    wave_lds_fence();
+#pragma unroll
+                    for (int l = 1; l <= kMaxLevels; ++l) {
+                        if (l > top) break;
+                        const int jn = (k2 >= 0 ? k2 : mu) >> (kFanLog * l);
+                        const double v = dt_sum_node(tr, l, jn);
+                        tr.d[l][jn] = v;
+                        a0 = l == top ? v : a0;
+                        wave_lds_fence();
+                    }
+                }
+            }
+            if (n_row && lane == 0) atomicAdd(&n_row[mu], 1u);
+            t = t_new;
+            ++fired;
+            hash = (hash ^ (unsigned long long)(uint32_t)mu) * kFnvPrime;
+            E1 = E1n;
+            m2 = m2n;
+            if (fired >= C.max_firings) { st = RTSSA_TRAJ_MAX_FIRINGS; break; }
+        }
+
+        const bool good = st == RTSSA_TRAJ_OK || st == RTSSA_TRAJ_ABSORBED;
+        if (it->samples) {
+            for (; g < it->G; ++g) {
+                int32_t* dst = it->samples + r * it->ss_r + (int64_t)g * it->ss_g;
+                for (int j = lane; j < N; j += 64) dst[j * it->ss_n] = good ? X[j] : -1;
+            }
+        }
+        if (it->x_final)
+            for (int j = lane; j < N; j += 64) it->x_final[r * N + j] = X[j];
+        if (lane == 0) {
+            if (it->t_last) it->t_last[r] = t;
+            if (it->status) it->status[r] = (uint8_t)st;
+            if (it->seq_hash) it->seq_hash[r] = hash;
+            atomicAdd(&ws->firings, (unsigned long long)fired);
+            atomicAdd(&ws->status_count[st], 1ull);
+        }
+        wave_lds_fence();                                  // X and the tree are reused
+    }
+}
+
 }  // namespace
 
 // LDS bytes of one trajectory: X, the leaves and every node level (arrays
@@ -512,4 +757,35 @@ int rt_launch_lazy(const rt_class_dev& C, int max_N, int max_M, int grid, int64_
     if (hipFreeAsync(wsp, stream) != hipSuccess && !rc)
         rc = rt_fail(RTSSA_E_HIP, "freeing the lazy workspace failed");
     return rc;
+}
+
+int rt_launch_dmtree(const rt_class_dev& C, int max_N, int max_M, int grid, int64_t units,
+                     hipStream_t stream, int* grid_used)
+{
+    const size_t lds = rt_lazy_lds_bytes(max_N, max_M);
+    if (lds == 0) return rt_fail(RTSSA_E_UNSUPPORTED, "network too large for the sum tree");
+    int dev = 0, lds_max = 0, cus = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) !=
+            hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+        return rt_fail(RTSSA_E_HIP, "device query failed");
+    if (lds + RT_LOG_SCRATCH * 4 > (size_t)lds_max)
+        return rt_fail(RTSSA_E_UNSUPPORTED, "network too large for the sum tree in LDS");
+    if (lds > 48 * 1024 &&
+        hipFuncSetAttribute((const void*)rt_dmtree_kernel,
+                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess)
+        return rt_fail(RTSSA_E_HIP, "cannot raise the LDS limit");
+    if (grid <= 0) {
+        int per_cu = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, rt_dmtree_kernel, 64, lds) !=
+                hipSuccess || per_cu < 1)
+            per_cu = 1;
+        grid = cus * per_cu;
+    }
+    if ((int64_t)grid > units) grid = (int)std::max<int64_t>(units, 1);
+    if (grid_used) *grid_used = grid;
+    hipLaunchKernelGGL(rt_dmtree_kernel, dim3(grid), dim3(64), lds, stream, C);
+    return hipGetLastError() == hipSuccess ? RTSSA_OK
+                                           : rt_fail(RTSSA_E_HIP, "sum-tree kernel launch failed");
 }
