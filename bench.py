@@ -105,6 +105,8 @@ def run_ensemble(api, w, steps, warmup, block=0, grid=0, mapping=0, method=0):
         "x_final": torch.empty((R, N), dtype=torch.int32, device=dev),
         "status": torch.empty((R,), dtype=torch.uint8, device=dev),
     }
+    if method in (api.METHOD_DIRECT, api.METHOD_DIRECT_TREE):
+        del out["T"]                      # the direct method has no internal times
     x0 = torch.tensor(w.x0, dtype=torch.int32, device=dev)
     s = torch.tensor(w.sample_t, dtype=torch.float64, device=dev)
 
@@ -243,6 +245,13 @@ def bench_large_lazy(api, W, steps, warmup, eager_value=None):
            r["firings_per_step"]}
     if eager_value:
         out["vs_eager"] = out["value"] / eager_value
+    # Gillespie's direct method in the same mapping (sum tree of fan-out 8):
+    # the paper's comparison of one reduction against a sum and a search
+    d = run_ensemble(api, w, steps, warmup, method=api.METHOD_DIRECT_TREE)
+    out["direct_tree"] = {"value": d["firings"] / d["wall"], "unit": "firings/s",
+                          "kernel_ms": d["kernel_s"] * 1e3,
+                          "firings_per_step": d["firings_per_step"]}
+    out["random_time_vs_direct"] = out["value"] / out["direct_tree"]["value"]
     return out
 
 
