@@ -7,13 +7,17 @@ A step is one full ensemble simulation (every trajectory to t_end) with all
 outputs written to HBM; inputs are resident before the timed region.
 
 Secondary measurements (attached to the same JSON line, or alone with
---workload): the large random network (N = 1000, M = 4000, 512 trajectories,
-workgroup mapping) and the gradient form (score-function gradient evals/s
-against plain expectation evals/s and against coupled finite differences at
-equal standard error, birth-death and Lotka-Volterra, 2^18 trajectories).
+--workload): the small parity case; Gillespie's direct method on the headline
+ensemble (direct); the large random network (N = 1000, M = 4000, 512
+trajectories: eager workgroup kernel, lazy form, direct method on a sum tree;
+large_random); piecewise-constant rates on the Lotka-Volterra model
+(schedule); the gradient form (score-function gradient evals/s against plain
+expectation evals/s and against coupled finite differences at equal standard
+error, birth-death and Lotka-Volterra, 2^18 trajectories; gradient); the
+batched form (4096 networks in one captured graph; batched).
 
     python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu-baseline]
-                    [--workload lv_ensemble|large_random|gradient|all]
+                    [--workload all|lv_ensemble|direct|large_random|schedule|gradient|batched]
 """
 import argparse
 import json
@@ -60,7 +64,7 @@ def parse():
     ap.add_argument("--trajectories", type=int, default=1 << 20)
     ap.add_argument("--workload", default="all",
                     choices=["all", "lv_ensemble", "large_random", "gradient", "batched",
-                             "direct"])
+                             "direct", "schedule"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--block", type=int, default=0)
@@ -165,6 +169,41 @@ def bench_lv_small(api, W, reps=5):
     return {"workload": "lotka_volterra_small", "trajectories": w.R, "t_end": w.t_end,
             "grid_points": len(w.sample_t), "firings_per_launch": fir,
             "kernel_ms": min(kms), "mapping": "thread"}
+
+
+def bench_schedule(api, W, R=1 << 18, reps=2):
+    """Piecewise-constant rates (Eq. 28 solved piece by piece) on the
+    Lotka-Volterra ensemble's model (2^18 trajectories, t_end 5): the rates
+    switch at t = 1, 2, 3, 4 (each piece scales c by 0.5..1.5); firings/s
+    with the schedule and without it, thread mapping both."""
+    import numpy as np
+    import torch
+    w = W.lv_ensemble(R)
+    x0 = torch.tensor(w.x0, dtype=torch.int32, device="cuda")
+    s = torch.tensor(w.sample_t, dtype=torch.float64, device="cuda")
+    times = np.array([1.0, 2.0, 3.0, 4.0])
+    scale = np.array([[1.5, 0.8, 1.2], [0.5, 1.0, 0.7], [1.0, 1.4, 1.0], [1.3, 0.6, 1.5]])
+    res = {}
+    for tag in ("constant", "schedule"):
+        net = api.Network(w.net)
+        if tag == "schedule":
+            net.set_schedule(times, scale * np.asarray(w.net.c)[None, :])
+        out = {"samples": torch.empty((R, len(w.sample_t), 2), dtype=torch.int32, device="cuda"),
+               "n": torch.empty((R, 3), dtype=torch.int32, device="cuda"),
+               "T": torch.empty((R, 3), dtype=torch.float64, device="cuda")}
+        api.simulate(net, x0, w.t_end, s, R, seed=w.seed, out=out, want=tuple(out))
+        fir, ms = 0, 0.0
+        for _ in range(reps):
+            st = api.simulate(net, x0, w.t_end, s, R, seed=w.seed, out=out, want=tuple(out))["stats"]
+            fir += st["firings"]
+            ms += st["kernel_ms"]
+        res[tag] = {"value": fir / (ms / 1e3), "unit": "firings/s (kernel time)",
+                    "kernel_ms": ms / reps, "firings_per_launch": fir / reps}
+    res["workload"] = "lotka_volterra_rate_schedule"
+    res["trajectories"] = R
+    res["breakpoints"] = [float(v) for v in times]
+    res["schedule_vs_constant"] = res["schedule"]["value"] / res["constant"]["value"]
+    return res
 
 
 def bench_direct(api, W, steps=2, warmup=1, R=1 << 20):
@@ -431,8 +470,10 @@ def main():
 
     from paper_2103_00405_amd import api, workloads as W
 
-    if args.workload in ("large_random", "gradient", "batched", "direct"):
-        if args.workload == "direct":
+    if args.workload in ("large_random", "gradient", "batched", "direct", "schedule"):
+        if args.workload == "schedule":
+            out = bench_schedule(api, W)
+        elif args.workload == "direct":
             out = bench_direct(api, W, args.steps, args.warmup)
         elif args.workload == "large_random":
             out = bench_large(api, W, args.steps, args.warmup)
@@ -493,6 +534,7 @@ def main():
                             "direct_method": direct,
                             "large_random": large,
                             "large_random_lazy": bench_large_lazy(api, W, 2, 1, large["value"]),
+                            "rate_schedule": bench_schedule(api, W),
                             "gradient": bench_gradient(api, W),
                             "batched": bench_batched(api, W, 2, cpu_s=cs)}
     if not args.no_cpu_baseline:
