@@ -268,7 +268,7 @@ typedef struct {
     double t_end;
     const double* sample_t;
     uint32_t net_id;
-    int32_t reserved;
+    int32_t method;        /* RTSSA_METHOD_RANDOM_TIME (0), _LAZY or _DIRECT_TREE */
     uint64_t traj_offset;
     int64_t R;
     int32_t* samples;
@@ -288,6 +288,11 @@ int rtssa_batch_create(const rtssa_batch_item* items, int32_t count, const rtssa
                        const char* plan_path, rtssa_batch** out);
 int rtssa_batch_run(rtssa_batch* batch, uint64_t seed, int32_t use_graph, rtssa_stream_t stream,
                     rtssa_stats* stats);
+/* Items may choose their method: RANDOM_TIME items are classed by mapping as
+ * above; LAZY and DIRECT_TREE items (each with the same conditions as in
+ * rtssa_simulate) form classes of their own, run one wavefront per trajectory
+ * (reported as mapping RTSSA_MAP_WAVE, 64 lanes); the lazy form's channel
+ * workspace is allocated by rtssa_batch_create.  opt->method must be 0. */
 /* cls < 0: *n_items receives the number of classes; else the class's
  * mapping, lanes per trajectory (1 for the thread mapping), items,
  * trajectories and largest channel count. */

@@ -36,7 +36,7 @@ class Options(C.Structure):
 
 class BatchItem(C.Structure):
     _fields_ = [("net", vp), ("x0", vp), ("x0_per_traj", i32), ("G", i32), ("t_end", f64),
-                ("sample_t", vp), ("net_id", u32), ("reserved", i32), ("traj_offset", u64),
+                ("sample_t", vp), ("net_id", u32), ("method", i32), ("traj_offset", u64),
                 ("R", i64), ("samples", vp), ("s_stride_r", i64), ("s_stride_g", i64),
                 ("s_stride_n", i64), ("n_out", vp), ("T_out", vp), ("x_final", vp),
                 ("t_last", vp), ("status", vp), ("seq_hash", vp), ("tie_step", vp)]

@@ -212,8 +212,10 @@ class Batch:
     """Many independent networks run by one persistent launch per size class
     (captured once into a hipGraph and replayed).  ``jobs`` is a list of dicts
     with keys net (Network), x0, t_end, sample_t, R and optionally net_id,
-    traj_offset; outputs are allocated here (per job: samples, n, T, x_final,
-    t_last, status, seq_hash, tie_step) and returned by ``run``."""
+    traj_offset, method (METHOD_RANDOM_TIME, METHOD_LAZY or
+    METHOD_DIRECT_TREE; the last has no T or tie_step); outputs are allocated
+    here (per job: samples, n, T, x_final, t_last, status, seq_hash, tie_step)
+    and returned by ``run``."""
 
     def __init__(self, jobs, max_firings=10_000_000, mapping=MAP_AUTO, plan_path=None,
                  want=("samples", "n", "T", "x_final", "t_last", "status", "tie_step"),
@@ -230,12 +232,15 @@ class Batch:
             s = torch.as_tensor(np.asarray(j["sample_t"], dtype=np.float64),
                                 dtype=torch.float64).to(dev).contiguous()
             G = int(s.numel())
+            method = int(j.get("method", METHOD_RANDOM_TIME))
+            jwant = tuple(k for k in want if method != METHOD_DIRECT_TREE or
+                          k not in ("T", "tie_step"))
             o = {}
             shapes = dict(samples=((R, G, net.N), torch.int32), n=((R, net.M), torch.int32),
                           T=((R, net.M), torch.float64), x_final=((R, net.N), torch.int32),
                           t_last=((R,), torch.float64), status=((R,), torch.uint8),
                           tie_step=((R,), torch.int32), seq_hash=((R,), torch.int64))
-            for k in set(want) | ({"seq_hash"} if with_hash else set()):
+            for k in set(jwant) | ({"seq_hash"} if with_hash else set()):
                 shape, dt = shapes[k]
                 o[k] = torch.empty(shape, dtype=dt, device=dev)
             smp = o.get("samples")
@@ -248,6 +253,7 @@ class Batch:
             it.t_end = float(j["t_end"])
             it.sample_t = s.data_ptr() if G else None
             it.net_id = int(j.get("net_id", i))
+            it.method = method
             it.traj_offset = int(j.get("traj_offset", 0))
             it.R = R
             it.samples = smp.data_ptr() if smp is not None and smp.numel() else None

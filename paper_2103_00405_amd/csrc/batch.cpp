@@ -27,8 +27,10 @@ namespace {
 struct class_key {
     int mapping;    // RTSSA_MAP_*
     int a, b;       // thread: padded (M, N); wave / workgroup: lanes per trajectory, 0
+    int method;     // RTSSA_METHOD_*: the tree methods have classes of their own
     bool operator<(const class_key& o) const
     {
+        if (method != o.method) return method < o.method;
         return mapping != o.mapping ? mapping < o.mapping : (a != o.a ? a < o.a : b < o.b);
     }
 };
@@ -63,12 +65,13 @@ int plan_lookup(const std::vector<plan_entry>& plan, int mapping, int M)
     return 0;
 }
 
-class_key classify(const rtssa_network* net, const std::vector<plan_entry>& plan,
+class_key classify(const rtssa_network* net, int method, const std::vector<plan_entry>& plan,
                    const rtssa_options& o)
 {
+    if (method != RTSSA_METHOD_RANDOM_TIME) return {RTSSA_MAP_WAVE, 64, 0, method};
     int mapping = o.mapping ? o.mapping : rt_auto_mapping(net);
     if (mapping == RTSSA_MAP_THREAD && rt_thread_supported(net->M, net->N))
-        return {RTSSA_MAP_THREAD, pad_thread_m(net->M), pad_thread_n(net->N)};
+        return {RTSSA_MAP_THREAD, pad_thread_m(net->M), pad_thread_n(net->N), 0};
     if (mapping == RTSSA_MAP_THREAD) mapping = RTSSA_MAP_WAVE;
     if (mapping == RTSSA_MAP_WAVE && (net->M > 512 || net->max_nu > 64))
         mapping = RTSSA_MAP_WORKGROUP;
@@ -76,11 +79,11 @@ class_key classify(const rtssa_network* net, const std::vector<plan_entry>& plan
         int L = plan_lookup(plan, RTSSA_MAP_WAVE, net->M);
         if (L <= 0) L = rt_subwave_lanes(net->M);
         while (L < 64 && (L < net->max_nu || L * 8 < net->M)) L <<= 1;
-        return {RTSSA_MAP_WAVE, L, 0};
+        return {RTSSA_MAP_WAVE, L, 0, 0};
     }
     int L = plan_lookup(plan, RTSSA_MAP_WORKGROUP, net->M);
     if (L <= 0) L = rt_auto_group_size(net->M);
-    return {RTSSA_MAP_WORKGROUP, L, 0};
+    return {RTSSA_MAP_WORKGROUP, L, 0, 0};
 }
 
 }  // namespace
@@ -93,6 +96,8 @@ struct rtssa_batch_class {
     rt_class_dev dev{};
     hipStream_t side = nullptr;
     int block_used = 0, grid_used = 0;
+    int lazy_grid = 0;          // lazy form: the grid its workspace is sized for
+    void* lazy_ws = nullptr;    // lazy form: channel workspace (in the batch's block)
 };
 
 struct rtssa_batch {
@@ -131,17 +136,33 @@ static int batch_create(const rtssa_batch_item* items, int32_t count, const rtss
     uint64_t maxf = o.max_firings ? o.max_firings : 10000000ull;
     if (maxf > 0xFFFFFFFFull) return rt_fail(RTSSA_E_INVALID, "max_firings must be < 2^32");
     if (o.method != RTSSA_METHOD_RANDOM_TIME)
-        return rt_fail(RTSSA_E_UNSUPPORTED, "the batched form runs the random-time method");
+        return rt_fail(RTSSA_E_UNSUPPORTED, "the batch's method is chosen per item "
+                                            "(rtssa_batch_item.method); opt->method must be 0");
     // validate every item (reads each sample grid once)
     for (int i = 0; i < count; ++i) {
         const rtssa_batch_item& b = items[i];
         int rc = rt_check_run(b.net, b.x0, b.x0_per_traj, b.t_end, b.sample_t, b.G,
                               b.traj_offset, b.R, nullptr);
-        if (rc) return rt_fail(rc, "item " + std::to_string(i) + ": " + rtssa_last_error());
+        const std::string at = "item " + std::to_string(i) + ": ";
+        if (rc) return rt_fail(rc, at + rtssa_last_error());
+        if (b.method != RTSSA_METHOD_RANDOM_TIME && b.method != RTSSA_METHOD_LAZY &&
+            b.method != RTSSA_METHOD_DIRECT_TREE)
+            return rt_fail(RTSSA_E_UNSUPPORTED, at + "batched items run RANDOM_TIME, LAZY or "
+                                                     "DIRECT_TREE");
+        if (b.method != RTSSA_METHOD_RANDOM_TIME) {
+            if (b.net->dev.sched_B > 0)
+                return rt_fail(RTSSA_E_UNSUPPORTED, at + "the tree methods take no rate schedule");
+            if (b.method == RTSSA_METHOD_DIRECT_TREE && (b.T_out || b.tie_step))
+                return rt_fail(RTSSA_E_INVALID, at + "the direct method has no T_out or tie_step");
+            if (b.R > 0) {
+                rc = rt_lazy_prepare(const_cast<rtssa_network*>(b.net));
+                if (rc) return rt_fail(rc, at + rtssa_last_error());
+            }
+        }
     }
     std::map<class_key, std::vector<int>> groups;
     for (int i = 0; i < count; ++i)
-        if (items[i].R > 0) groups[classify(items[i].net, plan, o)].push_back(i);
+        if (items[i].R > 0) groups[classify(items[i].net, items[i].method, plan, o)].push_back(i);
 
     rtssa_batch* B = new rtssa_batch();
     B->items.assign(items, items + count);
@@ -176,6 +197,19 @@ static int batch_create(const rtssa_batch_item* items, int32_t count, const rtss
         o_next.push_back(off);
         off = align(off + sizeof(unsigned long long) * c.members.size());
     }
+    // the lazy classes' channel workspaces, sized for their grids
+    std::vector<size_t> o_lazy(B->classes.size(), 0);
+    for (size_t ci = 0; ci < B->classes.size(); ++ci) {
+        auto& c = B->classes[ci];
+        if (c.key.method != RTSSA_METHOD_LAZY) continue;
+        int rc = rt_lazy_grid(c.max_N, c.max_M, o.grid, c.units, &c.lazy_grid);
+        if (rc) {
+            delete B;
+            return rc;
+        }
+        o_lazy[ci] = off;
+        off = align(off + rt_lazy_workspace_bytes(c.lazy_grid, c.max_M));
+    }
     const size_t o_ws = off;
     off = align(off + sizeof(rt_ws) * std::max<size_t>(1, B->classes.size()));
     const size_t o_key = off;
@@ -186,6 +220,8 @@ static int batch_create(const rtssa_batch_item* items, int32_t count, const rtss
     }
     char* base = (char*)B->dev_block;
     B->ws_dev = (rt_ws*)(base + o_ws);
+    for (size_t ci = 0; ci < B->classes.size(); ++ci)
+        if (B->classes[ci].key.method == RTSSA_METHOD_LAZY) B->classes[ci].lazy_ws = base + o_lazy[ci];
     B->key_dev = (uint32_t*)(base + o_key);
     int rc = RTSSA_OK;
     for (size_t ci = 0; ci < B->classes.size() && !rc; ++ci) {
@@ -255,9 +291,20 @@ static int batch_enqueue(rtssa_batch* B, hipStream_t stream)
         auto& c = B->classes[ci];
         hipStream_t s = ci == 0 ? stream : c.side;
         const int block = c.key.mapping == RTSSA_MAP_THREAD ? B->opt.block : c.key.a;
-        rc = rt_launch_class(c.key.mapping, c.key.mapping == RTSSA_MAP_THREAD ? c.key.a : c.max_M,
-                             c.key.mapping == RTSSA_MAP_THREAD ? c.key.b : c.max_N, c.max_nu,
-                             c.dev, block, B->opt.grid, c.units, s, &c.block_used, &c.grid_used);
+        if (c.key.method == RTSSA_METHOD_LAZY) {
+            c.block_used = 64;
+            rc = rt_launch_lazy(c.dev, c.max_N, c.max_M, c.lazy_grid, c.units, s, &c.grid_used,
+                                c.lazy_ws);
+        } else if (c.key.method == RTSSA_METHOD_DIRECT_TREE) {
+            c.block_used = 64;
+            rc = rt_launch_dmtree(c.dev, c.max_N, c.max_M, B->opt.grid, c.units, s, &c.grid_used);
+        } else {
+            rc = rt_launch_class(c.key.mapping,
+                                 c.key.mapping == RTSSA_MAP_THREAD ? c.key.a : c.max_M,
+                                 c.key.mapping == RTSSA_MAP_THREAD ? c.key.b : c.max_N, c.max_nu,
+                                 c.dev, block, B->opt.grid, c.units, s, &c.block_used,
+                                 &c.grid_used);
+        }
         if (!rc && ci > 0) rc = check_hip(hipEventRecord(B->joins[ci], s), "join");
     }
     for (size_t ci = 1; ci < B->classes.size() && !rc; ++ci)
@@ -381,7 +428,7 @@ extern "C" int rtssa_autotune(const rtssa_batch_item* items, int32_t count, int3
     std::map<std::pair<int, int>, bucket> buckets;
     for (int i = 0; i < count; ++i) {
         const rtssa_network* n = items[i].net;
-        if (items[i].R < 1) continue;
+        if (items[i].R < 1 || items[i].method != RTSSA_METHOD_RANDOM_TIME) continue;
         int m = rt_auto_mapping(n);
         if (m == RTSSA_MAP_THREAD) continue;
         if (m == RTSSA_MAP_WAVE && n->M > 512) m = RTSSA_MAP_WORKGROUP;

@@ -717,8 +717,9 @@ size_t rt_lazy_lds_bytes(int N, int M)
     return 0;
 }
 
-int rt_launch_lazy(const rt_class_dev& C, int max_N, int max_M, int grid, int64_t units,
-                   hipStream_t stream, int* grid_used)
+// The lazy kernel's grid: the requested one, or the resident wavefronts
+// (LDS-limited) of the device, never more than the trajectories.
+int rt_lazy_grid(int max_N, int max_M, int grid, int64_t units, int* grid_out)
 {
     const size_t lds = rt_lazy_lds_bytes(max_N, max_M);
     if (lds == 0) return rt_fail(RTSSA_E_UNSUPPORTED, "network too large for the lazy form");
@@ -742,19 +743,37 @@ int rt_launch_lazy(const rt_class_dev& C, int max_N, int max_M, int grid, int64_
         grid = cus * per_cu;
     }
     if ((int64_t)grid > units) grid = (int)std::max<int64_t>(units, 1);
-    if (grid_used) *grid_used = grid;
-    // one workspace slice of channel records and counts per wavefront
-    const int64_t m_stride = std::max(max_M, 1);
-    void* wsp = nullptr;
-    const size_t rec_bytes = (size_t)grid * m_stride * sizeof(rt_lazy_rec);
-    const size_t n_bytes = (size_t)grid * m_stride * sizeof(uint32_t);
-    int rc = check_hip(hipMallocAsync(&wsp, rec_bytes + n_bytes, stream), "lazy workspace");
+    *grid_out = grid;
+    return RTSSA_OK;
+}
+
+// one slice of channel records and counts per wavefront of the grid
+size_t rt_lazy_workspace_bytes(int grid, int max_M)
+{
+    const size_t m = (size_t)std::max(max_M, 1);
+    return (size_t)grid * m * (sizeof(rt_lazy_rec) + sizeof(uint32_t));
+}
+
+int rt_launch_lazy(const rt_class_dev& C, int max_N, int max_M, int grid, int64_t units,
+                   hipStream_t stream, int* grid_used, void* workspace)
+{
+    int rc = rt_lazy_grid(max_N, max_M, grid, units, &grid);
     if (rc) return rc;
+    if (grid_used) *grid_used = grid;
+    const size_t lds = rt_lazy_lds_bytes(max_N, max_M);
+    const int64_t m_stride = std::max(max_M, 1);
+    void* wsp = workspace;
+    if (!wsp) {
+        rc = check_hip(hipMallocAsync(&wsp, rt_lazy_workspace_bytes(grid, max_M), stream),
+                       "lazy workspace");
+        if (rc) return rc;
+    }
+    const size_t rec_bytes = (size_t)grid * m_stride * sizeof(rt_lazy_rec);
     hipLaunchKernelGGL(rt_lazy_kernel, dim3(grid), dim3(64), lds, stream, C, (rt_lazy_rec*)wsp,
                        (uint32_t*)((char*)wsp + rec_bytes), m_stride);
     rc = hipGetLastError() == hipSuccess ? RTSSA_OK
                                          : rt_fail(RTSSA_E_HIP, "lazy kernel launch failed");
-    if (hipFreeAsync(wsp, stream) != hipSuccess && !rc)
+    if (!workspace && hipFreeAsync(wsp, stream) != hipSuccess && !rc)
         rc = rt_fail(RTSSA_E_HIP, "freeing the lazy workspace failed");
     return rc;
 }

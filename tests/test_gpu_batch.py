@@ -107,3 +107,39 @@ def test_autotuned_plan_keeps_bits():
     for o0, o1 in zip(b0.outputs, b1.outputs):
         for k in KEYS:
             assert torch.equal(o0[k], o1[k]), k
+
+
+def test_batch_with_per_item_methods():
+    """Items choosing the lazy form or the direct method on a sum tree run in
+    classes of their own; every item equals its own rtssa_simulate with the
+    same method, seed and net_id, on the first run and on a graph replay with
+    a new seed, and two items equal the oracle."""
+    api = _api()
+    jobs = _jobs(api, n_nets=24, seed=9, target=500, R=10)
+    for i, j in enumerate(jobs):
+        j["method"] = (api.METHOD_LAZY, api.METHOD_DIRECT_TREE, api.METHOD_RANDOM_TIME)[i % 3]
+    b = api.Batch(jobs, with_hash=True)
+    kinds = {(c["mapping"], c["lanes"]) for c in b.classes()}
+    assert (api.MAP_WAVE, 64) in kinds
+    for seed in (13, 14):
+        b.run(seed=seed)
+        torch.cuda.synchronize()
+        for j, o in zip(jobs, b.outputs):
+            ref = api.simulate(j["net"], j["x0"], j["t_end"], j["sample_t"], j["R"], seed=seed,
+                               net_id=j["net_id"], with_hash=True, method=j["method"])
+            torch.cuda.synchronize()
+            for k in o:
+                assert torch.equal(o[k], ref[k]), (j["net_id"], j["method"], k)
+    for i in (0, 1):
+        j = jobs[i]
+        kw = dict(net_id=j["net_id"])
+        if j["method"] == api.METHOD_LAZY:
+            ref = oracle.simulate(j["spec"], j["x0"], j["t_end"], j["sample_t"], 14, j["R"],
+                                  lazy=True, **kw)
+            assert np.array_equal(b.outputs[i]["T"].cpu().numpy().view(np.uint64),
+                                  ref["T"].view(np.uint64))
+        else:
+            ref = oracle.direct_simulate(j["spec"], j["x0"], j["t_end"], j["sample_t"], 14,
+                                         j["R"], tree=True, **kw)
+        assert np.array_equal(b.outputs[i]["n"].cpu().numpy().view(np.uint32), ref["n"])
+        assert np.array_equal(b.outputs[i]["samples"].cpu().numpy(), ref["samples"])
