@@ -184,20 +184,74 @@ __device__ __forceinline__ double lazy_wave_min(double v)
     return lazy_min_f64(p, q);
 }
 
-// The second smallest tau over all leaves: every leaf but mu lies in the
-// group of mu's leaf or below a sibling of one of mu's ancestors, so it is the
-// smallest of those siblings' values (lane kFan l + i reads sibling i at level
-// l; level_off holds each level's tau array as a byte offset into the LDS
-// region, a table in LDS so that the per-lane level index does not turn into
-// a private-memory array).
-__device__ __forceinline__ double lazy_second(const char* region, const uint32_t* level_off,
-                                              int top, int mu, int lane)
+// The smaller of two entries from anywhere in the wavefront; on equal values
+// the lower channel (the order of a cross-lane reduction is not channel order).
+__device__ __forceinline__ lazy_min lazy_merge_any(const lazy_min& a, const lazy_min& b)
 {
-    const int lev = min(lane >> kFanLog, top - 1), i = lane & (kFan - 1);
-    const int jl = mu >> (kFanLog * lev);
-    const double x = ((const double*)(region + level_off[lev]))[(jl & ~(kFan - 1)) + i];
-    return lazy_wave_min((lane >> kFanLog) < top && i != (jl & (kFan - 1)) ? x
-                                                                          : __builtin_inf());
+    const bool blt = b.d < a.d, eq = b.d == a.d;
+    return lazy_min{blt ? b.d : a.d, blt ? b.k : (eq ? min(a.k, b.k) : a.k)};
+}
+
+template <int CTRL>
+__device__ __forceinline__ lazy_min lazy_dpp_step(const lazy_min& v)
+{
+    return lazy_merge_any(v, lazy_min{rt_dpp_f64<CTRL>(v.d), rt_dpp<CTRL>(v.k)});
+}
+
+template <int ROWS>
+__device__ __forceinline__ lazy_min lazy_swap_step(const lazy_min& v)
+{
+    lazy_min p, q;
+    p.d = rt_swap_f64<ROWS>(v.d, q.d);
+    uint32_t pk, qk;
+    rt_swap<ROWS>((uint32_t)v.k, pk, qk);
+    p.k = (int32_t)pk;
+    q.k = (int32_t)qk;
+    return lazy_merge_any(p, q);
+}
+
+// The smallest entry (and its channel) over the wavefront, in every lane.
+__device__ __forceinline__ lazy_min lazy_wave_argmin(lazy_min v)
+{
+    v = lazy_dpp_step<0xB1>(v);                          // quad_perm [1,0,3,2]
+    v = lazy_dpp_step<0x4E>(v);                          // quad_perm [2,3,0,1]
+    v = lazy_dpp_step<0x141>(v);                         // row_half_mirror
+    v = lazy_dpp_step<0x140>(v);                         // row_mirror
+    v = lazy_swap_step<16>(v);
+    return lazy_swap_step<32>(v);
+}
+
+// The top level (at most 64 entries, lane e holds entry e) and its reduction
+// to the next event: the smallest tau and its channel.
+__device__ __forceinline__ lazy_min lazy_top_entry(const double* top_d, const int32_t* top_k,
+                                                   int top_cnt, bool leaves_on_top, int lane)
+{
+    const int e = min(lane, top_cnt - 1);
+    const double d = top_d[e];
+    const int k = leaves_on_top ? lane : top_k[e];
+    return lazy_min{lane < top_cnt ? d : __builtin_inf(), lane < top_cnt ? k : 0x7FFFFFFF};
+}
+
+// The second smallest tau over all leaves: every leaf but mu lies in the
+// group of mu's leaf, below a sibling of one of mu's ancestors under the top
+// level, or below another entry of the top level, so it is the smallest of
+// those values.  Lane kFan l + i reads sibling i at level l < top (level_off
+// holds each level's tau array as a byte offset into the LDS region, a table
+// in LDS so that the per-lane level index does not turn into a private-memory
+// array); every lane also takes top-level entry `lane` unless it is mu's.
+__device__ __forceinline__ double lazy_second(const char* region, const uint32_t* level_off,
+                                              int top, int mu, const lazy_min& top_entry,
+                                              int lane)
+{
+    double sib = __builtin_inf();
+    if (top > 0) {
+        const int lev = min(lane >> kFanLog, top - 1), i = lane & (kFan - 1);
+        const int jl = mu >> (kFanLog * lev);
+        const double x = ((const double*)(region + level_off[lev]))[(jl & ~(kFan - 1)) + i];
+        sib = (lane >> kFanLog) < top && i != (jl & (kFan - 1)) ? x : __builtin_inf();
+    }
+    const double own = lane == (mu >> (kFanLog * top)) ? __builtin_inf() : top_entry.d;
+    return lazy_wave_min(lazy_min_f64(sib, own));
 }
 
 // A touched channel's update (mu: fresh = true, T_mu = P_mu, P_mu += E;
@@ -256,38 +310,43 @@ __global__ __launch_bounds__(64) void rt_lazy_kernel(rt_class_dev C, rt_lazy_rec
         const double t_end = it->t_end;
 
         // LDS: X [N, padded to 4], the leaves, then the node levels 1 .. top
-        // (sizes ceil(previous / 8), the root alone on top); every level
-        // index below is a compile-time constant after unrolling
+        // (sizes ceil(previous / 8)); the top level is the first with at
+        // most 64 entries (the leaves themselves when M <= 64), reduced to
+        // the next event by one wavefront argmin.  Every level index below is
+        // a compile-time constant after unrolling.
         lazy_tree tr;
         int32_t* X = dyn_lds;
         {
             char* p = (char*)(dyn_lds + ((N + 3) & ~3));
             tr.cnt[0] = M > 0 ? M : 1;
             tr.d[0] = (double*)p;
-            tr.kk[0] = nullptr;
+            tr.kk[0] = (int32_t*)p;                      // unused (leaves carry no channel)
             p += 8 * padf(tr.cnt[0]);
-            tr.top = 0;
+            int top_l = tr.cnt[0] <= 64 ? 0 : -1;
 #pragma unroll
             for (int l = 1; l <= kMaxLevels; ++l) {
                 tr.cnt[l] = (tr.cnt[l - 1] + kFan - 1) >> kFanLog;
-                const int P = tr.top == 0 ? padf(tr.cnt[l]) : 0;
+                const int P = top_l < 0 ? padf(tr.cnt[l]) : 0;
                 tr.d[l] = (double*)p;
                 tr.kk[l] = (int32_t*)(p + 8 * P);
                 p += 12 * P;
-                if (tr.top == 0 && tr.cnt[l] == 1) tr.top = l;
+                if (top_l < 0 && tr.cnt[l] <= 64) top_l = l;
             }
+            tr.top = top_l;
         }
         const int top = tr.top;
         double* const leaves = tr.d[0];
 #pragma unroll
         for (int l = 0; l <= kMaxLevels; ++l)
             if (lane == l) level_off[l] = (uint32_t)((char*)tr.d[l] - (char*)dyn_lds);
-        double* root_d = tr.d[1];
-        int32_t* root_k = tr.kk[1];
+        const double* top_d = tr.d[0];
+        const int32_t* top_k = tr.kk[0];
+        int top_cnt = tr.cnt[0];
 #pragma unroll
-        for (int l = 2; l <= kMaxLevels; ++l) {
-            root_d = l == top ? tr.d[l] : root_d;
-            root_k = l == top ? tr.kk[l] : root_k;
+        for (int l = 1; l <= kMaxLevels; ++l) {
+            top_d = l == top ? tr.d[l] : top_d;
+            top_k = l == top ? tr.kk[l] : top_k;
+            top_cnt = l == top ? tr.cnt[l] : top_cnt;
         }
 
         // ---- initial state: X, every channel's record and leaf, the tree
@@ -319,10 +378,12 @@ __global__ __launch_bounds__(64) void rt_lazy_kernel(rt_class_dev C, rt_lazy_rec
             wave_lds_fence();
         }
 
-        // the root: read once here, then kept in registers (every lane
-        // computes it at the top level of each tree update)
-        double root_tau = *root_d;
-        int root_ch = *root_k;
+        // the next event: the top level's argmin, kept in registers (every
+        // lane holds it) and recomputed at the end of each tree update
+        lazy_min top_e = lazy_top_entry(top_d, top_k, top_cnt, top == 0, lane);
+        lazy_min root = lazy_wave_argmin(top_e);
+        double root_tau = root.d;
+        int root_ch = root.k;
         double t = 0.0, s_next = it->G > 0 ? rt_const(it->s)[0] : __builtin_inf();
         int32_t g = 0;
         uint32_t fired = 0, tie = kTieNone;
@@ -362,7 +423,9 @@ __global__ __launch_bounds__(64) void rt_lazy_kernel(rt_class_dev C, rt_lazy_rec
             const uint32_t nm = nks[mu];
             // near-tie test (statistics only) while the loads are in flight
             {
-                const double d1 = t_new - t, d2 = lazy_second((const char*)dyn_lds, level_off, top, mu, lane) - t;
+                const double d1 = t_new - t;
+                const double d2 =
+                    lazy_second((const char*)dyn_lds, level_off, top, mu, top_e, lane) - t;
                 if (d2 - d1 <= 1e-12 * d1) {
                     if (lane == 0) atomicAdd(&ws->near_ties, 1ull);
                     tie = tie == kTieNone ? fired : tie;
@@ -388,10 +451,7 @@ __global__ __launch_bounds__(64) void rt_lazy_kernel(rt_class_dev C, rt_lazy_rec
             for (int l = 1; l <= kMaxLevels; ++l) {
                 if (l > top) break;
                 const int j = k >> (kFanLog * l);
-                const lazy_min nv = lazy_node(tr, l, j);
-                lazy_store(tr, l, j, nv);
-                root_tau = l == top ? nv.d : root_tau;
-                root_ch = l == top ? nv.k : root_ch;
+                lazy_store(tr, l, j, lazy_node(tr, l, j));
                 wave_lds_fence();
             }
             // ---- more than 63 other dependents: the rest of the CSR list
@@ -410,14 +470,15 @@ __global__ __launch_bounds__(64) void rt_lazy_kernel(rt_class_dev C, rt_lazy_rec
                     for (int l = 1; l <= kMaxLevels; ++l) {
                         if (l > top) break;
                         const int j = (k2 >= 0 ? k2 : mu) >> (kFanLog * l);
-                        const lazy_min nv = lazy_node(tr, l, j);
-                        lazy_store(tr, l, j, nv);
-                        root_tau = l == top ? nv.d : root_tau;
-                root_ch = l == top ? nv.k : root_ch;
+                        lazy_store(tr, l, j, lazy_node(tr, l, j));
                         wave_lds_fence();
                     }
                 }
             }
+            top_e = lazy_top_entry(top_d, top_k, top_cnt, top == 0, lane);
+            root = lazy_wave_argmin(top_e);
+            root_tau = root.d;
+            root_ch = root.k;
             if (lane == 0) nks[mu] = nm + 1u;
             t = t_new;
             ++fired;
@@ -701,21 +762,29 @@ __global__ __launch_bounds__(64) void rt_dmtree_kernel(rt_class_dev C)
 
 }  // namespace
 
-// LDS bytes of one trajectory: X, the leaves and every node level (arrays
-// padded to kFan entries); 0 when the tree would need more than kMaxLevels
-// levels.
-size_t rt_lazy_lds_bytes(int N, int M)
+// LDS bytes of one trajectory: X, the leaves and the node levels up to the
+// first with at most top_max entries (arrays padded to kFan entries; the
+// leaves count as that level when top_max > 1, while the sum tree always has
+// a root level above them); 0 when that takes more than kMaxLevels levels.
+static size_t tree_lds_bytes(int N, int M, int top_max)
 {
     size_t n = (size_t)((N + 3) & ~3) * 4;
     int c = M > 0 ? M : 1;
     n += (size_t)((c + kFan - 1) & ~(kFan - 1)) * 8;
+    if (top_max > 1 && c <= top_max) return n;
     for (int l = 1; l <= kMaxLevels; ++l) {
         c = (c + kFan - 1) >> kFanLog;
         n += (size_t)((c + kFan - 1) & ~(kFan - 1)) * 12;
-        if (c == 1) return n;
+        if (c <= top_max) return n;
     }
     return 0;
 }
+
+// the lazy form's tree stops at a top level of at most 64 entries
+size_t rt_lazy_lds_bytes(int N, int M) { return tree_lds_bytes(N, M, 64); }
+
+// the sum tree goes up to its single root
+static size_t dmtree_lds_bytes(int N, int M) { return tree_lds_bytes(N, M, 1); }
 
 // The lazy kernel's grid: the requested one, or the resident wavefronts
 // (LDS-limited) of the device, never more than the trajectories.
@@ -781,7 +850,7 @@ int rt_launch_lazy(const rt_class_dev& C, int max_N, int max_M, int grid, int64_
 int rt_launch_dmtree(const rt_class_dev& C, int max_N, int max_M, int grid, int64_t units,
                      hipStream_t stream, int* grid_used)
 {
-    const size_t lds = rt_lazy_lds_bytes(max_N, max_M);
+    const size_t lds = dmtree_lds_bytes(max_N, max_M);
     if (lds == 0) return rt_fail(RTSSA_E_UNSUPPORTED, "network too large for the sum tree");
     int dev = 0, lds_max = 0, cus = 0;
     if (hipGetDevice(&dev) != hipSuccess ||
