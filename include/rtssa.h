@@ -112,7 +112,7 @@ typedef struct {
  * fixed-stride rows (about 270 bytes per channel of device memory, kept
  * until the network is destroyed); that first run must not overlap another
  * call on the same network from a second host thread.  Its channel workspace
- * (36 bytes per channel per resident wavefront) is allocated stream-ordered
+ * (44 bytes per channel per resident wavefront) is allocated stream-ordered
  * by the call. */
 /* DIRECT_TREE is the direct method with a_0 and the channel search on a
  * fixed sum tree of fan-out 8 over the channels (entries past M are 0; a

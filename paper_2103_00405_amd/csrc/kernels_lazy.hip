@@ -12,27 +12,31 @@
 // tau_k, lowest k on ties (Eq. 25).  Work per firing is O(|D(mu)| log M)
 // rather than the eager form's O(M).
 //
-// Layout.  The wavefront's LDS region holds the species counts X and the
-// tree: the leaves are tau_k (M doubles); a node of level l >= 1 holds the
-// smallest tau over its kFan children of level l - 1 and that tau's channel;
-// the last level is the root, which every lane also keeps in registers.
-// Each level is stored as two arrays (tau, channel) padded to a multiple of
-// kFan entries with empty values, so that a node's children are read with a
-// few 16-byte loads and no bounds tests; merges use selects, not branches.
-// Fan-out 8 measured faster than 16 on 4000 channels (4 levels against 3, but
-// a shallower merge per level).  The second smallest tau (for the near-tie count
-// only) is the smallest over the siblings of mu's leaf and of each of its
-// ancestors below the root: one LDS read per lane and a wavefront minimum,
-// done while the firing's global loads are in flight.  The channels' T_k,
-// s_k, P_k, a_k (32 bytes) and n_k live in a global workspace, one slice per
-// wavefront of the grid.  A firing: the root gives mu; the wavefront loads
-// mu's fixed-stride rows (its jump and the channels it touches, so that one
-// load round trip suffices before the records), checks and applies the jump,
-// draws mu's next Exp(1) with all lanes, then one lane per touched channel
-// updates it and writes its leaf; the touched leaves' ancestors are recomputed
-// level by level, one lane per touched channel (lanes that share an ancestor
-// compute the same node).  No workgroup barrier is used: a wavefront's LDS accesses
-// complete in program order.
+// Layout.  The wavefront's LDS region holds the species counts X and a
+// minimum tree over the tau_k: the leaves are tau_k (M doubles); a node of
+// level l >= 1 holds the smallest tau over its kFan children of level l - 1
+// and that tau's channel.  Levels are built up to the first with at most 64
+// entries (the leaves themselves when M <= 64); that top level is reduced to
+// the next event by one wavefront argmin (DPP and permlane steps), which
+// every lane keeps in registers.  Each level is stored as two arrays (tau,
+// channel) padded to a multiple of kFan entries with empty values, so that a
+// node's children are read with a few 16-byte loads and no bounds tests;
+// merges use selects, not branches.  Fan-out 8 measured faster than 16.  The
+// second smallest tau (for the near-tie count only) is the smallest over the
+// siblings of mu's leaf and of its ancestors below the top level and over the
+// top level's other entries, taken while the firing's global loads are in
+// flight.  The channels' T_k, s_k, P_k, a_k (32 bytes), n_k and the spare word
+// of their last Philox block live in a global workspace, one slice per
+// wavefront of the grid.
+//
+// A firing: the argmin gives mu; the wavefront loads mu's fixed-stride rows
+// (its jump and the channels it touches, so that one load round trip
+// suffices before the records), checks and applies the jump, draws mu's next
+// Exp(1) with all lanes, then one lane per touched channel updates it and
+// writes its leaf; the touched leaves' ancestors are recomputed level by
+// level, one lane per touched channel (lanes that share an ancestor compute
+// the same node), and the top level is reduced again.  No workgroup barrier
+// is used: a wavefront's LDS accesses complete in program order.
 #include <hip/hip_runtime.h>
 
 #include "internal.h"
@@ -276,7 +280,8 @@ __device__ __forceinline__ rt_lazy_rec lazy_touch(rt_lazy_rec rc, bool fresh, do
 }
 
 __global__ __launch_bounds__(64) void rt_lazy_kernel(rt_class_dev C, rt_lazy_rec* rec_ws,
-                                                     uint32_t* n_ws, int64_t m_stride)
+                                                     unsigned long long* w_ws, uint32_t* n_ws,
+                                                     int64_t m_stride)
 {
     extern __shared__ int32_t dyn_lds[];
     __shared__ uint32_t log_scratch[RT_LOG_SCRATCH];
@@ -288,6 +293,10 @@ __global__ __launch_bounds__(64) void rt_lazy_kernel(rt_class_dev C, rt_lazy_rec
     const int64_t total = unit_start[C.count];
     rt_lazy_rec* const recs = rec_ws + (int64_t)blockIdx.x * m_stride;
     uint32_t* const nks = n_ws + (int64_t)blockIdx.x * m_stride;
+    // a channel's Philox block holds the words of two consecutive draws (n
+    // even: words 1:0, n odd: words 3:2); the odd one is kept here until the
+    // channel's next firing uses it
+    unsigned long long* const wnext = w_ws + (int64_t)blockIdx.x * m_stride;
 
     for (;;) {
         unsigned long long u = 0;
@@ -362,8 +371,10 @@ __global__ __launch_bounds__(64) void rt_lazy_kernel(rt_class_dev C, rt_lazy_rec
         }
         wave_lds_fence();
         for (int k = lane; k < M; k += 64) {
-            const double P = rt_exp1_wave(key0, key1, traj, net_id, (uint32_t)k, 0u,
-                                          &ws->slow_logs, log_scratch);
+            const rt_u4 w = rt_philox4x32_10(rt_u4{0u, (uint32_t)k, traj, net_id}, key0, key1);
+            wnext[k] = ((unsigned long long)w.w << 32) | w.z;
+            const double P = rt_neglog_wave((((uint64_t)w.y << 32) | w.x) >> 11, false,
+                                            &ws->slow_logs, log_scratch);
             const double a = lazy_propensity(react[k], cc[k], X);
             bool cl;
             leaves[k] = lazy_tau(0.0, 0.0, P, a, &cl);
@@ -421,6 +432,7 @@ __global__ __launch_bounds__(64) void rt_lazy_kernel(rt_class_dev C, rt_lazy_rec
             const int2 rr0 = react[k];
             const double c0 = cc[k];
             const uint32_t nm = nks[mu];
+            const unsigned long long w_odd = wnext[mu];
             // near-tie test (statistics only) while the loads are in flight
             {
                 const double d1 = t_new - t;
@@ -432,9 +444,17 @@ __global__ __launch_bounds__(64) void rt_lazy_kernel(rt_class_dev C, rt_lazy_rec
                 }
             }
             // the fired channel's next Exp(1) (Eq. 26), drawn by every lane
-            // while the loads are in flight
-            const double E = rt_exp1_uniform(key0, key1, traj, net_id, (uint32_t)mu, nm + 1u,
-                                             &ws->slow_logs, log_scratch);
+            // while the loads are in flight: draw n = nm + 1 takes the kept
+            // word when n is odd, else a new block whose odd word is kept
+            const uint32_t nd = nm + 1u;
+            uint64_t word = w_odd;
+            if ((nd & 1u) == 0u) {
+                const rt_u4 w =
+                    rt_philox4x32_10(rt_u4{nd >> 1, (uint32_t)mu, traj, net_id}, key0, key1);
+                word = ((uint64_t)w.y << 32) | w.x;
+                if (lane == 0) wnext[mu] = ((unsigned long long)w.w << 32) | w.z;
+            }
+            const double E = rt_neglog_uniform(word >> 11, &ws->slow_logs, log_scratch);
             // ---- the jump v_mu, checked against [0, 2^31 - 1]
             const int64_t xv = (int64_t)X[sp] + dl;
             const bool okl = !has_nu || (xv >= 0 && xv <= 0x7FFFFFFF);
@@ -816,11 +836,11 @@ int rt_lazy_grid(int max_N, int max_M, int grid, int64_t units, int* grid_out)
     return RTSSA_OK;
 }
 
-// one slice of channel records and counts per wavefront of the grid
+// one slice of channel records, kept draw words and counts per wavefront
 size_t rt_lazy_workspace_bytes(int grid, int max_M)
 {
     const size_t m = (size_t)std::max(max_M, 1);
-    return (size_t)grid * m * (sizeof(rt_lazy_rec) + sizeof(uint32_t));
+    return (size_t)grid * m * (sizeof(rt_lazy_rec) + sizeof(unsigned long long) + sizeof(uint32_t));
 }
 
 int rt_launch_lazy(const rt_class_dev& C, int max_N, int max_M, int grid, int64_t units,
@@ -838,8 +858,10 @@ int rt_launch_lazy(const rt_class_dev& C, int max_N, int max_M, int grid, int64_
         if (rc) return rc;
     }
     const size_t rec_bytes = (size_t)grid * m_stride * sizeof(rt_lazy_rec);
+    const size_t word_bytes = (size_t)grid * m_stride * sizeof(unsigned long long);
     hipLaunchKernelGGL(rt_lazy_kernel, dim3(grid), dim3(64), lds, stream, C, (rt_lazy_rec*)wsp,
-                       (uint32_t*)((char*)wsp + rec_bytes), m_stride);
+                       (unsigned long long*)((char*)wsp + rec_bytes),
+                       (uint32_t*)((char*)wsp + rec_bytes + word_bytes), m_stride);
     rc = hipGetLastError() == hipSuccess ? RTSSA_OK
                                          : rt_fail(RTSSA_E_HIP, "lazy kernel launch failed");
     if (!workspace && hipFreeAsync(wsp, stream) != hipSuccess && !rc)
