@@ -375,13 +375,15 @@ def bench_gradient(api, W, reps=3):
 
 
 BATCH_MAX_FIRINGS = 100_000     # per trajectory; 5x the 2e4 the t_end is set for
+LAZY_ABOVE_M = 512              # batched networks above this many channels run the lazy form
 
 
 def bench_batched(api, W, steps=2, n_nets=4096, solo_sample=32, tune_samples=16, cpu_s=0.0):
     """4096 random networks (M log-uniform in [3, 2048], N = M/4, 64
     trajectories each, t_end for about 2e4 firings) in one captured launch per
-    size class, lane counts chosen by the autotuner, against one rtssa_simulate
-    launch per network.  Networks whose rates grow with the state can run far
+    size class -- the networks above 512 channels in the lazy form, the others
+    with lane counts chosen by the autotuner -- against one rtssa_simulate
+    launch per network with the same method.  Networks whose rates grow with the state can run far
     past 2e4 firings; every trajectory is capped at 1e5 firings (status
     MAX_FIRINGS, counted), in the batch and in the per-network launches alike.
     The per-network time is measured on a stratified sample (every
@@ -392,8 +394,13 @@ def bench_batched(api, W, steps=2, n_nets=4096, solo_sample=32, tune_samples=16,
     import torch
     t0 = time.perf_counter()
     wl = W.batch_networks(n_nets)
+    # networks above LAZY_ABOVE_M channels run the lazy form (its own class,
+    # launched first), the others the eager mappings; the per-network launches
+    # below use the same method per network
     jobs = [dict(net=api.Network(w.net), x0=w.x0, t_end=w.t_end, sample_t=w.sample_t, R=w.R,
-                 net_id=w.net_id) for w in wl]
+                 net_id=w.net_id,
+                 method=api.METHOD_LAZY if w.net.M > LAZY_ABOVE_M else api.METHOD_RANDOM_TIME)
+            for w in wl]
     log("batched: %d networks generated in %.1f s" % (n_nets, time.perf_counter() - t0))
     want = ("samples", "n", "T", "x_final", "status")
     b0 = api.Batch(jobs, want=want, max_firings=BATCH_MAX_FIRINGS)
@@ -430,7 +437,7 @@ def bench_batched(api, W, steps=2, n_nets=4096, solo_sample=32, tune_samples=16,
         t1 = time.perf_counter()
         o = api.simulate(j["net"], j["x0"], j["t_end"], j["sample_t"], j["R"], seed=1,
                          net_id=j["net_id"], want=want, stats=False,
-                         max_firings=BATCH_MAX_FIRINGS)
+                         max_firings=BATCH_MAX_FIRINGS, method=j["method"])
         torch.cuda.synchronize()
         solo_ms += (time.perf_counter() - t1) * 1e3
         solo_fir += int(o["n"].to(torch.int64).sum())
@@ -455,6 +462,8 @@ def bench_batched(api, W, steps=2, n_nets=4096, solo_sample=32, tune_samples=16,
             "max_firings_per_trajectory": BATCH_MAX_FIRINGS,
             "trajectories_capped": capped, "autotune_s": tune_s, "plan": plan_text,
             "classes": b.classes(),
+            "lazy_above_M": LAZY_ABOVE_M,
+            "lazy_networks": sum(1 for j in jobs if j["method"] == api.METHOD_LAZY),
             "per_network_launches": {"networks_timed": len(idx), "sample_ms": solo_ms,
                                      "sample_firings": solo_fir,
                                      "estimated_ms_for_all": est_ms,
