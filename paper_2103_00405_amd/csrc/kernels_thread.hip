@@ -109,6 +109,9 @@ struct rt_line_writer {
 constexpr int thread_min_waves(int MT, int NT, int METHOD, bool SCHED)
 {
     if (METHOD == RTSSA_METHOD_DIRECT) return 4;
+    // 5 waves fit without scratch up to 3 channels and 2 species (and 2 x 4);
+    // on the Lotka-Volterra ensemble they measured 2.7 % faster than 4
+    if (!SCHED && ((MT <= 2 && NT <= 4) || (MT == 3 && NT <= 2))) return 5;
     if (!SCHED) return MT <= 4 ? 4 : (MT == 8 && NT == 8 ? 2 : 3);
     // with a schedule each lane also holds its rates in force
     if (MT <= 2 || (MT <= 4 && NT <= 4)) return 4;
