@@ -75,6 +75,8 @@ def _configure(L):
                                         C.c_int32, C.c_void_p, C.c_void_p]
     L.rto_lazy_simulate.restype = C.c_int
     L.rto_lazy_simulate.argtypes = L.rto_simulate.argtypes
+    L.rto_lazy_simulate_schedule.restype = C.c_int
+    L.rto_lazy_simulate_schedule.argtypes = L.rto_simulate_schedule.argtypes
     L.rto_direct_simulate.restype = C.c_int
     L.rto_direct_simulate.argtypes = [C.POINTER(_Net), C.c_void_p, C.c_int32, C.c_double,
                                       C.c_void_p, C.c_int32, C.c_uint64, C.c_uint32,
@@ -139,8 +141,6 @@ def simulate(net, x0, t_end, sample_t, seed, R, net_id=0, traj_offset=0,
     schedule = (times [B], rates [B][M]) gives piecewise-constant rates: the
     network's c before times[0], rates[i] from times[i] on.  lazy = True runs
     the lazy form (dependency-graph updates, smallest absolute firing time)."""
-    if lazy and schedule is not None:
-        raise ValueError("the lazy form takes no rate schedule")
     N, M = int(net.N), int(net.M)
     x0 = np.ascontiguousarray(x0, dtype=np.int32)
     per_traj = 1 if x0.ndim == 2 else 0
@@ -165,14 +165,13 @@ def simulate(net, x0, t_end, sample_t, seed, R, net_id=0, traj_offset=0,
             _ptr(out["samples"]), _ptr(out["n"]), _ptr(out["T"]),
             _ptr(out["x_final"]), _ptr(out["t_last"]), _ptr(out["status"]),
             _ptr(out["seq_hash"]), _ptr(out["tie_step"]), int(threads), C.byref(st))
-    if lazy:
-        rc = L.rto_lazy_simulate(*args)
-    elif schedule is None:
-        rc = L.rto_simulate(*args)
+    if schedule is None:
+        rc = (L.rto_lazy_simulate if lazy else L.rto_simulate)(*args)
     else:
         times = np.ascontiguousarray(schedule[0], dtype=np.float64)
         rates = np.ascontiguousarray(schedule[1], dtype=np.float64).reshape(times.size, M)
-        rc = L.rto_simulate_schedule(*args, int(times.size), _ptr(times), _ptr(rates))
+        fn = L.rto_lazy_simulate_schedule if lazy else L.rto_simulate_schedule
+        rc = fn(*args, int(times.size), _ptr(times), _ptr(rates))
     if rc not in (0,):
         raise RuntimeError("oracle rto_simulate failed with code %d (hard cases %d)"
                            % (rc, st.hard_cases))

@@ -323,12 +323,18 @@ static void simulate_path(job_t* jb, int64_t r, int32_t* X, double* T, double* P
  *     and counted).
  *   end: T_k = fma(a_k, RN(t_stop - s_k), T_k) for every k, with t_stop =
  *     t_end after OK or ABSORBED and the last event's time otherwise.
+ *   rate schedule (piecewise-constant c_k(t), as in simulate_path): when the
+ *     smallest tau_k lies past the next breakpoint b (b < t_end), every
+ *     channel runs its clock to b at its old propensity,
+ *     T_k = fma(a_k, RN(b - s_k), T_k), s_k = b, takes the new rates and a new
+ *     tau_k from t = b; nothing fires.
  * D(mu) holds the channels with a reactant species whose net change in nu_mu
  * is not zero (build_deps). */
 static void lazy_refresh(job_t* jb, const int32_t* X, int k, double t, const double* T,
-                         const double* P, double* a, double* inv, double* tau)
+                         const double* P, double* a, double* inv, double* tau,
+                         const double* crate)
 {
-    a[k] = propensity(jb->net, X, k);
+    a[k] = propensity_c(jb->net, X, k, crate[k]);
     inv[k] = a[k] > 0 ? 1.0 / a[k] : 0.0;
     if (a[k] == 0.0) {
         tau[k] = INFINITY;
@@ -354,13 +360,16 @@ static void simulate_path_lazy(job_t* jb, int64_t r, int32_t* X, double* T, doub
     const int32_t* x0 = jb->x0 + (jb->x0_per_traj ? (size_t)r * N : 0);
     for (int j = 0; j < N; j++) X[j] = x0[j];
     double t = 0.0;
+    const double* crate = net->c;
+    int32_t piece = 0;
+    double b_next = jb->B > 0 ? jb->sched_t[0] : INFINITY;
     for (int k = 0; k < M; k++) {
         T[k] = 0.0;
         s_up[k] = 0.0;
         n[k] = 0;
         P[k] = rto_exp1(seed, traj, nid, (uint32_t)k, 0);
         if (P[k] < 0) jb->stats.hard_cases++;
-        lazy_refresh(jb, X, k, 0.0, T, P, a, inv, tau);
+        lazy_refresh(jb, X, k, 0.0, T, P, a, inv, tau, crate);
     }
     int32_t g = 0;
     uint64_t fired = 0;
@@ -375,8 +384,20 @@ static void simulate_path_lazy(job_t* jb, int64_t r, int32_t* X, double* T, doub
             if (tau[k] < tau1) { tau2 = tau1; tau1 = tau[k]; mu = k; }
             else if (tau[k] < tau2) { tau2 = tau[k]; }
         }
-        if (tau1 == INFINITY) { st = RTO_ABSORBED; break; }
         double t_new = tau1;
+        if (b_next < jb->t_end && t_new > b_next) {
+            for (int k = 0; k < M; k++) {
+                T[k] = fma(a[k], b_next - s_up[k], T[k]);
+                s_up[k] = b_next;
+            }
+            t = b_next;
+            crate = jb->sched_c + (size_t)piece * M;
+            piece += 1;
+            b_next = piece < jb->B ? jb->sched_t[piece] : INFINITY;
+            for (int k = 0; k < M; k++) lazy_refresh(jb, X, k, t, T, P, a, inv, tau, crate);
+            continue;
+        }
+        if (tau1 == INFINITY) { st = RTO_ABSORBED; break; }
         if (t_new > jb->t_end) break;
         double d1 = t_new - t, d2 = tau2 - t;
         if (d2 - d1 <= 1e-12 * d1) {
@@ -404,7 +425,7 @@ static void simulate_path_lazy(job_t* jb, int64_t r, int32_t* X, double* T, doub
         double E_mu = rto_exp1(seed, traj, nid, (uint32_t)mu, n_mu);
         if (E_mu < 0) jb->stats.hard_cases++;
         P[mu] += E_mu;
-        lazy_refresh(jb, X, mu, t, T, P, a, inv, tau);
+        lazy_refresh(jb, X, mu, t, T, P, a, inv, tau, crate);
         /* each dependent runs its clock to t at its old propensity (Eq. 15),
          * then takes the new one */
         for (int q = jb->dep_ptr[mu]; q < jb->dep_ptr[mu + 1]; q++) {
@@ -412,7 +433,7 @@ static void simulate_path_lazy(job_t* jb, int64_t r, int32_t* X, double* T, doub
             if (k == mu) continue;
             T[k] = fma(a[k], t - s_up[k], T[k]);
             s_up[k] = t;
-            lazy_refresh(jb, X, k, t, T, P, a, inv, tau);
+            lazy_refresh(jb, X, k, t, T, P, a, inv, tau, crate);
         }
         if (fired >= jb->max_firings) { st = RTO_MAX_FIRINGS; break; }
     }
@@ -812,6 +833,25 @@ int rto_lazy_simulate(const rto_network* net, const int32_t* x0, int32_t x0_per_
     return run_all(net, x0, x0_per_traj, t_end, sample_t, G, seed, net_id, traj_offset, R,
                    max_firings, samples, n_out, T_out, x_final, t_last, status, seq_hash,
                    tie_step, nthreads, stats, 2, 0, NULL, NULL);
+}
+
+int rto_lazy_simulate_schedule(const rto_network* net, const int32_t* x0, int32_t x0_per_traj,
+                               double t_end, const double* sample_t, int32_t G,
+                               uint64_t seed, uint32_t net_id, uint64_t traj_offset, int64_t R,
+                               uint64_t max_firings,
+                               int32_t* samples, uint32_t* n_out, double* T_out,
+                               int32_t* x_final, double* t_last, uint8_t* status,
+                               uint64_t* seq_hash, uint32_t* tie_step, int32_t nthreads,
+                               rto_stats* stats, int32_t B, const double* sched_t,
+                               const double* sched_c)
+{
+    if (B < 0 || (B > 0 && (!sched_t || !sched_c))) return RTO_E_INVALID;
+    for (int32_t i = 0; i < B; i++)
+        if (!(sched_t[i] > (i ? sched_t[i - 1] : 0.0)) || !isfinite(sched_t[i]))
+            return RTO_E_INVALID;
+    return run_all(net, x0, x0_per_traj, t_end, sample_t, G, seed, net_id, traj_offset, R,
+                   max_firings, samples, n_out, T_out, x_final, t_last, status, seq_hash,
+                   tie_step, nthreads, stats, 2, B, sched_t, sched_c);
 }
 
 int rto_direct_simulate(const rto_network* net, const int32_t* x0, int32_t x0_per_traj,

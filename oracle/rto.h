@@ -89,6 +89,19 @@ int rto_lazy_simulate(const rto_network* net, const int32_t* x0, int32_t x0_per_
                       double* t_last, uint8_t* status, uint64_t* seq_hash, uint32_t* tie_step,
                       int32_t nthreads, rto_stats* stats);
 
+/* rto_lazy_simulate with piecewise-constant rate constants (as
+ * rto_simulate_schedule): at a breakpoint every clock runs to it at its old
+ * propensity and every channel takes the new rates. */
+int rto_lazy_simulate_schedule(const rto_network* net, const int32_t* x0, int32_t x0_per_traj,
+                               double t_end, const double* sample_t, int32_t G,
+                               uint64_t seed, uint32_t net_id, uint64_t traj_offset, int64_t R,
+                               uint64_t max_firings,
+                               int32_t* samples, uint32_t* n_out, double* T_out,
+                               int32_t* x_final, double* t_last, uint8_t* status,
+                               uint64_t* seq_hash, uint32_t* tie_step, int32_t nthreads,
+                               rto_stats* stats, int32_t B, const double* sched_t,
+                               const double* sched_c);
+
 /* Gillespie's direct method (section 3, Eq. 17-22) with draws keyed like the
  * GPU library's direct method: one Philox4x32-10 block per firing at counter
  * (firing index, 0xFFFFFFFF, traj, net_id).  Same arrays as rto_simulate

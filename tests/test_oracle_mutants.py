@@ -64,10 +64,33 @@ DIRECT_MUTANTS = {
 SCHEDULE_MUTANTS = {
     "sched_clock_not_run_to_breakpoint": ("for (int k = 0; k < M; k++) T[k] = fma(a[k], db, T[k]);",
                                           "for (int k = 0; k < M; k++) T[k] = T[k];"),
-    "sched_rates_one_piece_late": ("crate = jb->sched_c + (size_t)piece * M;",
-                                   "crate = piece ? jb->sched_c + (size_t)(piece - 1) * M : net->c;"),
-    "sched_time_not_moved": ("            t = b_next;\n            crate",
-                             "            crate"),
+    "sched_rates_one_piece_late": ("crate = jb->sched_c + (size_t)piece * M;\n"
+                                   "            piece += 1;\n"
+                                   "            b_next = piece < jb->B ? jb->sched_t[piece] : INFINITY;\n"
+                                   "            for (int k = 0; k < M; k++) {",
+                                   "crate = piece ? jb->sched_c + (size_t)(piece - 1) * M : net->c;\n"
+                                   "            piece += 1;\n"
+                                   "            b_next = piece < jb->B ? jb->sched_t[piece] : INFINITY;\n"
+                                   "            for (int k = 0; k < M; k++) {"),
+    "sched_time_not_moved": ("T[k] = fma(a[k], db, T[k]);\n            t = b_next;\n",
+                             "T[k] = fma(a[k], db, T[k]);\n"),
+}
+
+# the same mistakes in the lazy form's breakpoint (checked by the same pins,
+# run in the lazy form)
+LAZY_SCHEDULE_MUTANTS = {
+    "lazy_sched_clock_not_run": ("                T[k] = fma(a[k], b_next - s_up[k], T[k]);\n", ""),
+    "lazy_sched_rates_one_piece_late": (
+        "crate = jb->sched_c + (size_t)piece * M;\n"
+        "            piece += 1;\n"
+        "            b_next = piece < jb->B ? jb->sched_t[piece] : INFINITY;\n"
+        "            for (int k = 0; k < M; k++) lazy_refresh",
+        "crate = piece ? jb->sched_c + (size_t)(piece - 1) * M : net->c;\n"
+        "            piece += 1;\n"
+        "            b_next = piece < jb->B ? jb->sched_t[piece] : INFINITY;\n"
+        "            for (int k = 0; k < M; k++) lazy_refresh"),
+    "lazy_sched_time_not_moved": ("                s_up[k] = b_next;\n            }\n            t = b_next;\n",
+                                  "                s_up[k] = b_next;\n            }\n"),
 }
 
 
@@ -79,11 +102,11 @@ LAZY_MUTANTS = {
                                  "            T[k] = fma(a[k], t - s_up[k], T[k]);\n"),
     "lazy_advance_at_new_rate": ("            T[k] = fma(a[k], t - s_up[k], T[k]);\n"
                                  "            s_up[k] = t;\n"
-                                 "            lazy_refresh(jb, X, k, t, T, P, a, inv, tau);",
-                                 "            lazy_refresh(jb, X, k, t, T, P, a, inv, tau);\n"
+                                 "            lazy_refresh(jb, X, k, t, T, P, a, inv, tau, crate);",
+                                 "            lazy_refresh(jb, X, k, t, T, P, a, inv, tau, crate);\n"
                                  "            T[k] = fma(a[k], t - s_up[k], T[k]);\n"
                                  "            s_up[k] = t;"),
-    "lazy_fired_not_refreshed": ("        lazy_refresh(jb, X, mu, t, T, P, a, inv, tau);\n", ""),
+    "lazy_fired_not_refreshed": ("        lazy_refresh(jb, X, mu, t, T, P, a, inv, tau, crate);\n", ""),
     "lazy_tau_not_offset": ("tau[k] = t + gap;", "tau[k] = gap;"),
     "lazy_no_final_advance": ("double t_stop = good ? jb->t_end : t;", "double t_stop = t;"),
     "lazy_reused_draw": ("(uint32_t)mu, n_mu);", "(uint32_t)mu, n_mu - 1);"),
@@ -104,7 +127,8 @@ TREE_DM_MUTANTS = {
 
 def _build_mutant(tmp, name):
     old, new = (MUTANTS.get(name) or DIRECT_MUTANTS.get(name) or SCHEDULE_MUTANTS.get(name)
-                or LAZY_MUTANTS.get(name) or TREE_DM_MUTANTS[name])
+                or LAZY_MUTANTS.get(name) or LAZY_SCHEDULE_MUTANTS.get(name)
+                or TREE_DM_MUTANTS[name])
     src = open(os.path.join(ORACLE_DIR, "rto.c")).read()
     assert src.count(old) == 1, name
     for f in ("rto.h", "dm.c"):
@@ -268,12 +292,12 @@ def test_direct_pins_pass_on_the_real_oracle():
     assert _direct_pin_failures(oracle.lib()) == []
 
 
-def _schedule_pin_failures(L):
+def _schedule_pin_failures(L, lazy=False):
     """A quick subset of the schedule pins (tests/test_oracle_schedule.py)."""
     failed = []
     try:
         o = oracle.simulate(W.pure_birth(10.0), [0], 3.0, [0.5, 1.5, 2.5, 3.0], 1, 8000,
-                            schedule=([1.0, 2.0], [[0.0], [30.0]]), _lib=L)
+                            schedule=([1.0, 2.0], [[0.0], [30.0]]), _lib=L, lazy=lazy)
         for g, m in enumerate((5.0, 10.0, 25.0, 40.0)):
             X = o["samples"][:, g, 0].astype(float)
             if abs(X.mean() - m) > 4.5 * math.sqrt(m / X.size):
@@ -282,7 +306,7 @@ def _schedule_pin_failures(L):
         if not np.allclose(o["T"][:, 0], 40.0, rtol=1e-13):
             failed.append("birth_clock")
         o = oracle.simulate(W.birth_death(50.0, 1.0), [0], 3.0, [1.5, 3.0], 2, 8000,
-                            schedule=([1.0], [[10.0, 1.0]]), _lib=L)
+                            schedule=([1.0], [[10.0, 1.0]]), _lib=L, lazy=lazy)
         m1 = 50.0 * (1 - math.exp(-1.0))
         for g, t in enumerate((1.5, 3.0)):
             m = 10.0 + (m1 - 10.0) * math.exp(-(t - 1.0))
@@ -306,6 +330,19 @@ def test_schedule_pins_catch_planted_mistake(name):
 
 def test_schedule_pins_pass_on_the_real_oracle():
     assert _schedule_pin_failures(oracle.lib()) == []
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("name", sorted(LAZY_SCHEDULE_MUTANTS))
+def test_lazy_schedule_pins_catch_planted_mistake(name):
+    with tempfile.TemporaryDirectory() as tmp:
+        L = _build_mutant(tmp, name)
+        failed = _schedule_pin_failures(L, lazy=True)
+    assert failed, "mutant %s passed every pin" % name
+
+
+def test_lazy_schedule_pins_pass_on_the_real_oracle():
+    assert _schedule_pin_failures(oracle.lib(), lazy=True) == []
 
 
 def _lazy_pin_failures(L):
