@@ -97,10 +97,12 @@ def cpu_baseline(w, target_s):
             "sample": "first %d of the %d trajectories (%d firings, %.1f s)" % (R, w.R, fir, dt)}
 
 
-def run_ensemble(api, w, steps, warmup, block=0, grid=0, mapping=0, method=0):
+def run_ensemble(api, w, steps, warmup, block=0, grid=0, mapping=0, method=0, schedule=None):
     import torch
     dev = torch.device("cuda:0")
     net = api.Network(w.net, device=dev)
+    if schedule is not None:
+        net.set_schedule(*schedule)
     R, G, N, M = w.R, len(w.sample_t), w.net.N, w.net.M
     out = {
         "samples": torch.empty((R, G, N), dtype=torch.int32, device=dev),
@@ -294,6 +296,20 @@ def bench_large_lazy(api, W, steps, warmup, eager_value=None):
                           "kernel_ms": d["kernel_s"] * 1e3,
                           "firings_per_step": d["firings_per_step"]}
     out["random_time_vs_direct"] = out["value"] / out["direct_tree"]["value"]
+    # the same network with piecewise-constant rates: breakpoints at 0.2, 0.4,
+    # 0.6 and 0.8 of t_end, each piece scaling every rate by one factor (1.2,
+    # 0.8, 1.1, 0.9; a time warp with the same integral, so the firing counts
+    # match and the ratio is the cost of the breakpoints: every clock run to
+    # each, every leaf and the whole tree rebuilt)
+    import numpy as np
+    times = np.array([0.2, 0.4, 0.6, 0.8]) * w.t_end
+    rates = np.array([1.2, 0.8, 1.1, 0.9])[:, None] * np.asarray(w.net.c)[None, :]
+    s = run_ensemble(api, w, steps, warmup, method=api.METHOD_LAZY, schedule=(times, rates))
+    out["with_schedule"] = {"value": s["firings"] / s["wall"], "unit": "firings/s",
+                            "kernel_ms": s["kernel_s"] * 1e3,
+                            "firings_per_step": s["firings_per_step"],
+                            "breakpoints": [float(v) for v in times]}
+    out["schedule_vs_constant"] = out["with_schedule"]["value"] / out["value"]
     return out
 
 

@@ -107,7 +107,11 @@ typedef struct {
  * RN(tau_(2) - t) with RN(tau_(1) - t).  Same draws and law as RANDOM_TIME,
  * its own rounding.  One wavefront per trajectory (stats.mapping =
  * RTSSA_MAP_WAVE, block 64) with the tree in LDS; mapping must be AUTO or
- * WAVE; no rate schedule; E_UNSUPPORTED when the tree does not fit LDS
+ * WAVE.  With a rate schedule, at a breakpoint b every channel runs its
+ * clock to b at its old propensity, T_k = fma(a_k, RN(b - s_k), T_k),
+ * s_k = b, and takes the new rates and a new tau_k from t = b (a negative gap
+ * is clamped and counted as above); nothing fires at b.  E_UNSUPPORTED when
+ * the tree does not fit LDS
  * (about 13,000 channels).  The first LAZY run of a network builds its
  * fixed-stride rows (about 270 bytes per channel of device memory, kept
  * until the network is destroyed); that first run must not overlap another
@@ -122,8 +126,8 @@ typedef struct {
  * root with r = RN(u2 a_0) and at each node takes the first child with
  * v_i > 0 and r <= v_i (the last positive child if none), subtracting each
  * child it passes, r = RN(r - v_i).  Same law as DIRECT, its own rounding.
- * As DIRECT: T_out and tie_step must be NULL; as LAZY: mapping AUTO or
- * WAVE, no rate schedule, the same LDS limit and first-run rows. */
+ * As DIRECT: T_out and tie_step must be NULL and no rate schedule; as LAZY:
+ * mapping AUTO or WAVE, the same LDS limit and first-run rows. */
 enum {
     RTSSA_METHOD_RANDOM_TIME = 0,
     RTSSA_METHOD_DIRECT = 1,
@@ -189,8 +193,8 @@ int rtssa_network_info(const rtssa_network* net, int32_t* N, int32_t* M,
  * internal time runs to the breakpoint at the old rates
  * (T_k = fma(a_k, b - t, T_k)), t becomes the breakpoint and every a_k and
  * 1/a_k is recomputed with the new rates; no firing, no sample.  A network
- * with a schedule runs with the random-time method in every mapping, not in
- * the direct method (E_UNSUPPORTED).  Call it only while no launch using
+ * with a schedule runs with the random-time method in every mapping and in
+ * the LAZY form, not in DIRECT or DIRECT_TREE (E_UNSUPPORTED).  Call it only while no launch using
  * the network is in flight; while a batch holds the network it fails
  * with E_INVALID (the batch keeps the schedule's device address). */
 int rtssa_network_set_schedule(rtssa_network* net, int32_t B, const double* times,

@@ -193,8 +193,8 @@ extern "C" int rtssa_simulate(const rtssa_network* net, const int32_t* x0, int32
         return rt_fail(RTSSA_E_INVALID, "the direct method has no internal times or near-ties: "
                                         "T_out and tie_step must be NULL");
     if (wave_tree) {
-        if (net->dev.sched_B > 0)
-            return rt_fail(RTSSA_E_UNSUPPORTED, "the tree methods take no rate schedule");
+        if (o.method == RTSSA_METHOD_DIRECT_TREE && net->dev.sched_B > 0)
+            return rt_fail(RTSSA_E_UNSUPPORTED, "the direct method takes no rate schedule");
         if (o.mapping != RTSSA_MAP_AUTO && o.mapping != RTSSA_MAP_WAVE)
             return rt_fail(RTSSA_E_UNSUPPORTED, "the tree methods run one wavefront per trajectory");
         if (o.block != 0 && o.block != 64)

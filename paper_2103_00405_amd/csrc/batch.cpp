@@ -155,8 +155,9 @@ static int batch_create(const rtssa_batch_item* items, int32_t count, const rtss
             return rt_fail(RTSSA_E_UNSUPPORTED, at + "batched items run RANDOM_TIME, LAZY or "
                                                      "DIRECT_TREE");
         if (b.method != RTSSA_METHOD_RANDOM_TIME) {
-            if (b.net->dev.sched_B > 0)
-                return rt_fail(RTSSA_E_UNSUPPORTED, at + "the tree methods take no rate schedule");
+            if (b.method == RTSSA_METHOD_DIRECT_TREE && b.net->dev.sched_B > 0)
+                return rt_fail(RTSSA_E_UNSUPPORTED,
+                               at + "the direct method takes no rate schedule");
             if (b.method == RTSSA_METHOD_DIRECT_TREE && (b.T_out || b.tie_step))
                 return rt_fail(RTSSA_E_INVALID, at + "the direct method has no T_out or tie_step");
             if (b.R > 0) {
@@ -207,7 +208,9 @@ static int batch_create(const rtssa_batch_item* items, int32_t count, const rtss
     for (size_t ci = 0; ci < B->classes.size(); ++ci) {
         auto& c = B->classes[ci];
         if (c.key.method != RTSSA_METHOD_LAZY) continue;
-        int rc = rt_lazy_grid(c.max_N, c.max_M, o.grid, c.units, &c.lazy_grid);
+        bool sched = false;
+        for (int i : c.members) sched |= items[i].net->dev.sched_B > 0;
+        int rc = rt_lazy_grid(c.max_N, c.max_M, o.grid, c.units, sched, &c.lazy_grid);
         if (rc) {
             delete B;
             return rc;

@@ -157,14 +157,14 @@ bool rt_group_supported(int M, int L);
 size_t rt_group_lds_bytes(int N, int M, int L);
 int rt_launch_subwave(int max_M, const rt_class_dev& C, int L, int grid, hipStream_t stream,
                       int* grid_used);
-// the lazy form (one wavefront per trajectory, LDS tree); allocates its
-// channel workspace stream-ordered
+// the lazy form (one wavefront per trajectory, LDS tree)
 // workspace: NULL to allocate it stream-ordered for this launch, else at
 // least rt_lazy_workspace_bytes(grid, max_M) bytes for the grid that
 // rt_lazy_grid returns (the same grid the launch then uses)
 int rt_launch_lazy(const rt_class_dev& C, int max_N, int max_M, int grid, int64_t units,
                    hipStream_t stream, int* grid_used, void* workspace = nullptr);
-int rt_lazy_grid(int max_N, int max_M, int grid, int64_t units, int* grid_out);
+// sched: the class has a rate schedule (C.has_schedule), which picks the kernel
+int rt_lazy_grid(int max_N, int max_M, int grid, int64_t units, bool sched, int* grid_out);
 size_t rt_lazy_workspace_bytes(int grid, int max_M);
 size_t rt_lazy_lds_bytes(int N, int M);
 // the direct method on a sum tree (same mapping and layout as the lazy form)

@@ -279,6 +279,11 @@ __device__ __forceinline__ rt_lazy_rec lazy_touch(rt_lazy_rec rc, bool fresh, do
     return rc;
 }
 
+// SCHED: some network of the class has piecewise-constant rates.  When the
+// next event lies past the next breakpoint b (b < t_end), every channel runs
+// its clock to b at its old propensity, takes the next piece's rates and a new
+// next firing time from b, the tree is rebuilt, and nothing fires at b.
+template <bool SCHED>
 __global__ __launch_bounds__(64) void rt_lazy_kernel(rt_class_dev C, rt_lazy_rec* rec_ws,
                                                      unsigned long long* w_ws, uint32_t* n_ws,
                                                      int64_t m_stride)
@@ -308,7 +313,7 @@ __global__ __launch_bounds__(64) void rt_lazy_kernel(rt_class_dev C, rt_lazy_rec
         const rt_net_dev net = it->net;
         const int N = net.N, M = net.M;
         const rt_cptr<int2> react = rt_const(net.react);
-        const rt_cptr<double> cc = rt_const(net.c);
+        rt_cptr<double> cc = rt_const(net.c);             // the rates of the current piece
         const rt_cptr<int32_t> dep_ptr = rt_const(net.dep_ptr), dep_idx = rt_const(net.dep_idx);
         const rt_cptr<int32_t> touch = rt_const(net.touch), touch_more = rt_const(net.touch_more);
         const rt_cptr<int2> nu_fixed = rt_const(net.nu_fixed);
@@ -400,13 +405,40 @@ __global__ __launch_bounds__(64) void rt_lazy_kernel(rt_class_dev C, rt_lazy_rec
         uint32_t fired = 0, tie = kTieNone;
         unsigned long long hash = kFnvOffset;
         int st = RTSSA_TRAJ_OK;
+        int32_t piece = 0;
+        double b_next = SCHED && net.sched_B > 0 ? rt_const(net.sched_t)[0] : __builtin_inf();
 
         for (;;) {
             // ---- the next event: the root of the tree
             const double tau1 = root_tau;
             const int mu = __builtin_amdgcn_readfirstlane(root_ch);
-            if (tau1 == __builtin_inf()) { st = RTSSA_TRAJ_ABSORBED; break; }
             const double t_new = tau1;
+            if (SCHED && b_next < t_end && t_new > b_next) {
+                // ---- a rate breakpoint comes first (every value tested here
+                // is the same in every lane): all clocks run to it at their old
+                // propensities, then new rates, new leaves, the whole tree
+                t = b_next;
+                cc = rt_const(net.sched_c + (int64_t)piece * M);
+                ++piece;
+                b_next = piece < net.sched_B ? rt_const(net.sched_t)[piece] : __builtin_inf();
+                for (int k = lane; k < M; k += 64)
+                    recs[k] = lazy_touch(recs[k], false, 0.0, t, react[k], cc[k], X, &leaves[k],
+                                         &ws->clamps);
+                wave_lds_fence();
+#pragma unroll
+                for (int l = 1; l <= kMaxLevels; ++l) {
+                    if (l > top) break;
+                    for (int j = lane; j < tr.cnt[l]; j += 64)
+                        lazy_store(tr, l, j, lazy_node(tr, l, j));
+                    wave_lds_fence();
+                }
+                top_e = lazy_top_entry(top_d, top_k, top_cnt, top == 0, lane);
+                root = lazy_wave_argmin(top_e);
+                root_tau = root.d;
+                root_ch = root.k;
+                continue;
+            }
+            if (tau1 == __builtin_inf()) { st = RTSSA_TRAJ_ABSORBED; break; }
             if (t_new > t_end) break;
             while (s_next < t_new) {
                 if (it->samples) {
@@ -808,8 +840,9 @@ static size_t dmtree_lds_bytes(int N, int M) { return tree_lds_bytes(N, M, 1); }
 
 // The lazy kernel's grid: the requested one, or the resident wavefronts
 // (LDS-limited) of the device, never more than the trajectories.
-int rt_lazy_grid(int max_N, int max_M, int grid, int64_t units, int* grid_out)
+int rt_lazy_grid(int max_N, int max_M, int grid, int64_t units, bool sched, int* grid_out)
 {
+    const void* fn = sched ? (const void*)rt_lazy_kernel<true> : (const void*)rt_lazy_kernel<false>;
     const size_t lds = rt_lazy_lds_bytes(max_N, max_M);
     if (lds == 0) return rt_fail(RTSSA_E_UNSUPPORTED, "network too large for the lazy form");
     int dev = 0, lds_max = 0, cus = 0;
@@ -821,13 +854,13 @@ int rt_lazy_grid(int max_N, int max_M, int grid, int64_t units, int* grid_out)
     if (lds + RT_LOG_SCRATCH * 4 > (size_t)lds_max)
         return rt_fail(RTSSA_E_UNSUPPORTED, "network too large for the lazy form's LDS tree");
     if (lds > 48 * 1024 &&
-        hipFuncSetAttribute((const void*)rt_lazy_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
-                            (int)lds) != hipSuccess)
+        hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) !=
+            hipSuccess)
         return rt_fail(RTSSA_E_HIP, "cannot raise the LDS limit");
     if (grid <= 0) {
         int per_cu = 0;
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, rt_lazy_kernel, 64, lds) !=
-                hipSuccess || per_cu < 1)
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, 64, lds) != hipSuccess ||
+            per_cu < 1)
             per_cu = 1;
         grid = cus * per_cu;
     }
@@ -846,7 +879,8 @@ size_t rt_lazy_workspace_bytes(int grid, int max_M)
 int rt_launch_lazy(const rt_class_dev& C, int max_N, int max_M, int grid, int64_t units,
                    hipStream_t stream, int* grid_used, void* workspace)
 {
-    int rc = rt_lazy_grid(max_N, max_M, grid, units, &grid);
+    const bool sched = C.has_schedule != 0;
+    int rc = rt_lazy_grid(max_N, max_M, grid, units, sched, &grid);
     if (rc) return rc;
     if (grid_used) *grid_used = grid;
     const size_t lds = rt_lazy_lds_bytes(max_N, max_M);
@@ -859,7 +893,8 @@ int rt_launch_lazy(const rt_class_dev& C, int max_N, int max_M, int grid, int64_
     }
     const size_t rec_bytes = (size_t)grid * m_stride * sizeof(rt_lazy_rec);
     const size_t word_bytes = (size_t)grid * m_stride * sizeof(unsigned long long);
-    hipLaunchKernelGGL(rt_lazy_kernel, dim3(grid), dim3(64), lds, stream, C, (rt_lazy_rec*)wsp,
+    auto* kern = sched ? rt_lazy_kernel<true> : rt_lazy_kernel<false>;
+    hipLaunchKernelGGL(kern, dim3(grid), dim3(64), lds, stream, C, (rt_lazy_rec*)wsp,
                        (unsigned long long*)((char*)wsp + rec_bytes),
                        (uint32_t*)((char*)wsp + rec_bytes + word_bytes), m_stride);
     rc = hipGetLastError() == hipSuccess ? RTSSA_OK

@@ -3,9 +3,10 @@ updates, 8-ary minimum tree in LDS).
 
 Every output is compared bit for bit with the oracle's lazy form on random
 networks from 1 to 8000 channels (tree depths 1 to 5), on a network where a
-firing touches more than 64 channels, on every end state, and on the large
-random network (N = 1000, M = 4000) at its full ensemble size, where sampled
-trajectories are recomputed by the oracle and Eq. 5 is checked on all."""
+firing touches more than 64 channels, on every end state, with piecewise-constant
+rate schedules (alone and in a batch), and on the large random network
+(N = 1000, M = 4000) at its full ensemble size, where sampled trajectories are
+recomputed by the oracle and Eq. 5 is checked on all."""
 import numpy as np
 import pytest
 import torch
@@ -148,9 +149,106 @@ def test_refuses_what_it_does_not_run():
     net = api.Network(w.net)
     with pytest.raises(api._lib.RtssaError):
         api.simulate(net, w.x0, 1.0, [1.0], 8, method=api.METHOD_LAZY, mapping=api.MAP_THREAD)
-    net.set_schedule([0.5], [[1.0, 0.01, 1.0]])
-    with pytest.raises(api._lib.RtssaError):
-        api.simulate(net, w.x0, 1.0, [1.0], 8, method=api.METHOD_LAZY)
+
+
+def _schedule(spec, t_end, seed):
+    """Breakpoints at 0.2, 0.45, 0.7 and 1.3 of t_end (the last one never
+    reached); each piece scales every rate by a factor in [0.2, 3] and the
+    second switches about a third of the channels off."""
+    rng = np.random.default_rng(1000 + seed)
+    times = np.array([0.2, 0.45, 0.7, 1.3]) * t_end
+    c = np.asarray(spec.c, dtype=np.float64)
+    rates = c[None, :] * rng.uniform(0.2, 3.0, size=(times.size, c.size))
+    rates[1, rng.random(c.size) < 0.35] = 0.0
+    return times, rates
+
+
+def _run_sched(api, spec, sched, x0, t_end, grid, R, seed):
+    net = api.Network(spec)
+    net.set_schedule(*sched)
+    g = api.simulate(net, np.asarray(x0, np.int32), t_end, grid, R, seed=seed, net_id=seed,
+                     with_hash=True, method=api.METHOD_LAZY)
+    torch.cuda.synchronize()
+    ref = oracle.simulate(spec, x0, t_end, grid, seed, R, net_id=seed, lazy=True,
+                          schedule=sched)
+    _assert_same(g, ref)
+    return g
+
+
+@pytest.mark.parametrize("N,M,seed", [
+    (1, 1, 41), (3, 8, 42), (10, 64, 43), (12, 65, 44), (60, 513, 45), (250, 2000, 46),
+    (500, 4097, 47),
+])
+def test_schedule_random_networks_bit_exact(N, M, seed):
+    """Every clock runs to each breakpoint and the leaves and the whole tree
+    are rebuilt with the new rates: the bits of the oracle's lazy form."""
+    api = _api()
+    spec, x0 = _net(N, M, seed)
+    t_end = float(1200 / max(W.initial_total_rate(spec, x0), 1e-9))
+    grid = np.sort(np.random.default_rng(seed).uniform(0, t_end, size=9))
+    _run_sched(api, spec, _schedule(spec, t_end, seed), x0, t_end, grid, 24, seed)
+
+
+def test_schedule_closed_forms_and_wide_touch():
+    api = _api()
+    # birth at 10, 0 on [1, 2), 30 after: nothing absorbed, T(3) = 40
+    grid = np.array([0.5, 1.5, 2.5, 3.0])
+    sched = (np.array([1.0, 2.0]), np.array([[0.0], [30.0]]))
+    g = _run_sched(api, W.pure_birth(10.0), sched, [0], 3.0, grid, 256, 4)
+    assert (_np(g["status"]) == api.TRAJ_OK).all()
+    assert np.allclose(_np(g["T"])[:, 0], 40.0, rtol=1e-13, atol=0)
+    # an all-zero last piece absorbs at the breakpoint
+    sched = (np.array([1.0]), np.array([[0.0]]))
+    g = _run_sched(api, W.pure_birth(10.0), sched, [0], 3.0, grid, 64, 5)
+    assert (_np(g["status"]) == api.TRAJ_ABSORBED).all() and (_np(g["t_last"]) == 1.0).all()
+    # Lotka-Volterra with a piece where predation stops
+    w = W.lv_small(64)
+    sched = (np.array([0.5, 1.0, 1.5]),
+             np.array([[5.0, 0.02, 5.0], [10.0, 0.0, 2.0], [8.0, 0.01, 12.0]]))
+    _run_sched(api, w.net, sched, w.x0, 2.0, W.uniform_grid(2.0, 21), 48, 3)
+    # a firing that touches 100 channels, rates switched twice
+    rx = [({}, {0: 1}, 40.0)]
+    rx += [({0: 1, i: 1}, {i: 1}, 0.002 * (1 + i % 7)) for i in range(1, 101)]
+    rx += [({i: 1}, {}, 0.01) for i in range(1, 101, 9)]
+    spec = W.from_reactions(101, rx)
+    x0 = np.concatenate([[0], np.random.default_rng(3).integers(5, 60, size=100)]).astype(np.int32)
+    c = np.asarray(spec.c)
+    sched = (np.array([1.0, 2.0]), np.stack([c * 2.0, c * 0.5]))
+    _run_sched(api, spec, sched, x0, 3.0, W.uniform_grid(3.0, 7), 64, 6)
+
+
+def test_schedule_in_a_batch():
+    """Lazy items with and without schedules share one class (the scheduled
+    kernel runs both); each equals its own run and the oracle."""
+    api = _api()
+    rng = np.random.default_rng(51)
+    jobs, specs = [], []
+    for i, M in enumerate([70, 300, 900, 130, 2000, 520]):
+        N = max(2, M // 4)
+        spec = W.random_network(N, M, rng, logc=(-1.0, 1.0), bimol_scale=0.05)
+        x0 = rng.integers(0, 80, size=N).astype(np.int32)
+        t_end = float(600 / max(W.initial_total_rate(spec, x0), 1e-9))
+        net = api.Network(spec)
+        sched = None
+        if i % 2 == 0:
+            sched = _schedule(spec, t_end, 60 + i)
+            net.set_schedule(*sched)
+        jobs.append(dict(net=net, x0=x0, t_end=t_end, sample_t=W.uniform_grid(t_end, 6), R=12,
+                         net_id=i, method=api.METHOD_LAZY))
+        specs.append((spec, sched))
+    b = api.Batch(jobs, with_hash=True)
+    b.run(seed=5)
+    torch.cuda.synchronize()
+    for j, o, (spec, sched) in zip(jobs, b.outputs, specs):
+        solo = api.simulate(j["net"], j["x0"], j["t_end"], j["sample_t"], j["R"], seed=5,
+                            net_id=j["net_id"], with_hash=True, method=api.METHOD_LAZY)
+        torch.cuda.synchronize()
+        for k in KEYS:
+            assert torch.equal(o[k], solo[k]), (j["net_id"], k)
+        ref = oracle.simulate(spec, j["x0"], j["t_end"], j["sample_t"], 5, j["R"],
+                              net_id=j["net_id"], lazy=True, schedule=sched)
+        _assert_same(o, ref, stats=False)
+    b.close()
 
 
 def test_large_random_network_full_size():

@@ -108,33 +108,3 @@ def test_schedule_identities():
     with pytest.raises(RuntimeError):
         oracle.simulate(w.net, w.x0, 5.0, [5.0], 1, 4, schedule=([2.0, 2.0], np.ones((2, 3))))
 
-
-@pytest.mark.parametrize("which", ["lv", "random"])
-def test_lazy_and_eager_fire_the_same_sequences(lazy, which):
-    """With a schedule too the two forms differ only in rounding: the same
-    channels fire on nearly every trajectory and the internal times agree to
-    rounding level where they do."""
-    if not lazy:
-        pytest.skip("compares the two forms once")
-    if which == "lv":
-        w = W.lv_small(256)
-        net, x0, t_end, R = w.net, w.x0, 4.0, 256
-        sched = ([1.0, 2.5], np.array([[2.0, 0.005, 0.5], [0.5, 0.02, 2.0]]))
-    else:
-        rng = np.random.default_rng(40)
-        net = W.random_network(30, 90, rng, logc=(-1.0, 1.0), bimol_scale=0.05)
-        x0 = rng.integers(0, 80, size=30).astype(np.int32)
-        t_end = float(2000 / W.initial_total_rate(net, x0))
-        c = np.asarray(net.c)
-        rates = c[None, :] * rng.uniform(0.2, 3.0, size=(3, c.size))
-        rates[1, rng.random(c.size) < 0.35] = 0.0
-        sched, R = (np.array([0.2, 0.45, 0.7]) * t_end, rates), 128
-    grid = W.uniform_grid(t_end, 9)
-    z = oracle.simulate(net, x0, t_end, grid, 9, R, schedule=sched)
-    e = oracle.simulate.func(net, x0, t_end, grid, 9, R, schedule=sched)
-    same = e["seq_hash"] == z["seq_hash"]
-    assert same.mean() >= 0.95, same.mean()
-    for k in ("n", "x_final", "samples", "status"):
-        assert np.array_equal(e[k][same], z[k][same]), k
-    rel = np.abs(e["T"][same] - z["T"][same]) / np.maximum(np.abs(e["T"][same]), 1.0)
-    assert rel.max() < 1e-9
