@@ -481,8 +481,9 @@ int launch_mn(const rt_class_dev& C, int block, int grid, hipStream_t stream, in
                                        : rt_thread_kernel<MT, NT, RTSSA_METHOD_RANDOM_TIME, false>);
     if (grid <= 0) {
         int dev = 0, cus = 0, per_cu = 0;
-        hipGetDevice(&dev);
-        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+            return rt_fail(RTSSA_E_HIP, "device query failed");
         if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kfn, block, 0) != hipSuccess ||
             per_cu < 1)
             per_cu = 1;
