@@ -407,6 +407,16 @@ __global__ __launch_bounds__(64) void rt_lazy_kernel(rt_class_dev C, rt_lazy_rec
         int st = RTSSA_TRAJ_OK;
         int32_t piece = 0;
         double b_next = SCHED && net.sched_B > 0 ? rt_const(net.sched_t)[0] : __builtin_inf();
+        // the count and kept word of the channel that fired last (last_mu)
+        // come from registers, never from a load: a load issued while the
+        // store of the same address is still in flight may return the old
+        // value.  Every other channel's last store completed before any load
+        // of it is issued (vector memory operations complete in order, and
+        // each firing waits for its row loads, issued after the previous
+        // firing's stores).
+        int last_mu = -1;
+        uint32_t last_nm = 0;
+        unsigned long long last_w = 0;
 
         for (;;) {
             // ---- the next event: the root of the tree
@@ -463,8 +473,10 @@ __global__ __launch_bounds__(64) void rt_lazy_kernel(rt_class_dev C, rt_lazy_rec
             const rt_lazy_rec rc0 = recs[k];
             const int2 rr0 = react[k];
             const double c0 = cc[k];
-            const uint32_t nm = nks[mu];
-            const unsigned long long w_odd = wnext[mu];
+            const uint32_t nm_ld = nks[mu];
+            const unsigned long long w_ld = wnext[mu];
+            const uint32_t nm = mu == last_mu ? last_nm : nm_ld;
+            const unsigned long long w_odd = mu == last_mu ? last_w : w_ld;
             // near-tie test (statistics only) while the loads are in flight
             {
                 const double d1 = t_new - t;
@@ -480,11 +492,13 @@ __global__ __launch_bounds__(64) void rt_lazy_kernel(rt_class_dev C, rt_lazy_rec
             // word when n is odd, else a new block whose odd word is kept
             const uint32_t nd = nm + 1u;
             uint64_t word = w_odd;
+            unsigned long long w_keep = w_odd;              // wnext[mu] after this firing
             if ((nd & 1u) == 0u) {
                 const rt_u4 w =
                     rt_philox4x32_10(rt_u4{nd >> 1, (uint32_t)mu, traj, net_id}, key0, key1);
                 word = ((uint64_t)w.y << 32) | w.x;
-                if (lane == 0) wnext[mu] = ((unsigned long long)w.w << 32) | w.z;
+                w_keep = ((unsigned long long)w.w << 32) | w.z;
+                if (lane == 0) wnext[mu] = w_keep;
             }
             const double E = rt_neglog_uniform(word >> 11, &ws->slow_logs, log_scratch);
             // ---- the jump v_mu, checked against [0, 2^31 - 1]
@@ -532,6 +546,9 @@ __global__ __launch_bounds__(64) void rt_lazy_kernel(rt_class_dev C, rt_lazy_rec
             root_tau = root.d;
             root_ch = root.k;
             if (lane == 0) nks[mu] = nm + 1u;
+            last_mu = mu;
+            last_nm = nm + 1u;
+            last_w = w_keep;
             t = t_new;
             ++fired;
             hash = (hash ^ (unsigned long long)(uint32_t)mu) * kFnvPrime;
