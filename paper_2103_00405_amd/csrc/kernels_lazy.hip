@@ -408,12 +408,9 @@ __global__ __launch_bounds__(64) void rt_lazy_kernel(rt_class_dev C, rt_lazy_rec
         int32_t piece = 0;
         double b_next = SCHED && net.sched_B > 0 ? rt_const(net.sched_t)[0] : __builtin_inf();
         // the count and kept word of the channel that fired last (last_mu)
-        // come from registers, never from a load: a load issued while the
-        // store of the same address is still in flight may return the old
-        // value.  Every other channel's last store completed before any load
-        // of it is issued (vector memory operations complete in order, and
-        // each firing waits for its row loads, issued after the previous
-        // firing's stores).
+        // come from registers, not from a load of what this wavefront stored
+        // at that firing: when the same channel fires again its draw starts
+        // without a round trip to the workspace.
         int last_mu = -1;
         uint32_t last_nm = 0;
         unsigned long long last_w = 0;
