@@ -134,7 +134,7 @@ def run_ensemble(api, w, steps, warmup, block=0, grid=0, mapping=0, method=0, sc
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     return dict(firings=firings, wall=wall, kernel_s=sum(kms) / len(kms) / 1e3, stats=st,
-                firings_per_step=firings / steps)
+                firings_per_step=firings / steps, out=out)
 
 
 def oracle_rate(jobs, threads, target_s):
@@ -152,6 +152,21 @@ def oracle_rate(jobs, threads, target_s):
         if dt > target_s:
             break
     return fir, dt, runs
+
+
+def ensemble_moments(out, sample_t):
+    """Mean and sample variance (n - 1) of every species at every sample
+    point over the trajectories of the last step that ended OK or absorbed
+    (computed after the timed region; a report, not part of a step)."""
+    import torch
+    ok = out["status"] <= 1
+    x = out["samples"][ok].to(torch.float64)            # [trajectories, G, N]
+    mean, var = x.mean(dim=0).cpu().numpy(), x.var(dim=0).cpu().numpy()
+    res = {"trajectories": int(ok.sum()), "t": [float(v) for v in sample_t]}
+    for j in range(mean.shape[1]):
+        res["mean_X%d" % (j + 1)] = [float("%.7g" % v) for v in mean[:, j]]
+        res["var_X%d" % (j + 1)] = [float("%.7g" % v) for v in var[:, j]]
+    return res
 
 
 def bench_lv_small(api, W, reps=5):
@@ -545,6 +560,9 @@ def main():
         "firings_per_step": r["firings_per_step"],
         "near_ties": st["near_ties"],
         "slow_logs": st["slow_logs"],
+        # the measured HBM traffic of one launch over its kernel time
+        "hbm_GBps": LV_TRAFFIC_BYTES_PER_LAUNCH / r["kernel_s"] / 1e9,
+        "ensemble": ensemble_moments(r["out"], w.sample_t),
     }
     if args.calibrate_copy_mib:
         nb = args.calibrate_copy_mib << 20
