@@ -55,14 +55,15 @@ def test_birth_death_analytic_gradient():
 
 def _coupled_fd(api, net, w, c0, k, h, seed, species=0):
     """X_T(species) at c_k e^{+h} and c_k e^{-h} with the same seed and
-    trajectory ids (common per-channel streams)."""
+    trajectory ids (common per-channel streams); species=None: every one."""
     vals = []
     for s in (+1, -1):
         c = c0.copy()
         c[k] *= math.exp(s * h)
         net.set_rates(c)
         o = api.simulate(net, w.x0, w.t_end, w.sample_t, w.R, seed=seed, want=("x_final",))
-        vals.append(o["x_final"][:, species].to(torch.float64))
+        x = o["x_final"].to(torch.float64)
+        vals.append(x if species is None else x[:, species])
     net.set_rates(c0)
     return vals
 
@@ -91,23 +92,27 @@ def test_coupled_finite_differences_birth_death():
 
 
 def test_coupled_finite_differences_lotka_volterra():
-    """The ensemble model at T = 5 (2^18 trajectories): the score estimate of
-    dE[X1_T]/dlog c_k agrees with coupled central differences within their
-    standard errors (no closed form here)."""
+    """The ensemble model at T = 5 (2^18 trajectories): the score estimates of
+    dE[X_j]/dlog c_k and dE[X_j^2]/dlog c_k for both species agree with
+    coupled central differences within their standard errors (no closed form
+    here)."""
     api = _api()
     w = W.lv_gradient()
     net = api.Network(w.net)
     h = 1e-3
     c0 = np.array(w.net.c)
     base = api.simulate(net, w.x0, w.t_end, w.sample_t, w.R, seed=11, want=("x_final", "n", "T"))
-    X = base["x_final"][:, 0].to(torch.float64)
-    g, se = api.score_grad(X, base["n"], base["T"])
-    for k in range(3):
-        up, down = _coupled_fd(api, net, w, c0, k, h, 11)
-        d = (up - down) / (2 * h)
-        fd, fd_se = float(d.mean()), float(d.std() / math.sqrt(w.R))
-        assert abs(fd - float(g[k])) < 3.29 * math.sqrt(fd_se**2 + float(se[k])**2), \
-            (k, fd, fd_se, float(g[k]), float(se[k]))
+    X = base["x_final"].to(torch.float64)
+    fds = [_coupled_fd(api, net, w, c0, k, h, 11, species=None) for k in range(3)]
+    for j in range(2):
+        for power in (1, 2):
+            g, se = api.score_grad(X[:, j] ** power, base["n"], base["T"])
+            for k in range(3):
+                up, down = fds[k]
+                d = (up[:, j] ** power - down[:, j] ** power) / (2 * h)
+                fd, fd_se = float(d.mean()), float(d.std() / math.sqrt(w.R))
+                assert abs(fd - float(g[k])) < 3.29 * math.sqrt(fd_se**2 + float(se[k])**2), \
+                    (j, power, k, fd, fd_se, float(g[k]), float(se[k]))
 
 
 def test_autograd_expectation():
