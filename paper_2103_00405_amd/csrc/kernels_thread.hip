@@ -60,7 +60,8 @@ __device__ __forceinline__ double propensity(int kind, int s0, int s1, double c,
     if (kind == RT_H_ZERO) {
         h = 1;
     } else if (kind == RT_H_ONE) {
-        h = (uint32_t)pick(X, s0);
+        // h < 2^32: its conversion is exact without the two-part form
+        return c * (double)(uint32_t)pick(X, s0);
     } else if (kind == RT_H_PAIR) {
         uint32_t x = (uint32_t)pick(X, s0);
         h = ((uint64_t)x * (uint32_t)(x - 1u)) >> 1;   // x = 0 gives 0
@@ -267,9 +268,11 @@ __global__ __launch_bounds__(256, thread_min_waves(MT, NT, METHOD, SCHED)) void 
                 int32_t dl = nu[0][j];
 #pragma unroll
                 for (int k = 1; k < MT; ++k) dl = (mu == k) ? nu[k][j] : dl;
-                const int64_t v = (int64_t)X[j] + dl;
-                ok = ok && v >= 0 && v <= 0x7FFFFFFF;
-                Xn[j] = (int32_t)v;
+                // X_j in [0, 2^31 - 1] and an int32 change: the exact sum is
+                // outside that range exactly when its 32-bit wrap is negative
+                const int32_t v = (int32_t)((uint32_t)X[j] + (uint32_t)dl);
+                ok = ok && v >= 0;
+                Xn[j] = v;
             }
             const bool event = live && !term && !brk;     // this pass may apply an event
             const bool near_tie = METHOD == RTSSA_METHOD_RANDOM_TIME && event &&
