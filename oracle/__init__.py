@@ -58,6 +58,11 @@ def _configure(L):
     L.rto_neglog_u53.argtypes = [C.c_uint64]
     L.rto_philox4x32_10.restype = None
     L.rto_philox4x32_10.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p]
+    L.rto_argmin2.restype = None
+    L.rto_argmin2.argtypes = [C.c_void_p, C.c_int32, C.POINTER(C.c_int32),
+                              C.POINTER(C.c_double), C.POINTER(C.c_double)]
+    L.rto_near_tie.restype = C.c_int
+    L.rto_near_tie.argtypes = [C.c_double, C.c_double]
     L.rto_simulate.restype = C.c_int
     L.rto_simulate.argtypes = [C.POINTER(_Net), C.c_void_p, C.c_int32, C.c_double,
                                C.c_void_p, C.c_int32, C.c_uint64, C.c_uint32,
@@ -133,6 +138,26 @@ def exp1(seed, traj, net_id, k, n):
 def neglog_u53(m):
     """RN(-ln((m+1) 2^-53)); -1.0 flags an input the quad log cannot certify."""
     return lib().rto_neglog_u53(int(m))
+
+
+def argmin2(values, _lib=None):
+    """The selection step of Eq. 25 over ``values``: (mu, v1, v2) with mu the
+    lowest index among the smallest values (-1 when none is finite), v1 that
+    value and v2 the second smallest counted with multiplicity."""
+    v = np.ascontiguousarray(values, dtype=np.float64)
+    if v.size == 0:
+        v = np.zeros(1, np.float64)
+        M = 0
+    else:
+        M = int(v.size)
+    mu, v1, v2 = C.c_int32(), C.c_double(), C.c_double()
+    (_lib or lib()).rto_argmin2(v.ctypes.data, M, C.byref(mu), C.byref(v1), C.byref(v2))
+    return int(mu.value), float(v1.value), float(v2.value)
+
+
+def near_tie(d1, d2, _lib=None):
+    """The near-tie rule: RN(d2 - d1) <= RN(1e-12 d1)."""
+    return bool((_lib or lib()).rto_near_tie(float(d1), float(d2)))
 
 
 def simulate(net, x0, t_end, sample_t, seed, R, net_id=0, traj_offset=0,

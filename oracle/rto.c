@@ -139,6 +139,38 @@ static double propensity(const rto_network* net, const int32_t* X, int k)
     return propensity_c(net, X, k, net->c[k]);
 }
 
+/* ------------------------------------------------------------ selection */
+/* The selection step of Eq. 25 over M values (the gaps of the eager form,
+ * or the absolute next firing times of the lazy form): *mu is the lowest k
+ * among the smallest values and *v1 that value; *v2 is the second smallest
+ * value counted with multiplicity, so two equal smallest values give
+ * *v2 = *v1, and *v2 = +inf when fewer than two values are finite.  When no
+ * value is finite (nothing can fire, or M = 0), *mu = -1 and *v1 = +inf.
+ * Values are never NaN.  Both path functions below select through this one
+ * function. */
+void rto_argmin2(const double* v, int32_t M, int32_t* mu, double* v1, double* v2)
+{
+    int32_t best = -1;
+    double d1 = INFINITY, d2 = INFINITY;
+    for (int32_t k = 0; k < M; k++) {
+        if (v[k] < d1) { d2 = d1; d1 = v[k]; best = k; }
+        else if (v[k] < d2) { d2 = v[k]; }
+    }
+    *mu = best;
+    *v1 = d1;
+    *v2 = d2;
+}
+
+/* The near-tie rule for the two smallest gaps d1 <= d2 (finite d1): they are
+ * within 1e-12 relative when RN(d2 - d1) <= RN(1e-12 d1).  Eq. 4 gives ties
+ * probability zero; in binary64 a near-tie is where another rounding order
+ * could select another channel, so every such event is counted and the first
+ * one's firing index reported. */
+int rto_near_tie(double d1, double d2)
+{
+    return d2 - d1 <= 1e-12 * d1;
+}
+
 /* ------------------------------------------------------------ one path */
 typedef struct {
     const rto_network* net;
@@ -178,7 +210,7 @@ static void write_sample(job_t* jb, int64_t r, int32_t g, const int32_t* X, int 
 }
 
 static void simulate_path(job_t* jb, int64_t r, int32_t* X, double* T, double* P,
-                          double* a, double* inv, uint32_t* n)
+                          double* a, double* inv, uint32_t* n, double* gap)
 {
     const rto_network* net = jb->net;
     const int N = net->N, M = net->M;
@@ -209,21 +241,19 @@ static void simulate_path(job_t* jb, int64_t r, int32_t* X, double* T, double* P
     uint64_t hash = 0xcbf29ce484222325ull;
 
     for (;;) {
-        /* gaps and argmin: lowest k among the minimal gaps; d2 is the second
-         * order statistic of the gaps */
-        int mu = -1;
-        double d1 = INFINITY, d2 = INFINITY;
+        /* gaps (Eq. 23-24 in internal time), then the selection of Eq. 25:
+         * lowest k among the minimal gaps; d2 is the second order statistic */
         for (int k = 0; k < M; k++) {
-            double d;
             if (a[k] == 0.0) {
-                d = INFINITY;
+                gap[k] = INFINITY;
             } else {
-                d = (P[k] - T[k]) * inv[k];
-                if (d < 0.0) d = 0.0;
+                double d = (P[k] - T[k]) * inv[k];
+                gap[k] = d < 0.0 ? 0.0 : d;
             }
-            if (d < d1) { d2 = d1; d1 = d; mu = k; }
-            else if (d < d2) { d2 = d; }
         }
+        int32_t mu;
+        double d1, d2;
+        rto_argmin2(gap, M, &mu, &d1, &d2);
         double t_new = t + d1;
         /* Eq. 28 with piecewise-constant c_k(t): when the next firing would
          * fall after a rate breakpoint (before t_end), every internal clock
@@ -244,7 +274,7 @@ static void simulate_path(job_t* jb, int64_t r, int32_t* X, double* T, double* P
         }
         if (d1 == INFINITY) { st = RTO_ABSORBED; break; }
         if (t_new > jb->t_end) break;
-        if (d2 - d1 <= 1e-12 * d1) {
+        if (rto_near_tie(d1, d2)) {
             jb->stats.near_ties++;
             if (tie == TIE_NONE) tie = (uint32_t)fired;
         }
@@ -378,12 +408,9 @@ static void simulate_path_lazy(job_t* jb, int64_t r, int32_t* X, double* T, doub
     uint64_t hash = 0xcbf29ce484222325ull;
 
     for (;;) {
-        int mu = -1;
-        double tau1 = INFINITY, tau2 = INFINITY;
-        for (int k = 0; k < M; k++) {
-            if (tau[k] < tau1) { tau2 = tau1; tau1 = tau[k]; mu = k; }
-            else if (tau[k] < tau2) { tau2 = tau[k]; }
-        }
+        int32_t mu;
+        double tau1, tau2;
+        rto_argmin2(tau, M, &mu, &tau1, &tau2);
         double t_new = tau1;
         if (b_next < jb->t_end && t_new > b_next) {
             for (int k = 0; k < M; k++) {
@@ -400,7 +427,7 @@ static void simulate_path_lazy(job_t* jb, int64_t r, int32_t* X, double* T, doub
         if (tau1 == INFINITY) { st = RTO_ABSORBED; break; }
         if (t_new > jb->t_end) break;
         double d1 = t_new - t, d2 = tau2 - t;
-        if (d2 - d1 <= 1e-12 * d1) {
+        if (rto_near_tie(d1, d2)) {
             jb->stats.near_ties++;
             if (tie == TIE_NONE) tie = (uint32_t)fired;
         }
@@ -672,7 +699,7 @@ static void* run_job(void* arg)
         if (jb->method == 1) simulate_path_direct(jb, r, X, a, n);
         else if (jb->method == 3) simulate_path_direct_tree(jb, r, X, a, n);
         else if (jb->method == 2) simulate_path_lazy(jb, r, X, T, P, a, inv, n, s_up, tau);
-        else simulate_path(jb, r, X, T, P, a, inv, n);
+        else simulate_path(jb, r, X, T, P, a, inv, n, tau);
     }
     free(X); free(T); free(P); free(a); free(inv); free(n); free(s_up); free(tau);
     return NULL;

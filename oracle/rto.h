@@ -48,6 +48,13 @@ double rto_neglog_u53(uint64_t m);
 /* Philox4x32-10 block function. */
 void rto_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]);
 
+/* The selection step of Eq. 25 over v[0..M): *mu = the lowest k among the
+ * smallest values (-1 when none is finite), *v1 = that value, *v2 = the
+ * second smallest value counted with multiplicity (+inf if none). */
+void rto_argmin2(const double* v, int32_t M, int32_t* mu, double* v1, double* v2);
+/* The near-tie rule: 1 when RN(d2 - d1) <= RN(1e-12 d1), else 0. */
+int rto_near_tie(double d1, double d2);
+
 /* Simulate R trajectories with ids traj_offset .. traj_offset+R-1.
  * x0: [N] when x0_per_traj == 0, else [R][N].
  * samples: [R][G][N] int32 (may be NULL when G == 0).

@@ -33,8 +33,8 @@ MUTANTS = {
                              "changed species */\n        for (int k = 0; k < M; k++) {\n"
                              "            a[k] = propensity_c(net, X, k, crate[(k + 1) % M]);"),
     "time_step_halved": ("double t_new = t + d1;", "double t_new = t + 0.5 * d1;"),
-    "argmax_instead_of_argmin": ("if (d < d1) { d2 = d1; d1 = d; mu = k; }",
-                                 "if (d1 == INFINITY || d > d1) { d2 = d1; d1 = d; mu = k; }"),
+    "argmax_instead_of_argmin": ("if (v[k] < d1) { d2 = d1; d1 = v[k]; best = k; }",
+                                 "if (d1 == INFINITY || v[k] > d1) { d2 = d1; d1 = v[k]; best = k; }"),
     "jump_sign_flipped": ("T[mu] = P[mu];\n        t = t_new;\n"
                           "        for (int e = jb->nu_ptr[mu]; e < jb->nu_ptr[mu + 1]; e++)\n"
                           "            X[jb->nu_species[e]] += jb->nu_delta[e];",
@@ -125,10 +125,21 @@ TREE_DM_MUTANTS = {
 }
 
 
+# mistakes in the selection step (Eq. 25) and the near-tie rule
+ARGMIN_MUTANTS = {
+    "near_tie_threshold_on_d2": ("return d2 - d1 <= 1e-12 * d1;", "return d2 - d1 <= 1e-12 * d2;"),
+    "near_tie_strict": ("return d2 - d1 <= 1e-12 * d1;", "return d2 - d1 < 1e-12 * d1;"),
+    "second_min_skips_equal": ("else if (v[k] < d2) { d2 = v[k]; }",
+                               "else if (v[k] < d2 && v[k] != d1) { d2 = v[k]; }"),
+    "tie_goes_to_last_channel": ("if (v[k] < d1) { d2 = d1; d1 = v[k]; best = k; }",
+                                 "if (v[k] <= d1) { d2 = d1; d1 = v[k]; best = k; }"),
+}
+
+
 def _build_mutant(tmp, name):
     old, new = (MUTANTS.get(name) or DIRECT_MUTANTS.get(name) or SCHEDULE_MUTANTS.get(name)
                 or LAZY_MUTANTS.get(name) or LAZY_SCHEDULE_MUTANTS.get(name)
-                or TREE_DM_MUTANTS[name])
+                or ARGMIN_MUTANTS.get(name) or TREE_DM_MUTANTS[name])
     src = open(os.path.join(ORACLE_DIR, "rto.c")).read()
     assert src.count(old) == 1, name
     for f in ("rto.h", "dm.c"):
@@ -441,3 +452,13 @@ def test_tree_dm_pins_catch_planted_mistake(name):
 
 def test_tree_dm_pins_pass_on_the_real_oracle():
     assert _tree_dm_pin_failures(oracle.lib()) == []
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("name", sorted(ARGMIN_MUTANTS))
+def test_selection_pins_catch_planted_mistake(name):
+    from test_oracle_argmin import pin_failures
+    with tempfile.TemporaryDirectory() as tmp:
+        L = _build_mutant(tmp, name)
+        failed = pin_failures(L)
+    assert failed, "mutant %s passed every pin" % name
