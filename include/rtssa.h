@@ -63,9 +63,10 @@ typedef enum {
     RTSSA_E_NOMEM = -4        /* device or host allocation failed */
 } rtssa_status;
 
-/* per-trajectory end states */
+/* per-trajectory end states; NOT_RUN: the call's sample grid failed the
+ * device-side check (see rtssa_simulate) and nothing was simulated */
 enum { RTSSA_TRAJ_OK = 0, RTSSA_TRAJ_ABSORBED = 1, RTSSA_TRAJ_OVERFLOW = 2,
-       RTSSA_TRAJ_MAX_FIRINGS = 3 };
+       RTSSA_TRAJ_MAX_FIRINGS = 3, RTSSA_TRAJ_NOT_RUN = 255 };
 
 /* kernel mappings (work decomposition of one trajectory) */
 enum { RTSSA_MAP_AUTO = 0, RTSSA_MAP_THREAD = 1, RTSSA_MAP_WAVE = 2, RTSSA_MAP_WORKGROUP = 3 };
@@ -84,7 +85,7 @@ typedef struct {
     int32_t mapping;          /* mapping that ran */
     int32_t block;            /* workgroup size that ran */
     int32_t grid;             /* workgroups launched */
-    int32_t reserved;
+    int32_t bad_input;        /* 1: the sample grid failed the device-side check */
 } rtssa_stats;
 
 /* Simulation method.  RANDOM_TIME is the paper's next reaction random time
@@ -141,6 +142,12 @@ typedef struct {
     int32_t block;         /* workgroup size; 0 = the mapping's default */
     int32_t grid;          /* workgroups of the persistent grid; 0 = fill the GPU */
     int32_t method;        /* RTSSA_METHOD_*; 0 = random time */
+    /* device workspace of at least rtssa_workspace_size() bytes, 256-byte
+     * aligned, owned by the caller and not shared with a call in flight;
+     * NULL: the call allocates it stream-ordered and frees it after the
+     * launch */
+    void* workspace;
+    uint64_t workspace_bytes;
 } rtssa_options;
 
 /* Message for the last failure on this thread (never NULL). */
@@ -201,6 +208,18 @@ int rtssa_network_set_schedule(rtssa_network* net, int32_t B, const double* time
                                const double* rates);
 
 /*
+ * Device workspace, in bytes, of one rtssa_simulate call of this network with
+ * R trajectories and these options (opt may be NULL): the run's counters and
+ * work-queue heads, plus, for LAZY, one slice of channel records per resident
+ * wavefront (about 44 bytes per channel each).  For LAZY and DIRECT_TREE it
+ * also builds the network's fixed-stride rows if they are not built yet
+ * (synchronous; they are allocated once per network), so that a later call
+ * with a caller workspace allocates nothing.  No stream work otherwise.
+ */
+int rtssa_workspace_size(const rtssa_network* net, int64_t R, const rtssa_options* opt,
+                         size_t* bytes);
+
+/*
  * Simulate trajectories traj_offset .. traj_offset + R - 1 of the network on
  * the GPU (the whole hot path of section 4, Table 2, in one launch).
  *   x0        device int32 [N] (x0_per_traj = 0) or [R][N] (x0_per_traj = 1);
@@ -208,7 +227,10 @@ int rtssa_network_set_schedule(rtssa_network* net, int32_t B, const double* time
  *             device memory; negative counts give meaningless propensities).
  *   t_end     finite, >= 0.
  *   sample_t  device float64 [G], non-decreasing, within [0, t_end]
- *             (read once by the host for validation; may be NULL when G = 0).
+ *             (may be NULL when G = 0); checked on the device by the call's
+ *             first kernel: a grid that fails the check simulates nothing,
+ *             every status[r] becomes RTSSA_TRAJ_NOT_RUN, and with stats the
+ *             call returns RTSSA_E_INVALID (stats->bad_input = 1).
  *   seed      Philox key; net_id is the fourth counter word.
  *   traj_offset + R <= 2^32.
  * Outputs, all device memory, any of them may be NULL to skip it:
@@ -219,9 +241,14 @@ int rtssa_network_set_schedule(rtssa_network* net, int32_t B, const double* time
  *   status    uint8 [R] RTSSA_TRAJ_*; seq_hash uint64 [R]
  *   tie_step  uint32 [R] index of the first near-tie event, RTSSA_TIE_NONE if none
  * stats (host, may be NULL): when given, the call waits for the stream and
- * fills it; otherwise the call returns without waiting.
- * opt may be NULL (defaults).  Device scratch (a few hundred bytes of
- * counters) is allocated stream-ordered by this call.
+ * fills it; otherwise the call only enqueues work on the stream and returns
+ * without waiting.
+ * opt may be NULL (defaults).  With opt->workspace the call allocates
+ * nothing and synchronises nothing unless stats is given, so it can be
+ * captured into a caller's hipGraph (for LAZY and DIRECT_TREE the network's
+ * rows must have been built by rtssa_workspace_size or an earlier run, else
+ * RTSSA_E_INVALID); without it a workspace of rtssa_workspace_size() bytes
+ * is allocated stream-ordered and freed after the launch.
  */
 int rtssa_simulate(const rtssa_network* net, const int32_t* x0, int32_t x0_per_traj,
                    double t_end, const double* sample_t, int32_t G,
@@ -232,6 +259,9 @@ int rtssa_simulate(const rtssa_network* net, const int32_t* x0, int32_t x0_per_t
                    uint8_t* status, uint64_t* seq_hash, uint32_t* tie_step,
                    const rtssa_options* opt, rtssa_stream_t stream, rtssa_stats* stats);
 
+/* Device workspace of rtssa_score_grad for R trajectories of M channels. */
+int rtssa_score_grad_workspace_size(int64_t R, int32_t M, size_t* bytes);
+
 /*
  * Score-function gradient of E[f(X_T)] with respect to log c_k.  For mass
  * action a_k = c_k h_k (Eq. 1), so the derivative of the path log-likelihood
@@ -241,10 +271,13 @@ int rtssa_simulate(const rtssa_network* net, const int32_t* x0, int32_t x0_per_t
  *   f [R], n [R][M], T [R][M]: device inputs.
  *   grad [M], se [M]: device outputs (se = standard error of the mean of the
  *   per-path terms; se may be NULL).  R >= 1, M >= 1.
+ *   workspace: device memory of rtssa_score_grad_workspace_size() bytes
+ *   (8-byte aligned), or NULL to allocate it stream-ordered.
+ * Deterministic: a fixed partition into blocks and a fixed reduction tree.
  */
 int rtssa_score_grad(const double* f, const uint32_t* n, const double* T, int64_t R,
                      int32_t M, int32_t baseline, double* grad, double* se,
-                     rtssa_stream_t stream);
+                     void* workspace, uint64_t workspace_bytes, rtssa_stream_t stream);
 
 /* ---------------------------------------------------------------------
  * Batches: many independent networks in one launch.
@@ -330,6 +363,21 @@ int rtssa_debug_neglog(const uint64_t* m, double* out, uint8_t* slow, int64_t co
 double rtssa_debug_neglog_host(uint64_t m, int32_t force_accurate, int32_t* slow);
 /* The fast phase's double-double approximation yh + yl of -ln u (m < 2^53 - 1). */
 void rtssa_debug_neglog_fast_host(uint64_t m, double* yh, double* yl);
+/* The selection step (Eq. 25) and the near-tie rule of one mapping, run by
+ * the same device functions as the simulation kernels on given values:
+ * v device float64 [count][M] (no NaN; +inf allowed); per row r:
+ * mu[r] = the lowest k among the smallest values, v1[r] that value,
+ * v2[r] the second smallest counted with multiplicity (+inf if none),
+ * near[r] = 1 when RN(v2 - v1) <= RN(1e-12 v1).  mu is meaningful only when
+ * v1 is finite.  mapping RTSSA_MAP_THREAD: one lane per row, channels in
+ * order; RTSSA_MAP_WAVE: groups of lanes = 2..64 lanes of a wavefront, lane l
+ * holding channels l + s lanes, reduced by lane exchanges; RTSSA_MAP_WORKGROUP:
+ * one workgroup of lanes = 64..1024 threads per row, wavefronts merged through
+ * LDS.  Outputs are device memory: mu int32 [count], v1 and v2 float64
+ * [count], near uint8 [count]. */
+int rtssa_debug_select(const double* v, int32_t M, int64_t count, int32_t mapping,
+                       int32_t lanes, int32_t* mu, double* v1, double* v2, uint8_t* near,
+                       rtssa_stream_t stream);
 /* out[4i..4i+3] = Philox4x32-10(ctr[4i..4i+3], key) */
 int rtssa_debug_philox(const uint32_t* ctr, uint32_t key0, uint32_t key1, uint32_t* out,
                        int64_t count, rtssa_stream_t stream);

@@ -19,19 +19,19 @@ i32, i64, u32, u64, f64 = C.c_int32, C.c_int64, C.c_uint32, C.c_uint64, C.c_doub
 class Stats(C.Structure):
     _fields_ = [("firings", u64), ("near_ties", u64), ("clamps", u64), ("slow_logs", u64),
                 ("status_count", u64 * 4), ("kernel_ms", f64), ("mapping", i32),
-                ("block", i32), ("grid", i32), ("reserved", i32)]
+                ("block", i32), ("grid", i32), ("bad_input", i32)]
 
     def as_dict(self):
         return dict(firings=int(self.firings), near_ties=int(self.near_ties),
                     clamps=int(self.clamps), slow_logs=int(self.slow_logs),
                     status_count=[int(x) for x in self.status_count],
                     kernel_ms=float(self.kernel_ms), mapping=int(self.mapping),
-                    block=int(self.block), grid=int(self.grid))
+                    block=int(self.block), grid=int(self.grid), bad_input=int(self.bad_input))
 
 
 class Options(C.Structure):
     _fields_ = [("max_firings", u64), ("mapping", i32), ("block", i32), ("grid", i32),
-                ("method", i32)]
+                ("method", i32), ("workspace", vp), ("workspace_bytes", u64)]
 
 
 class BatchItem(C.Structure):
@@ -53,7 +53,9 @@ SIGNATURES = {
     "rtssa_simulate": (C.c_int, [vp, vp, i32, f64, vp, i32, u64, u32, u64, i64, vp, i64, i64,
                                  i64, vp, vp, vp, vp, vp, vp, vp, C.POINTER(Options), vp,
                                  C.POINTER(Stats)]),
-    "rtssa_score_grad": (C.c_int, [vp, vp, vp, i64, i32, i32, vp, vp, vp]),
+    "rtssa_workspace_size": (C.c_int, [vp, i64, C.POINTER(Options), C.POINTER(C.c_size_t)]),
+    "rtssa_score_grad_workspace_size": (C.c_int, [i64, i32, C.POINTER(C.c_size_t)]),
+    "rtssa_score_grad": (C.c_int, [vp, vp, vp, i64, i32, i32, vp, vp, vp, u64, vp]),
     "rtssa_batch_create": (C.c_int, [C.POINTER(BatchItem), i32, C.POINTER(Options), C.c_char_p,
                                      C.POINTER(vp)]),
     "rtssa_batch_run": (C.c_int, [vp, u64, i32, vp, C.POINTER(Stats)]),
@@ -64,6 +66,7 @@ SIGNATURES = {
     "rtssa_debug_neglog_host": (f64, [u64, i32, C.POINTER(i32)]),
     "rtssa_debug_neglog_fast_host": (None, [u64, C.POINTER(f64), C.POINTER(f64)]),
     "rtssa_debug_philox": (C.c_int, [vp, u32, u32, vp, i64, vp]),
+    "rtssa_debug_select": (C.c_int, [vp, i32, i64, i32, i32, vp, vp, vp, vp, vp]),
     "rtssa_debug_philox_host": (None, [vp, u32, u32, vp]),
 }
 

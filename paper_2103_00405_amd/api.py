@@ -107,7 +107,7 @@ def simulate(net: Network, x0, t_end: float, sample_t, R: int, seed: int = 1, ne
              block: int = 0, grid: int = 0, want=("samples", "n", "T", "x_final", "t_last",
                                                   "status", "tie_step"),
              with_hash: bool = False, stats: bool = True, out: Optional[dict] = None,
-             method: int = METHOD_RANDOM_TIME):
+             method: int = METHOD_RANDOM_TIME, workspace: Optional[torch.Tensor] = None):
     """Run R trajectories on the GPU; returns a dict of device tensors (+ 'stats').
 
     x0 is [N] (shared) or [R, N] (per trajectory), host or device.  sample_t is
@@ -118,7 +118,10 @@ def simulate(net: Network, x0, t_end: float, sample_t, R: int, seed: int = 1, ne
     ``want``); METHOD_LAZY runs the lazy form for large networks (one
     wavefront per trajectory, dependency-graph updates, a minimum tree in
     LDS); METHOD_DIRECT_TREE the direct method on a sum tree in the same
-    mapping (no T or tie_step either)."""
+    mapping (no T or tie_step either).  ``workspace`` (uint8 device tensor,
+    256-byte aligned) may supply the call's workspace; by default one of
+    ``rtssa_workspace_size`` bytes is taken from torch's allocator.  With
+    stats=False the call only enqueues work on the current stream."""
     if method in (METHOD_DIRECT, METHOD_DIRECT_TREE):
         want = tuple(k for k in want if k not in ("T", "tie_step"))
     dev = net.device
@@ -130,8 +133,8 @@ def simulate(net: Network, x0, t_end: float, sample_t, R: int, seed: int = 1, ne
         raise ValueError("initial counts must be >= 0")
     x0 = x0.to(dev).contiguous()
     per_traj = 1 if x0.dim() == 2 else 0
-    if per_traj and tuple(x0.shape) != (R, N):
-        raise ValueError("x0 must be [N] or [R, N]")
+    if (per_traj and tuple(x0.shape) != (R, N)) or (not per_traj and tuple(x0.shape) != (N,)):
+        raise ValueError("x0 must be [N] or [R, N] with N = %d, got %s" % (N, tuple(x0.shape)))
     s = torch.as_tensor(np.asarray(sample_t, dtype=np.float64) if not torch.is_tensor(sample_t)
                         else sample_t, dtype=torch.float64).to(dev).contiguous()
     G = int(s.numel())
@@ -148,6 +151,16 @@ def simulate(net: Network, x0, t_end: float, sample_t, R: int, seed: int = 1, ne
     smp = o.get("samples")
     st_r, st_g, st_n = (smp.stride() if smp is not None else (0, 0, 0))
     opt = Options(int(max_firings), int(mapping), int(block), int(grid), int(method))
+    # the call's device workspace comes from torch's allocator (stream-ordered
+    # reuse, no allocation inside the library)
+    nbytes = C.c_size_t()
+    with torch.cuda.device(dev):
+        check(lib().rtssa_workspace_size(net.handle, R, C.byref(opt), C.byref(nbytes)))
+    ws = workspace
+    if ws is None or ws.numel() < nbytes.value:
+        ws = torch.empty(max(1, nbytes.value), dtype=torch.uint8, device=dev)
+    opt.workspace = ws.data_ptr()
+    opt.workspace_bytes = ws.numel()
     st = Stats()
     with torch.cuda.device(dev):
         check(lib().rtssa_simulate(net.handle, _ptr(x0), per_traj, float(t_end),
@@ -159,6 +172,8 @@ def simulate(net: Network, x0, t_end: float, sample_t, R: int, seed: int = 1, ne
                                    C.byref(opt), _stream(dev), C.byref(st) if stats else None))
     if stats:
         o["stats"] = st.as_dict()
+    # ws returns to torch's pool here: its reuse is ordered after this call's
+    # work on the same stream
     return o
 
 
@@ -171,9 +186,12 @@ def score_grad(f: torch.Tensor, n: torch.Tensor, T: torch.Tensor, baseline: bool
     T = T.to(torch.float64).contiguous()
     grad = torch.empty(M, dtype=torch.float64, device=dev)
     se = torch.empty(M, dtype=torch.float64, device=dev)
+    nbytes = C.c_size_t()
+    check(lib().rtssa_score_grad_workspace_size(R, M, C.byref(nbytes)))
+    ws = torch.empty(max(8, nbytes.value), dtype=torch.uint8, device=dev)
     with torch.cuda.device(dev):
         check(lib().rtssa_score_grad(_ptr(f), _ptr(n), _ptr(T), R, M, 1 if baseline else 0,
-                                     _ptr(grad), _ptr(se), _stream(dev)))
+                                     _ptr(grad), _ptr(se), _ptr(ws), ws.numel(), _stream(dev)))
     return grad, se
 
 
@@ -186,6 +204,12 @@ class _Expectation(torch.autograd.Function):
         net.set_rates(c)
         o = simulate(net, x0, t_end, [t_end], R, seed=seed, want=("x_final", "n", "T", "status"),
                      stats=False)
+        # a path stopped by an overflow or the firing cap has neither X(t_end)
+        # nor T_k(t_end): E[f] and the score n_k - T_k would be biased
+        bad = int((o["status"] > TRAJ_ABSORBED).sum())
+        if bad:
+            raise RuntimeError("%d of %d trajectories stopped before t_end (overflow or firing "
+                               "cap); the expectation and its gradient are undefined" % (bad, R))
         fx = f(o["x_final"]).to(torch.float64)
         ctx.save_for_backward(fx, o["n"], o["T"])
         ctx.baseline = baseline
@@ -229,6 +253,9 @@ class Batch:
             net = j["net"]
             R = int(j["R"])
             x0 = torch.as_tensor(np.asarray(j["x0"]), dtype=torch.int32).to(dev).contiguous()
+            if tuple(x0.shape) not in ((net.N,), (R, net.N)):
+                raise ValueError("job %d: x0 must be [N] or [R, N] with N = %d, got %s"
+                                 % (i, net.N, tuple(x0.shape)))
             s = torch.as_tensor(np.asarray(j["sample_t"], dtype=np.float64),
                                 dtype=torch.float64).to(dev).contiguous()
             G = int(s.numel())

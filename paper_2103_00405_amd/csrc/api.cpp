@@ -124,10 +124,10 @@ rt_item_dev rt_make_item(const rtssa_network* net, const int32_t* x0, int32_t x0
     return it;
 }
 
-// Validates the sample grid (read once from the device) and the run sizes.
+// Host-side checks of a run's sizes and pointers; the sample grid's values
+// stay on the device and are checked there by the setup kernel.
 int rt_check_run(const rtssa_network* net, const int32_t* x0, int32_t x0_per_traj, double t_end,
-                 const double* sample_t, int32_t G, uint64_t traj_offset, int64_t R,
-                 hipStream_t stream)
+                 const double* sample_t, int32_t G, uint64_t traj_offset, int64_t R)
 {
     if (!net) return rt_fail(RTSSA_E_INVALID, "net is NULL");
     if (R < 0 || G < 0) return rt_fail(RTSSA_E_INVALID, "R and G must be >= 0");
@@ -137,18 +137,22 @@ int rt_check_run(const rtssa_network* net, const int32_t* x0, int32_t x0_per_tra
     if (R > 0 && !x0 && net->N > 0) return rt_fail(RTSSA_E_INVALID, "x0 is NULL");
     if (G > 0 && !sample_t) return rt_fail(RTSSA_E_INVALID, "sample_t is NULL with G > 0");
     if (x0_per_traj != 0 && x0_per_traj != 1) return rt_fail(RTSSA_E_INVALID, "x0_per_traj must be 0 or 1");
-    if (G > 0 && R > 0) {
-        std::vector<double> s(G);
-        int rc = check_hip(hipMemcpyAsync(s.data(), sample_t, sizeof(double) * G,
-                                          hipMemcpyDeviceToHost, stream), "reading sample_t");
-        if (!rc) rc = check_hip(hipStreamSynchronize(stream), "reading sample_t");
-        if (rc) return rc;
-        for (int g = 0; g < G; ++g) {
-            if (!(s[g] >= 0.0 && s[g] <= t_end))
-                return rt_fail(RTSSA_E_INVALID, "sample_t values must lie in [0, t_end]");
-            if (g > 0 && s[g] < s[g - 1])
-                return rt_fail(RTSSA_E_INVALID, "sample_t must be non-decreasing");
-        }
+    return RTSSA_OK;
+}
+
+// Reads a sample grid from the device and checks it (synchronous).
+int rt_check_grid_host(const double* sample_t, int32_t G, double t_end)
+{
+    if (G <= 0) return RTSSA_OK;
+    std::vector<double> s(G);
+    int rc = check_hip(hipMemcpy(s.data(), sample_t, sizeof(double) * G, hipMemcpyDeviceToHost),
+                       "reading sample_t");
+    if (rc) return rc;
+    for (int g = 0; g < G; ++g) {
+        if (!(s[g] >= 0.0 && s[g] <= t_end))
+            return rt_fail(RTSSA_E_INVALID, "sample_t values must lie in [0, t_end]");
+        if (g > 0 && s[g] < s[g - 1])
+            return rt_fail(RTSSA_E_INVALID, "sample_t must be non-decreasing");
     }
     return RTSSA_OK;
 }
@@ -162,34 +166,15 @@ void rt_fill_stats(rtssa_stats* stats, const rt_ws& h)
     for (int q = 0; q < 4; ++q) stats->status_count[q] += h.status_count[q];
 }
 
-struct rt_run_scratch {
-    rt_ws ws;
-    rt_item_dev item;
-    int64_t unit_start[2];
-    unsigned long long item_next[2];
-};
 
-extern "C" int rtssa_simulate(const rtssa_network* net, const int32_t* x0, int32_t x0_per_traj,
-                              double t_end, const double* sample_t, int32_t G, uint64_t seed,
-                              uint32_t net_id, uint64_t traj_offset, int64_t R, int32_t* samples,
-                              int64_t s_stride_r, int64_t s_stride_g, int64_t s_stride_n,
-                              uint32_t* n_out, double* T_out, int32_t* x_final, double* t_last,
-                              uint8_t* status, uint64_t* seq_hash, uint32_t* tie_step,
-                              const rtssa_options* opt, rtssa_stream_t stream_, rtssa_stats* stats)
+int rt_check_method(const rtssa_network* net, const rtssa_options& o, bool want_T,
+                           bool want_tie)
 {
-    hipStream_t stream = (hipStream_t)stream_;
-    rtssa_options o{};
-    if (opt) o = *opt;
-    uint64_t maxf = o.max_firings ? o.max_firings : 10000000ull;
-    if (maxf > 0xFFFFFFFFull) return rt_fail(RTSSA_E_INVALID, "max_firings must be < 2^32");
-    if (stats) memset(stats, 0, sizeof(*stats));
-    int rc = rt_check_run(net, x0, x0_per_traj, t_end, sample_t, G, traj_offset, R, stream);
-    if (rc) return rc;
     if (o.method != RTSSA_METHOD_RANDOM_TIME && o.method != RTSSA_METHOD_DIRECT &&
         o.method != RTSSA_METHOD_LAZY && o.method != RTSSA_METHOD_DIRECT_TREE)
         return rt_fail(RTSSA_E_INVALID, "unknown method");
     const bool wave_tree = o.method == RTSSA_METHOD_LAZY || o.method == RTSSA_METHOD_DIRECT_TREE;
-    if (o.method == RTSSA_METHOD_DIRECT_TREE && (T_out || tie_step))
+    if (o.method == RTSSA_METHOD_DIRECT_TREE && (want_T || want_tie))
         return rt_fail(RTSSA_E_INVALID, "the direct method has no internal times or near-ties: "
                                         "T_out and tie_step must be NULL");
     if (wave_tree) {
@@ -201,15 +186,11 @@ extern "C" int rtssa_simulate(const rtssa_network* net, const int32_t* x0, int32
             return rt_fail(RTSSA_E_INVALID, "the tree methods' block is 64 lanes");
         if (net->max_nu > 64)
             return rt_fail(RTSSA_E_UNSUPPORTED, "a reaction changes more than 64 species");
-        if (R > 0) {
-            rc = rt_lazy_prepare(const_cast<rtssa_network*>(net));
-            if (rc) return rc;
-        }
     }
     if (o.method == RTSSA_METHOD_DIRECT) {
         if (net->dev.sched_B > 0)
             return rt_fail(RTSSA_E_UNSUPPORTED, "rate schedules run with the random-time method");
-        if (T_out || tie_step)
+        if (want_T || want_tie)
             return rt_fail(RTSSA_E_INVALID, "the direct method has no internal times or near-ties: "
                                             "T_out and tie_step must be NULL");
         if (!rt_thread_supported(net->M, net->N) ||
@@ -218,16 +199,85 @@ extern "C" int rtssa_simulate(const rtssa_network* net, const int32_t* x0, int32
                                                 "thread mapping (M, N <= 8); "
                                                 "RTSSA_METHOD_DIRECT_TREE runs larger networks");
     }
-    if (R == 0) return RTSSA_OK;
-    int mapping = o.method == RTSSA_METHOD_DIRECT
-                      ? RTSSA_MAP_THREAD
-                      : (wave_tree
-                             ? RTSSA_MAP_WAVE
-                             : (o.mapping == RTSSA_MAP_AUTO ? rt_auto_mapping(net) : o.mapping));
+    return RTSSA_OK;
+}
 
-    rt_run_scratch* sc = nullptr;
-    rc = check_hip(hipMallocAsync((void**)&sc, sizeof(rt_run_scratch), stream), "scratch allocation");
+// Workspace of one run: the counters, descriptor and queue heads, then (LAZY)
+// the channel records of the lazy grid that the launch will use.  cap > 0
+// bounds the workspace: the lazy grid then keeps only as many resident
+// wavefronts as their channel records fit in cap (at least one).
+int rt_run_workspace(const rtssa_network* net, int64_t R, const rtssa_options& o, size_t cap,
+                     size_t* bytes, int* lazy_grid)
+{
+    const size_t base = rt_align256(sizeof(rt_run_scratch));
+    size_t b = base;
+    *lazy_grid = 0;
+    if (o.method == RTSSA_METHOD_LAZY && R > 0) {
+        int req = o.grid;
+        if (cap > 0) {
+            const size_t per_wave = rt_lazy_workspace_bytes(1, net->M);
+            if (cap < base + rt_align256(per_wave))
+                return rt_fail(RTSSA_E_UNSUPPORTED,
+                               "the lazy form needs " + std::to_string(base + rt_align256(per_wave)) +
+                                   " bytes of workspace for one wavefront; the maximum is " +
+                                   std::to_string(cap));
+            const int fit = (int)std::min<size_t>((cap - base - 255) / per_wave, 1 << 30);
+            req = req > 0 ? std::min(req, fit) : fit;
+        }
+        int g = 0;
+        const int rc = rt_lazy_grid(net->N, net->M, req, R, net->dev.sched_B > 0, &g);
+        if (rc) return rc;
+        if (cap > 0 && o.grid <= 0) {
+            // the device's own resident count when it is below the cap
+            int full = 0;
+            const int rc2 = rt_lazy_grid(net->N, net->M, 0, R, net->dev.sched_B > 0, &full);
+            if (rc2) return rc2;
+            g = std::min(g, full);
+        }
+        *lazy_grid = g;
+        b += rt_align256(rt_lazy_workspace_bytes(g, net->M));
+    }
+    *bytes = b;
+    return RTSSA_OK;
+}
+
+extern "C" int rtssa_workspace_size(const rtssa_network* net, int64_t R, const rtssa_options* opt,
+                                    size_t* bytes)
+{
+    if (!net || !bytes) return rt_fail(RTSSA_E_INVALID, "NULL argument");
+    if (R < 0) return rt_fail(RTSSA_E_INVALID, "R must be >= 0");
+    rtssa_options o{};
+    if (opt) o = *opt;
+    int rc = rt_check_method(net, o, false, false);
     if (rc) return rc;
+    if (o.method == RTSSA_METHOD_LAZY || o.method == RTSSA_METHOD_DIRECT_TREE) {
+        rc = rt_lazy_prepare(const_cast<rtssa_network*>(net));
+        if (rc) return rc;
+    }
+    int lazy_grid = 0;
+    return rt_run_workspace(net, R, o, 0, bytes, &lazy_grid);
+}
+
+// One run on a workspace the caller provides (ws, at least the bytes that
+// rt_run_workspace reports for lazy_grid): validates, enqueues the setup and
+// simulation kernels on the stream; with stats, waits and fills them.
+int rt_simulate_on(const rtssa_network* net, const int32_t* x0, int32_t x0_per_traj,
+                   double t_end, const double* sample_t, int32_t G, uint64_t seed,
+                   uint32_t net_id, uint64_t traj_offset, int64_t R, int32_t* samples,
+                   int64_t s_stride_r, int64_t s_stride_g, int64_t s_stride_n, uint32_t* n_out,
+                   double* T_out, int32_t* x_final, double* t_last, uint8_t* status,
+                   uint64_t* seq_hash, uint32_t* tie_step, const rtssa_options& o, void* wsp,
+                   int lazy_grid, hipStream_t stream, rtssa_stats* stats)
+{
+    const uint64_t maxf = o.max_firings ? o.max_firings : 10000000ull;
+    const bool wave_tree = o.method == RTSSA_METHOD_LAZY || o.method == RTSSA_METHOD_DIRECT_TREE;
+    const int mapping = o.method == RTSSA_METHOD_DIRECT
+                            ? RTSSA_MAP_THREAD
+                            : (wave_tree ? RTSSA_MAP_WAVE
+                                         : (o.mapping == RTSSA_MAP_AUTO ? rt_auto_mapping(net)
+                                                                        : o.mapping));
+    rt_run_scratch* sc = (rt_run_scratch*)wsp;
+    void* lazy_ws = (char*)wsp + rt_align256(sizeof(rt_run_scratch));
     const rt_item_dev item = rt_make_item(net, x0, x0_per_traj, t_end, sample_t, G, net_id,
                                           traj_offset, R, samples, s_stride_r, s_stride_g,
                                           s_stride_n, n_out, T_out, x_final, t_last, status,
@@ -249,13 +299,13 @@ extern "C" int rtssa_simulate(const rtssa_network* net, const int32_t* x0, int32
         hipEventCreate(&ev0);
         hipEventCreate(&ev1);
     }
-    rc = rt_launch_setup(&sc->ws, sc->item_next, 2, (uint32_t)seed, (uint32_t)(seed >> 32),
-                         nullptr, &item, &sc->item, sc->unit_start, stream);
+    int rc = rt_launch_setup(&sc->ws, sc->item_next, 2, (uint32_t)seed, (uint32_t)(seed >> 32),
+                             nullptr, &item, &sc->item, sc->unit_start, stream);
     if (!rc && stats) hipEventRecord(ev0, stream);
     int grid_used = 0, block_used = 0;
     if (!rc && o.method == RTSSA_METHOD_LAZY) {
         block_used = 64;
-        rc = rt_launch_lazy(C, net->N, net->M, o.grid, R, stream, &grid_used);
+        rc = rt_launch_lazy(C, net->N, net->M, lazy_grid, R, stream, &grid_used, lazy_ws);
     } else if (!rc && o.method == RTSSA_METHOD_DIRECT_TREE) {
         block_used = 64;
         rc = rt_launch_dmtree(C, net->N, net->M, o.grid, R, stream, &grid_used);
@@ -277,22 +327,96 @@ extern "C" int rtssa_simulate(const rtssa_network* net, const int32_t* x0, int32
             stats->mapping = mapping;
             stats->block = block_used;
             stats->grid = grid_used;
+            stats->bad_input = h.bad_input ? 1 : 0;
+            if (h.bad_input)
+                rc = rt_fail(RTSSA_E_INVALID, "sample_t must be non-decreasing and lie in "
+                                              "[0, t_end] (checked on the device; nothing ran)");
         }
     }
     if (ev0) hipEventDestroy(ev0);
     if (ev1) hipEventDestroy(ev1);
-    hipFreeAsync(sc, stream);
     return rc;
+}
+
+// Argument checks shared by the entry points; *ready: the run has work.
+int rt_simulate_checks(const rtssa_network* net, const int32_t* x0, int32_t x0_per_traj,
+                       double t_end, const double* sample_t, int32_t G, uint64_t traj_offset,
+                       int64_t R, const double* T_out, const uint32_t* tie_step,
+                       const rtssa_options& o, bool may_build_rows)
+{
+    uint64_t maxf = o.max_firings ? o.max_firings : 10000000ull;
+    if (maxf > 0xFFFFFFFFull) return rt_fail(RTSSA_E_INVALID, "max_firings must be < 2^32");
+    int rc = rt_check_run(net, x0, x0_per_traj, t_end, sample_t, G, traj_offset, R);
+    if (rc) return rc;
+    rc = rt_check_method(net, o, T_out != nullptr, tie_step != nullptr);
+    if (rc) return rc;
+    const bool wave_tree = o.method == RTSSA_METHOD_LAZY || o.method == RTSSA_METHOD_DIRECT_TREE;
+    if (wave_tree && R > 0) {
+        if (!may_build_rows && !net->lazy_block)
+            return rt_fail(RTSSA_E_INVALID, "the tree methods need the network's rows built "
+                                            "first (rtssa_workspace_size)");
+        rc = rt_lazy_prepare(const_cast<rtssa_network*>(net));
+        if (rc) return rc;
+    }
+    return RTSSA_OK;
+}
+
+extern "C" int rtssa_simulate(const rtssa_network* net, const int32_t* x0, int32_t x0_per_traj,
+                              double t_end, const double* sample_t, int32_t G, uint64_t seed,
+                              uint32_t net_id, uint64_t traj_offset, int64_t R, int32_t* samples,
+                              int64_t s_stride_r, int64_t s_stride_g, int64_t s_stride_n,
+                              uint32_t* n_out, double* T_out, int32_t* x_final, double* t_last,
+                              uint8_t* status, uint64_t* seq_hash, uint32_t* tie_step,
+                              const rtssa_options* opt, rtssa_stream_t stream_, rtssa_stats* stats)
+{
+    hipStream_t stream = (hipStream_t)stream_;
+    rtssa_options o{};
+    if (opt) o = *opt;
+    if (stats) memset(stats, 0, sizeof(*stats));
+    if (o.workspace && ((uintptr_t)o.workspace & 255u))
+        return rt_fail(RTSSA_E_INVALID, "the workspace must be 256-byte aligned");
+    int rc = rt_simulate_checks(net, x0, x0_per_traj, t_end, sample_t, G, traj_offset, R, T_out,
+                                tie_step, o, o.workspace == nullptr);
+    if (rc || R == 0) return rc;
+    size_t need = 0;
+    int lazy_grid = 0;
+    rc = rt_run_workspace(net, R, o, 0, &need, &lazy_grid);
+    if (rc) return rc;
+    void* wsp = o.workspace;
+    if (wsp) {
+        if (o.workspace_bytes < need)
+            return rt_fail(RTSSA_E_INVALID, "workspace too small: " + std::to_string(need) +
+                                                " bytes needed (rtssa_workspace_size)");
+    } else {
+        rc = check_hip(hipMallocAsync(&wsp, need, stream), "workspace allocation");
+        if (rc) return rc;
+    }
+    rc = rt_simulate_on(net, x0, x0_per_traj, t_end, sample_t, G, seed, net_id, traj_offset, R,
+                        samples, s_stride_r, s_stride_g, s_stride_n, n_out, T_out, x_final, t_last,
+                        status, seq_hash, tie_step, o, wsp, lazy_grid, stream, stats);
+    if (!o.workspace) hipFreeAsync(wsp, stream);
+    return rc;
+}
+
+extern "C" int rtssa_score_grad_workspace_size(int64_t R, int32_t M, size_t* bytes)
+{
+    if (!bytes || R < 1 || M < 1) return rt_fail(RTSSA_E_INVALID, "R, M >= 1 and bytes required");
+    *bytes = rt_score_grad_workspace_bytes(R, M);
+    return RTSSA_OK;
 }
 
 extern "C" int rtssa_score_grad(const double* f, const uint32_t* n, const double* T, int64_t R,
                                 int32_t M, int32_t baseline, double* grad, double* se,
-                                rtssa_stream_t stream)
+                                void* workspace, uint64_t workspace_bytes, rtssa_stream_t stream)
 {
     if (!f || !n || !T || !grad) return rt_fail(RTSSA_E_INVALID, "NULL argument");
     if (R < 1 || M < 1) return rt_fail(RTSSA_E_INVALID, "R and M must be >= 1");
     if (baseline != 0 && baseline != 1) return rt_fail(RTSSA_E_INVALID, "baseline must be 0 or 1");
-    return rt_launch_score_grad(f, n, T, R, M, baseline, grad, se, (hipStream_t)stream);
+    if (workspace && (workspace_bytes < rt_score_grad_workspace_bytes(R, M) ||
+                      ((uintptr_t)workspace & 7u)))
+        return rt_fail(RTSSA_E_INVALID, "score workspace too small or misaligned");
+    return rt_launch_score_grad(f, n, T, R, M, baseline, grad, se, workspace,
+                                (hipStream_t)stream);
 }
 
 extern "C" int rtssa_debug_neglog(const uint64_t* m, double* out, uint8_t* slow, int64_t count,
@@ -307,4 +431,15 @@ extern "C" int rtssa_debug_philox(const uint32_t* ctr, uint32_t key0, uint32_t k
 {
     if (count < 0 || (count > 0 && (!ctr || !out))) return rt_fail(RTSSA_E_INVALID, "bad arguments");
     return rt_launch_debug_philox(ctr, key0, key1, out, count, (hipStream_t)stream);
+}
+
+extern "C" int rtssa_debug_select(const double* v, int32_t M, int64_t count, int32_t mapping,
+                                  int32_t lanes, int32_t* mu, double* v1, double* v2,
+                                  uint8_t* near, rtssa_stream_t stream)
+{
+    if (count < 0 || M < 0) return rt_fail(RTSSA_E_INVALID, "count and M must be >= 0");
+    if (count > 0 && (!mu || !v1 || !v2 || !near || (M > 0 && !v)))
+        return rt_fail(RTSSA_E_INVALID, "NULL argument");
+    return rt_launch_debug_select(v, M, count, mapping, lanes, mu, v1, v2, near,
+                                  (hipStream_t)stream);
 }

@@ -147,7 +147,8 @@ static int batch_create(const rtssa_batch_item* items, int32_t count, const rtss
     for (int i = 0; i < count; ++i) {
         const rtssa_batch_item& b = items[i];
         int rc = rt_check_run(b.net, b.x0, b.x0_per_traj, b.t_end, b.sample_t, b.G,
-                              b.traj_offset, b.R, nullptr);
+                              b.traj_offset, b.R);
+        if (!rc && b.R > 0) rc = rt_check_grid_host(b.sample_t, b.G, b.t_end);
         const std::string at = "item " + std::to_string(i) + ": ";
         if (rc) return rt_fail(rc, at + rtssa_last_error());
         if (b.method != RTSSA_METHOD_RANDOM_TIME && b.method != RTSSA_METHOD_LAZY &&

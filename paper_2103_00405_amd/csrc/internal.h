@@ -93,7 +93,8 @@ struct rt_ws {
     unsigned long long status_count[4];
     unsigned long long next_unit;    // trajectory units or items handed out
     uint32_t key0, key1;
-    unsigned long long pad[6];
+    unsigned long long bad_input;    // 1: a single run's sample grid failed its check
+    unsigned long long pad[5];
 };
 
 // A class of items run by one persistent kernel: items[0 .. count); the
@@ -115,6 +116,18 @@ struct rt_class_dev {
     int32_t has_schedule;   // some item's network has a rate schedule
 };
 
+// Device workspace of one single run: counters, its item descriptor and
+// unit range, the per-item trajectory counter; the lazy form's channel
+// records follow at the next 256-byte boundary.
+struct rt_run_scratch {
+    rt_ws ws;
+    rt_item_dev item;
+    int64_t unit_start[2];
+    unsigned long long item_next[2];
+};
+
+inline size_t rt_align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
 // error reporting and mapping choice (api.cpp)
 int rt_fail(int code, const std::string& msg);
 int rt_auto_mapping(const rtssa_network* net);
@@ -128,9 +141,11 @@ rt_item_dev rt_make_item(const rtssa_network* net, const int32_t* x0, int32_t x0
                          int64_t s_stride_g, int64_t s_stride_n, uint32_t* n_out, double* T_out,
                          int32_t* x_final, double* t_last, uint8_t* status, uint64_t* seq_hash,
                          uint32_t* tie_step);
+// host-side checks of one run's arguments (no device access)
 int rt_check_run(const rtssa_network* net, const int32_t* x0, int32_t x0_per_traj, double t_end,
-                 const double* sample_t, int32_t G, uint64_t traj_offset, int64_t R,
-                 hipStream_t stream);
+                 const double* sample_t, int32_t G, uint64_t traj_offset, int64_t R);
+// reads a sample grid from the device and checks it (synchronous; batch creation)
+int rt_check_grid_host(const double* sample_t, int32_t G, double t_end);
 void rt_fill_stats(rtssa_stats* stats, const rt_ws& h);
 int check_hip(hipError_t e, const char* what);
 
@@ -141,11 +156,15 @@ int rt_launch_thread(int M, int N, const rt_class_dev& C, int block, int grid,
 int rt_launch_setup(rt_ws* ws, unsigned long long* extra, int64_t n_extra, uint32_t key0,
                     uint32_t key1, const uint32_t* key_src, const rt_item_dev* item,
                     rt_item_dev* item_dst, int64_t* unit_start, hipStream_t stream);
+size_t rt_score_grad_workspace_bytes(int64_t R, int32_t M);
 int rt_launch_score_grad(const double* f, const uint32_t* n, const double* T, int64_t R,
                          int32_t M, int32_t baseline, double* grad, double* se,
-                         hipStream_t stream);
+                         void* workspace, hipStream_t stream);
 int rt_launch_debug_neglog(const uint64_t* m, double* out, uint8_t* slow, int64_t count,
                            int force, hipStream_t stream);
+int rt_launch_debug_select(const double* v, int32_t M, int64_t count, int32_t mapping,
+                           int32_t lanes, int32_t* mu, double* v1, double* v2, uint8_t* near,
+                           hipStream_t stream);
 int rt_launch_debug_philox(const uint32_t* ctr, uint32_t k0, uint32_t k1, uint32_t* out,
                            int64_t count, hipStream_t stream);
 int rt_thread_supported(int M, int N);
@@ -174,3 +193,21 @@ int rt_launch_dmtree(const rt_class_dev& C, int max_N, int max_M, int grid, int6
 int rt_lazy_prepare(rtssa_network* net);
 int rt_subwave_slots(int M, int L);
 int rt_subwave_lanes(int M);
+
+// single runs (api.cpp), shared by rtssa_simulate and its allocation-free
+// variant
+int rt_check_method(const rtssa_network* net, const rtssa_options& o, bool want_T,
+                    bool want_tie);
+int rt_simulate_checks(const rtssa_network* net, const int32_t* x0, int32_t x0_per_traj,
+                       double t_end, const double* sample_t, int32_t G, uint64_t traj_offset,
+                       int64_t R, const double* T_out, const uint32_t* tie_step,
+                       const rtssa_options& o, bool may_build_rows);
+int rt_run_workspace(const rtssa_network* net, int64_t R, const rtssa_options& o, size_t cap,
+                     size_t* bytes, int* lazy_grid);
+int rt_simulate_on(const rtssa_network* net, const int32_t* x0, int32_t x0_per_traj,
+                   double t_end, const double* sample_t, int32_t G, uint64_t seed,
+                   uint32_t net_id, uint64_t traj_offset, int64_t R, int32_t* samples,
+                   int64_t s_stride_r, int64_t s_stride_g, int64_t s_stride_n, uint32_t* n_out,
+                   double* T_out, int32_t* x_final, double* t_last, uint8_t* status,
+                   uint64_t* seq_hash, uint32_t* tie_step, const rtssa_options& o, void* wsp,
+                   int lazy_grid, hipStream_t stream, rtssa_stats* stats);

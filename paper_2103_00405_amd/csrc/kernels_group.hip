@@ -33,51 +33,12 @@
 
 namespace {
 
-constexpr uint32_t kTieNone = 0xFFFFFFFFu;
-constexpr unsigned long long kFnvOffset = 0xcbf29ce484222325ull;
-constexpr unsigned long long kFnvPrime = 0x100000001b3ull;
-
-__device__ __forceinline__ double u64_to_f64(uint64_t h)
-{
-    return fma((double)(uint32_t)(h >> 32), 0x1p32, (double)(uint32_t)h);
-}
-
-// a_k = RN(c_k RN(h_k(X))) with X in LDS (Eq. 1-2).
-__device__ __forceinline__ double group_propensity(int2 rr, double c, const int32_t* X)
-{
-    const int kind = (int)((uint32_t)rr.x >> 29);
-    const int s0 = rr.x & RT_SPECIES_MASK;
-    uint64_t h;
-    if (kind == RT_H_ZERO) {
-        h = 1;
-    } else if (kind == RT_H_ONE) {
-        h = (uint32_t)X[s0];
-    } else if (kind == RT_H_PAIR) {
-        const uint32_t x = (uint32_t)X[s0];
-        h = ((uint64_t)x * (uint32_t)(x - 1u)) >> 1;
-    } else {
-        h = (uint64_t)(uint32_t)X[s0] * (uint32_t)X[rr.y];
-    }
-    return c * u64_to_f64(h);
-}
-
 struct rt_group_shared {
     rt_min2 wave_min[16];
     unsigned long long next_traj;
     int ok;
     uint32_t log_scratch[16][RT_LOG_SCRATCH];
 };
-
-// Index of the item owning global unit u: unit_start[i] <= u < unit_start[i+1].
-__device__ __forceinline__ int group_find_item(rt_cptr<int64_t> unit_start, int count, int64_t u)
-{
-    int lo = 0, hi = count;
-    while (hi - lo > 1) {
-        const int mid = (lo + hi) >> 1;
-        if (unit_start[mid] <= u) lo = mid; else hi = mid;
-    }
-    return lo;
-}
 
 // Waves per SIMD the register allocation aims at: 16 slots of channel state
 // fit 2, 8 fit 3 (2 with a rate schedule's state), fewer fit 4.
@@ -124,7 +85,7 @@ __global__ __launch_bounds__(L, group_min_waves(S, SCHED)) void rt_group_kernel(
                                          (int)(u_lds >> 32)) << 32) |
                                      (uint32_t)__builtin_amdgcn_readfirstlane((int)u_lds));
         if (u >= total) break;
-        const int item = __builtin_amdgcn_readfirstlane(group_find_item(unit_start, C.count, u));
+        const int item = __builtin_amdgcn_readfirstlane(rt_find_item(unit_start, C.count, u));
         const rt_cptr<rt_item_dev> it = rt_const(C.items) + item;
         const rt_net_dev net = it->net;
         const int N = net.N, M = net.M;
@@ -158,7 +119,7 @@ __global__ __launch_bounds__(L, group_min_waves(S, SCHED)) void rt_group_kernel(
             if (k < M) {
                 const double p0 = rt_exp1_wave(key0, key1, traj, net_id, (uint32_t)k, 0u,
                                                &ws->slow_logs, sc);
-                const double an = group_propensity(react[k], cc[k], X);
+                const double an = rt_propensity_mem(react[k], cc[k], X);
                 const double in = 1.0 / an;
 #pragma unroll
                 for (int s = 0; s < S; ++s) {
@@ -205,7 +166,7 @@ __global__ __launch_bounds__(L, group_min_waves(S, SCHED)) void rt_group_kernel(
                     const int s1 = __builtin_ctz(stale);
                     stale &= stale - 1u;
                     const int k = tid + s1 * L;
-                    const double an = group_propensity(react[k], crate[k], X);
+                    const double an = rt_propensity_mem(react[k], crate[k], X);
                     const double in = 1.0 / an;
 #pragma unroll
                     for (int s = 0; s < S; ++s) {
@@ -222,18 +183,9 @@ __global__ __launch_bounds__(L, group_min_waves(S, SCHED)) void rt_group_kernel(
                 const double d = a[s] == 0.0 ? __builtin_inf() : fmax(raw, 0.0);
                 rt_min2_push(loc, d, s);                   // slot now, channel below
             }
-            loc.k = loc.k == 0x7FFFFFFF ? loc.k : tid + (loc.k << LOG2L);
-            // ---- argmin over the workgroup
-            loc = rt_min2_allreduce<64>(loc);
-            if constexpr (W > 1) {
-                if (lane == 0) sh.wave_min[wave] = loc;
-            }
-            __syncthreads();                               // barrier 1
-            if constexpr (W > 1) {
-                // every lane reads partial (lane mod W): the groups of W lanes
-                // all reduce the same W values
-                loc = rt_min2_allreduce<W>(sh.wave_min[lane & (W - 1)]);
-            }
+            loc = rt_min2_slot_to_channel(loc, tid, LOG2L);
+            // ---- argmin over the workgroup (barrier 1 inside)
+            loc = rt_min2_group_allreduce<L>(loc, sh.wave_min);
             const double d1 = loc.d1, d2 = loc.d2;
             mu = __builtin_amdgcn_readfirstlane(loc.k);
             const double t_new = t + d1;
@@ -258,7 +210,7 @@ __global__ __launch_bounds__(L, group_min_waves(S, SCHED)) void rt_group_kernel(
             }
             if (d1 == __builtin_inf()) { st = RTSSA_TRAJ_ABSORBED; break; }
             if (t_new > t_end) { st = RTSSA_TRAJ_OK; break; }
-            if (d2 - d1 <= 1e-12 * d1) {
+            if (rt_near_tie(d1, d2)) {
                 if (tid == 0) atomicAdd(&ws->near_ties, 1ull);
                 tie = tie == kTieNone ? fired : tie;
             }

@@ -45,9 +45,6 @@
 
 namespace {
 
-constexpr uint32_t kTieNone = 0xFFFFFFFFu;
-constexpr unsigned long long kFnvOffset = 0xcbf29ce484222325ull;
-constexpr unsigned long long kFnvPrime = 0x100000001b3ull;
 constexpr int kFanLog = 3;               // children per node: 2^kFanLog
 constexpr int kFan = 1 << kFanLog;
 constexpr int kMaxLevels = 64 / kFan;    // one lane per sibling in lazy_second
@@ -55,46 +52,6 @@ constexpr int kMaxLevels = 64 / kFan;    // one lane per sibling in lazy_second
 struct rt_lazy_rec {                     // a channel's state in the workspace
     double T, s, P, a;
 };
-
-__device__ __forceinline__ double u64_to_f64(uint64_t h)
-{
-    return fma((double)(uint32_t)(h >> 32), 0x1p32, (double)(uint32_t)h);
-}
-
-// a_k = RN(c_k RN(h_k(X))) with X in LDS (Eq. 1-2).
-__device__ __forceinline__ double lazy_propensity(int2 rr, double c, const int32_t* X)
-{
-    const int kind = (int)((uint32_t)rr.x >> 29);
-    const int s0 = rr.x & RT_SPECIES_MASK;
-    uint64_t h;
-    if (kind == RT_H_ZERO) {
-        h = 1;
-    } else if (kind == RT_H_ONE) {
-        h = (uint32_t)X[s0];
-    } else if (kind == RT_H_PAIR) {
-        const uint32_t x = (uint32_t)X[s0];
-        h = ((uint64_t)x * (uint32_t)(x - 1u)) >> 1;
-    } else {
-        h = (uint64_t)(uint32_t)X[s0] * (uint32_t)X[rr.y];
-    }
-    return c * u64_to_f64(h);
-}
-
-__device__ __forceinline__ void wave_lds_fence()
-{
-    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-}
-
-__device__ __forceinline__ int find_item(rt_cptr<int64_t> unit_start, int count, int64_t u)
-{
-    int lo = 0, hi = count;
-    while (hi - lo > 1) {
-        const int mid = (lo + hi) >> 1;
-        if (unit_start[mid] <= u) lo = mid; else hi = mid;
-    }
-    return lo;
-}
 
 // A refreshed channel's next firing time: +inf when a = 0, else
 // t + max(0, RN(RN(P - T) * RN(1 / a))); *clamped when the raw gap is negative.
@@ -272,7 +229,7 @@ __device__ __forceinline__ rt_lazy_rec lazy_touch(rt_lazy_rec rc, bool fresh, do
         rc.T = fma(rc.a, t - rc.s, rc.T);
     }
     rc.s = t;
-    rc.a = lazy_propensity(rr, c, X);
+    rc.a = rt_propensity_mem(rr, c, X);
     bool cl;
     *leaf = lazy_tau(t, rc.T, rc.P, rc.a, &cl);
     if (cl) atomicAdd(clamps, 1ull);
@@ -308,7 +265,7 @@ __global__ __launch_bounds__(64) void rt_lazy_kernel(rt_class_dev C, rt_lazy_rec
         if (lane == 0) u = atomicAdd(&ws->next_unit, 1ull);
         u = __shfl(u, 0, 64);
         if ((int64_t)u >= total) break;
-        const int item = __builtin_amdgcn_readfirstlane(find_item(unit_start, C.count, (int64_t)u));
+        const int item = __builtin_amdgcn_readfirstlane(rt_find_item(unit_start, C.count, (int64_t)u));
         const rt_cptr<rt_item_dev> it = rt_const(C.items) + item;
         const rt_net_dev net = it->net;
         const int N = net.N, M = net.M;
@@ -374,24 +331,24 @@ __global__ __launch_bounds__(64) void rt_lazy_kernel(rt_class_dev C, rt_lazy_rec
             for (int j = tr.cnt[l] + lane; j < padf(tr.cnt[l]); j += 64)
                 lazy_store(tr, l, j, lazy_min{__builtin_inf(), 0x7FFFFFFF});
         }
-        wave_lds_fence();
+        rt_wave_lds_fence();
         for (int k = lane; k < M; k += 64) {
             const rt_u4 w = rt_philox4x32_10(rt_u4{0u, (uint32_t)k, traj, net_id}, key0, key1);
             wnext[k] = ((unsigned long long)w.w << 32) | w.z;
             const double P = rt_neglog_wave((((uint64_t)w.y << 32) | w.x) >> 11, false,
                                             &ws->slow_logs, log_scratch);
-            const double a = lazy_propensity(react[k], cc[k], X);
+            const double a = rt_propensity_mem(react[k], cc[k], X);
             bool cl;
             leaves[k] = lazy_tau(0.0, 0.0, P, a, &cl);
             recs[k] = rt_lazy_rec{0.0, 0.0, P, a};
             nks[k] = 0u;
         }
-        wave_lds_fence();
+        rt_wave_lds_fence();
 #pragma unroll
         for (int l = 1; l <= kMaxLevels; ++l) {
             if (l > top) break;
             for (int j = lane; j < tr.cnt[l]; j += 64) lazy_store(tr, l, j, lazy_node(tr, l, j));
-            wave_lds_fence();
+            rt_wave_lds_fence();
         }
 
         // the next event: the top level's argmin, kept in registers (every
@@ -431,13 +388,13 @@ __global__ __launch_bounds__(64) void rt_lazy_kernel(rt_class_dev C, rt_lazy_rec
                 for (int k = lane; k < M; k += 64)
                     recs[k] = lazy_touch(recs[k], false, 0.0, t, react[k], cc[k], X, &leaves[k],
                                          &ws->clamps);
-                wave_lds_fence();
+                rt_wave_lds_fence();
 #pragma unroll
                 for (int l = 1; l <= kMaxLevels; ++l) {
                     if (l > top) break;
                     for (int j = lane; j < tr.cnt[l]; j += 64)
                         lazy_store(tr, l, j, lazy_node(tr, l, j));
-                    wave_lds_fence();
+                    rt_wave_lds_fence();
                 }
                 top_e = lazy_top_entry(top_d, top_k, top_cnt, top == 0, lane);
                 root = lazy_wave_argmin(top_e);
@@ -479,7 +436,7 @@ __global__ __launch_bounds__(64) void rt_lazy_kernel(rt_class_dev C, rt_lazy_rec
                 const double d1 = t_new - t;
                 const double d2 =
                     lazy_second((const char*)dyn_lds, level_off, top, mu, top_e, lane) - t;
-                if (d2 - d1 <= 1e-12 * d1) {
+                if (rt_near_tie(d1, d2)) {
                     if (lane == 0) atomicAdd(&ws->near_ties, 1ull);
                     tie = tie == kTieNone ? fired : tie;
                 }
@@ -503,11 +460,11 @@ __global__ __launch_bounds__(64) void rt_lazy_kernel(rt_class_dev C, rt_lazy_rec
             const bool okl = !has_nu || (xv >= 0 && xv <= 0x7FFFFFFF);
             if (__ballot(!okl) != 0ull) { st = RTSSA_TRAJ_OVERFLOW; break; }
             if (has_nu) X[sp] = (int32_t)xv;
-            wave_lds_fence();
+            rt_wave_lds_fence();
             // ---- first round of touched channels, then their ancestors
             if (act) recs[k] = lazy_touch(rc0, lane == 0, E, t_new, rr0, c0, X, &leaves[k],
                                           &ws->clamps);
-            wave_lds_fence();
+            rt_wave_lds_fence();
             // (lanes without a touched channel follow mu's path: they compute
             // and store the same values as lane 0)
 #pragma unroll
@@ -515,7 +472,7 @@ __global__ __launch_bounds__(64) void rt_lazy_kernel(rt_class_dev C, rt_lazy_rec
                 if (l > top) break;
                 const int j = k >> (kFanLog * l);
                 lazy_store(tr, l, j, lazy_node(tr, l, j));
-                wave_lds_fence();
+                rt_wave_lds_fence();
             }
             // ---- more than 63 other dependents: the rest of the CSR list
             // D(mu) from the 64th on, 64 per round (mu itself skipped)
@@ -528,13 +485,13 @@ __global__ __launch_bounds__(64) void rt_lazy_kernel(rt_class_dev C, rt_lazy_rec
                     if (k2 >= 0)
                         recs[k2] = lazy_touch(recs[k2], false, E, t_new, react[k2], cc[k2], X,
                                               &leaves[k2], &ws->clamps);
-                    wave_lds_fence();
+                    rt_wave_lds_fence();
 #pragma unroll
                     for (int l = 1; l <= kMaxLevels; ++l) {
                         if (l > top) break;
                         const int j = (k2 >= 0 ? k2 : mu) >> (kFanLog * l);
                         lazy_store(tr, l, j, lazy_node(tr, l, j));
-                        wave_lds_fence();
+                        rt_wave_lds_fence();
                     }
                 }
             }
@@ -577,7 +534,7 @@ __global__ __launch_bounds__(64) void rt_lazy_kernel(rt_class_dev C, rt_lazy_rec
             atomicAdd(&ws->firings, (unsigned long long)fired);
             atomicAdd(&ws->status_count[st], 1ull);
         }
-        wave_lds_fence();                                  // X and the tree are reused
+        rt_wave_lds_fence();                                  // X and the tree are reused
     }
 }
 
@@ -630,7 +587,7 @@ __global__ __launch_bounds__(64) void rt_dmtree_kernel(rt_class_dev C)
         if (lane == 0) u = atomicAdd(&ws->next_unit, 1ull);
         u = __shfl(u, 0, 64);
         if ((int64_t)u >= total) break;
-        const int item = __builtin_amdgcn_readfirstlane(find_item(unit_start, C.count, (int64_t)u));
+        const int item = __builtin_amdgcn_readfirstlane(rt_find_item(unit_start, C.count, (int64_t)u));
         const rt_cptr<rt_item_dev> it = rt_const(C.items) + item;
         const rt_net_dev net = it->net;
         const int N = net.N, M = net.M;
@@ -676,20 +633,20 @@ __global__ __launch_bounds__(64) void rt_dmtree_kernel(rt_class_dev C)
         // ---- initial state: X, the propensities, every node, zero counts
         const int32_t* x0 = it->x0 + (it->x0_per_traj ? r * N : 0);
         for (int j = lane; j < N; j += 64) X[j] = x0[j];
-        wave_lds_fence();
+        rt_wave_lds_fence();
         for (int k = lane; k < padf(tr.cnt[0]); k += 64)
-            leaves[k] = k < M ? lazy_propensity(react[k], cc[k], X) : 0.0;
+            leaves[k] = k < M ? rt_propensity_mem(react[k], cc[k], X) : 0.0;
 #pragma unroll
         for (int l = 1; l <= kMaxLevels; ++l) {
             if (l > top) break;
             for (int j = tr.cnt[l] + lane; j < padf(tr.cnt[l]); j += 64) tr.d[l][j] = 0.0;
         }
-        wave_lds_fence();
+        rt_wave_lds_fence();
 #pragma unroll
         for (int l = 1; l <= kMaxLevels; ++l) {
             if (l > top) break;
             for (int j = lane; j < tr.cnt[l]; j += 64) tr.d[l][j] = dt_sum_node(tr, l, j);
-            wave_lds_fence();
+            rt_wave_lds_fence();
         }
         if (n_row) {
             for (int k = lane; k < M; k += 64) n_row[k] = 0u;
@@ -765,10 +722,10 @@ __global__ __launch_bounds__(64) void rt_dmtree_kernel(rt_class_dev C)
             const bool okl = !has_nu || (xv >= 0 && xv <= 0x7FFFFFFF);
             if (__ballot(!okl) != 0ull) { st = RTSSA_TRAJ_OVERFLOW; break; }
             if (has_nu) X[sp] = (int32_t)xv;
-            wave_lds_fence();
+            rt_wave_lds_fence();
             // ---- new propensities (mu and D(mu)) and their ancestors' sums
-            if (act) leaves[k] = lazy_propensity(rr0, c0, X);
-            wave_lds_fence();
+            if (act) leaves[k] = rt_propensity_mem(rr0, c0, X);
+            rt_wave_lds_fence();
 #pragma unroll
             for (int l = 1; l <= kMaxLevels; ++l) {
                 if (l > top) break;
@@ -776,7 +733,7 @@ __global__ __launch_bounds__(64) void rt_dmtree_kernel(rt_class_dev C)
                 const double v = dt_sum_node(tr, l, jn);
                 tr.d[l][jn] = v;
                 a0 = l == top ? v : a0;
-                wave_lds_fence();
+                rt_wave_lds_fence();
             }
             if (n_other > 63) {
                 const int de = dep_ptr[mu + 1];
@@ -784,8 +741,8 @@ __global__ __launch_bounds__(64) void rt_dmtree_kernel(rt_class_dev C)
                     const int q = q0 + lane;
                     int k2 = q < de ? dep_idx[q] : -1;
                     if (k2 == mu) k2 = -1;
-                    if (k2 >= 0) leaves[k2] = lazy_propensity(react[k2], cc[k2], X);
-                    wave_lds_fence();
+                    if (k2 >= 0) leaves[k2] = rt_propensity_mem(react[k2], cc[k2], X);
+                    rt_wave_lds_fence();
 #pragma unroll
                     for (int l = 1; l <= kMaxLevels; ++l) {
                         if (l > top) break;
@@ -793,7 +750,7 @@ __global__ __launch_bounds__(64) void rt_dmtree_kernel(rt_class_dev C)
                         const double v = dt_sum_node(tr, l, jn);
                         tr.d[l][jn] = v;
                         a0 = l == top ? v : a0;
-                        wave_lds_fence();
+                        rt_wave_lds_fence();
                     }
                 }
             }
@@ -822,7 +779,7 @@ __global__ __launch_bounds__(64) void rt_dmtree_kernel(rt_class_dev C)
             atomicAdd(&ws->firings, (unsigned long long)fired);
             atomicAdd(&ws->status_count[st], 1ull);
         }
-        wave_lds_fence();                                  // X and the tree are reused
+        rt_wave_lds_fence();                                  // X and the tree are reused
     }
 }
 

@@ -4,6 +4,7 @@
 
 #include "internal.h"
 #include "rt_device.h"
+#include "rt_wave.h"
 
 namespace {
 
@@ -113,19 +114,127 @@ __global__ void rt_debug_philox_kernel(const uint32_t* ctr, uint32_t k0, uint32_
     out[4 * i + 3] = w.w;
 }
 
+// ---- the selection step (Eq. 25) and near-tie rule of each mapping, on
+// rows of given values (test hook); the same device functions as the kernels
+__device__ __forceinline__ void debug_sel_store(int64_t r, const rt_min2& v, int32_t* mu,
+                                                double* v1, double* v2, uint8_t* near)
+{
+    mu[r] = v.k;
+    v1[r] = v.d1;
+    v2[r] = v.d2;
+    near[r] = rt_near_tie(v.d1, v.d2) ? 1 : 0;
+}
+
+// thread mapping: one lane per row, channels in order from {+inf, +inf, 0}
+__global__ __launch_bounds__(256) void rt_debug_sel_thread_kernel(
+    const double* v, int32_t M, int64_t count, int32_t* mu, double* v1, double* v2, uint8_t* near)
+{
+    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= count) return;
+    rt_min2 sel{__builtin_inf(), __builtin_inf(), 0};
+    for (int k = 0; k < M; ++k) rt_min2_push(sel, v[r * M + k], k);
+    debug_sel_store(r, sel, mu, v1, v2, near);
+}
+
+// sub-wavefront mapping: W lanes per row, lane l holds channels l + s W
+template <int W>
+__global__ __launch_bounds__(256) void rt_debug_sel_wave_kernel(
+    const double* v, int32_t M, int64_t count, int32_t* mu, double* v1, double* v2, uint8_t* near)
+{
+    constexpr int LOG2W = __builtin_ctz(W);
+    const int li = (int)(threadIdx.x & (W - 1));
+    const int64_t r = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> LOG2W;
+    rt_min2 loc = rt_min2_empty();
+    if (r < count)
+        for (int s = 0; li + s * W < M; ++s) rt_min2_push(loc, v[r * M + li + s * W], s);
+    loc = rt_min2_slot_to_channel(loc, li, LOG2W);
+    loc = rt_min2_allreduce<W>(loc);                 // every lane of the group is active
+    if (r < count && li == 0) debug_sel_store(r, loc, mu, v1, v2, near);
+}
+
+// workgroup mapping: one row per workgroup of L threads
+template <int L>
+__global__ __launch_bounds__(L) void rt_debug_sel_group_kernel(
+    const double* v, int32_t M, int64_t count, int32_t* mu, double* v1, double* v2, uint8_t* near)
+{
+    __shared__ rt_min2 wave_min[16];
+    const int tid = threadIdx.x;
+    const int64_t r = blockIdx.x;
+    rt_min2 loc = rt_min2_empty();
+    for (int s = 0; tid + s * L < M; ++s) rt_min2_push(loc, v[r * M + tid + s * L], s);
+    loc = rt_min2_slot_to_channel(loc, tid, __builtin_ctz(L));
+    loc = rt_min2_group_allreduce<L>(loc, wave_min);
+    if (tid == 0) debug_sel_store(r, loc, mu, v1, v2, near);
+}
+
+typedef void (*debug_sel_t)(const double*, int32_t, int64_t, int32_t*, double*, double*, uint8_t*);
+
 }  // namespace
+
+int rt_launch_debug_select(const double* v, int32_t M, int64_t count, int32_t mapping,
+                           int32_t lanes, int32_t* mu, double* v1, double* v2, uint8_t* near,
+                           hipStream_t stream)
+{
+    if (count <= 0) return RTSSA_OK;
+    debug_sel_t k = nullptr;
+    int64_t blocks = 0;
+    int block = 256;
+    if (mapping == RTSSA_MAP_THREAD) {
+        k = rt_debug_sel_thread_kernel;
+        blocks = (count + 255) / 256;
+    } else if (mapping == RTSSA_MAP_WAVE) {
+        switch (lanes) {
+            case 2: k = rt_debug_sel_wave_kernel<2>; break;
+            case 4: k = rt_debug_sel_wave_kernel<4>; break;
+            case 8: k = rt_debug_sel_wave_kernel<8>; break;
+            case 16: k = rt_debug_sel_wave_kernel<16>; break;
+            case 32: k = rt_debug_sel_wave_kernel<32>; break;
+            case 64: k = rt_debug_sel_wave_kernel<64>; break;
+            default: return rt_fail(RTSSA_E_INVALID, "wavefront lanes must be 2..64, a power of 2");
+        }
+        blocks = (count * lanes + 255) / 256;
+    } else if (mapping == RTSSA_MAP_WORKGROUP) {
+        switch (lanes) {
+            case 64: k = rt_debug_sel_group_kernel<64>; break;
+            case 128: k = rt_debug_sel_group_kernel<128>; break;
+            case 256: k = rt_debug_sel_group_kernel<256>; break;
+            case 512: k = rt_debug_sel_group_kernel<512>; break;
+            case 1024: k = rt_debug_sel_group_kernel<1024>; break;
+            default: return rt_fail(RTSSA_E_INVALID, "workgroup size must be 64..1024, a power of 2");
+        }
+        block = lanes;
+        blocks = count;
+    } else {
+        return rt_fail(RTSSA_E_INVALID, "unknown mapping");
+    }
+    if (blocks > 0x7FFFFFFF) return rt_fail(RTSSA_E_INVALID, "too many rows");
+    hipLaunchKernelGGL(k, dim3((unsigned)blocks), dim3(block), 0, stream, v, M, count, mu, v1, v2,
+                       near);
+    return hipGetLastError() == hipSuccess ? RTSSA_OK : rt_fail(RTSSA_E_HIP, "launch failed");
+}
+
+// blocks of the score reduction: one per 4096 trajectories, 1..256
+static int score_blocks(int64_t R)
+{
+    int64_t nb = (R + 4095) / 4096;
+    return (int)(nb > 256 ? 256 : (nb < 1 ? 1 : nb));
+}
+
+size_t rt_score_grad_workspace_bytes(int64_t R, int32_t M)
+{
+    const size_t nb = (size_t)score_blocks(R);
+    return sizeof(double) * (nb + nb * (size_t)M * 2);
+}
 
 int rt_launch_score_grad(const double* f, const uint32_t* n, const double* T, int64_t R,
                          int32_t M, int32_t baseline, double* grad, double* se,
-                         hipStream_t stream)
+                         void* workspace, hipStream_t stream)
 {
-    int nb = (int)((R + 4095) / 4096);
-    if (nb > 256) nb = 256;
-    if (nb < 1) nb = 1;
+    const int nb = score_blocks(R);
     const int64_t chunk = (R + nb - 1) / nb;
-    double* buf = nullptr;
-    const size_t bytes = sizeof(double) * ((size_t)nb + (size_t)nb * M * 2);
-    if (hipMallocAsync((void**)&buf, bytes, stream) != hipSuccess)
+    double* buf = (double*)workspace;
+    const size_t bytes = rt_score_grad_workspace_bytes(R, M);
+    if (!buf && hipMallocAsync((void**)&buf, bytes, stream) != hipSuccess)
         return rt_fail(RTSSA_E_NOMEM, "score workspace allocation failed");
     double* fpart = buf;
     double* part = buf + nb;
@@ -135,7 +244,7 @@ int rt_launch_score_grad(const double* f, const uint32_t* n, const double* T, in
     hipLaunchKernelGGL(rt_score_final_kernel, dim3((M + 255) / 256), dim3(256), 0, stream, part,
                        nb, M, R, grad, se);
     hipError_t e = hipGetLastError();
-    hipFreeAsync(buf, stream);
+    if (!workspace) hipFreeAsync(buf, stream);
     return e == hipSuccess ? RTSSA_OK : rt_fail(RTSSA_E_HIP, "score kernel launch failed");
 }
 

@@ -29,53 +29,7 @@
 
 namespace {
 
-constexpr uint32_t kTieNone = 0xFFFFFFFFu;
-constexpr unsigned long long kFnvOffset = 0xcbf29ce484222325ull;
-constexpr unsigned long long kFnvPrime = 0x100000001b3ull;
 constexpr int kBlock = 256;
-
-__device__ __forceinline__ double u64_to_f64(uint64_t h)
-{
-    return fma((double)(uint32_t)(h >> 32), 0x1p32, (double)(uint32_t)h);
-}
-
-// a_k = RN(c_k RN(h_k(X))) with X in LDS (Eq. 1-2).
-__device__ __forceinline__ double sw_propensity(int2 rr, double c, const int32_t* X)
-{
-    const int kind = (int)((uint32_t)rr.x >> 29);
-    const int s0 = rr.x & RT_SPECIES_MASK;
-    uint64_t h;
-    if (kind == RT_H_ZERO) {
-        h = 1;
-    } else if (kind == RT_H_ONE) {
-        h = (uint32_t)X[s0];
-    } else if (kind == RT_H_PAIR) {
-        const uint32_t x = (uint32_t)X[s0];
-        h = ((uint64_t)x * (uint32_t)(x - 1u)) >> 1;
-    } else {
-        h = (uint64_t)(uint32_t)X[s0] * (uint32_t)X[rr.y];
-    }
-    return c * u64_to_f64(h);
-}
-
-// Orders the wavefront's LDS accesses (the hardware completes them in order
-// for one wavefront; this keeps the compiler from reordering them).
-__device__ __forceinline__ void wave_lds_fence()
-{
-    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-}
-
-// Index of the item owning global unit u: unit_start[i] <= u < unit_start[i+1].
-__device__ __forceinline__ int find_item(rt_cptr<int64_t> unit_start, int count, int64_t u)
-{
-    int lo = 0, hi = count;   // unit_start[lo] <= u < unit_start[hi]
-    while (hi - lo > 1) {
-        const int mid = (lo + hi) >> 1;
-        if (unit_start[mid] <= u) lo = mid; else hi = mid;
-    }
-    return lo;
-}
 
 // Waves per SIMD the register allocation must allow: 8 slots of channel
 // state fit 3 (2 with a rate schedule's state); fewer slots are left to the
@@ -153,7 +107,7 @@ __global__ __launch_bounds__(kBlock, subwave_min_waves(S, SCHED)) void rt_subwav
                 const int s1 = __builtin_ctz(stale);
                 stale &= stale - 1u;
                 const int k = li + s1 * L;
-                const double an = sw_propensity(rt_const(net->react)[k], crate[k], X);
+                const double an = rt_propensity_mem(rt_const(net->react)[k], crate[k], X);
                 const double in = 1.0 / an;
 #pragma unroll
                 for (int s = 0; s < S; ++s) {
@@ -169,7 +123,7 @@ __global__ __launch_bounds__(kBlock, subwave_min_waves(S, SCHED)) void rt_subwav
             const double d = a[s] == 0.0 ? __builtin_inf() : fmax(raw, 0.0);
             rt_min2_push(loc, d, s);                       // slot now, channel below
         }
-        loc.k = loc.k == 0x7FFFFFFF ? loc.k : li + (loc.k << LOG2L);
+        loc = rt_min2_slot_to_channel(loc, li, LOG2L);
         // ---- argmin across the group's lanes (lowest k wins ties)
         loc = rt_min2_allreduce<L>(loc);
         const double d1 = loc.d1, d2 = loc.d2;
@@ -197,16 +151,20 @@ __global__ __launch_bounds__(kBlock, subwave_min_waves(S, SCHED)) void rt_subwav
             xv = (int32_t)v;
         }
         const bool ok = (__ballot(!okl) & gmask) == 0ull;
-        const bool near_tie = event && d2 - d1 <= 1e-12 * d1;
+        const bool near_tie = event && rt_near_tie(d1, d2);
         // a zero gap may have been clamped from a negative raw gap
         const bool rare =
             !live || term || near_tie || d1 == 0.0 || !ok || s_next < t_new || brk;
         if (__builtin_expect(__ballot(rare) != 0ull, 0)) {
+            // Counted once per event: when another group of the wavefront
+            // stops or meets a breakpoint, this group repeats its pass below
+            // without applying its event, so the counters are bumped only once
+            // the event is known to be applied (or, for a near-tie, when the
+            // event ends the trajectory by an overflow, as the oracle counts
+            // it); tie and the samples are idempotent.
+            bool clamped = false;
             if (event) {
-                if (near_tie) {
-                    if (li == 0) atomicAdd(&ws->near_ties, 1ull);
-                    tie = tie == kTieNone ? fired : tie;
-                }
+                if (near_tie) tie = tie == kTieNone ? fired : tie;
                 while (s_next < t_new) {
                     if (it->samples) {
                         int32_t* dst = it->samples + r * it->ss_r + (int64_t)g * it->ss_g;
@@ -217,14 +175,13 @@ __global__ __launch_bounds__(kBlock, subwave_min_waves(S, SCHED)) void rt_subwav
                 }
                 if (ok && d1 == 0.0 && li == (kmin & (L - 1))) {
                     const int sm = kmin >> LOG2L;
-                    bool clamped = false;
 #pragma unroll
                     for (int s = 0; s < S; ++s)
                         clamped = s == sm ? (Pk[s] - T[s]) * inv[s] < 0.0 : clamped;
-                    if (clamped) atomicAdd(&ws->clamps, 1ull);
                 }
             }
             const bool stop = !live || term || !ok;
+            if (near_tie && stop && li == 0) atomicAdd(&ws->near_ties, 1ull);   // event && !ok
             if (stop && !fresh) {
                 // ---- end of the trajectory
                 const int st = capped ? RTSSA_TRAJ_MAX_FIRINGS
@@ -263,13 +220,13 @@ __global__ __launch_bounds__(kBlock, subwave_min_waves(S, SCHED)) void rt_subwav
                 unsigned long long u = 0;
                 if (li == 0) u = atomicAdd(&ws->next_unit, 1ull);
                 u = __shfl(u, lane - li, 64);
-                wave_lds_fence();                          // X and flags are reused
+                rt_wave_lds_fence();                          // X and flags are reused
                 fresh = false;
                 capped = false;
                 pending = false;
                 active = (int64_t)u < total;
                 if (active) {
-                    const int item = find_item(unit_start, C.count, (int64_t)u);
+                    const int item = rt_find_item(unit_start, C.count, (int64_t)u);
                     it = rt_const(C.items) + item;
                     r = (int64_t)u - unit_start[item];
                     M = it->net.M;
@@ -290,7 +247,7 @@ __global__ __launch_bounds__(kBlock, subwave_min_waves(S, SCHED)) void rt_subwav
                     fired = 0;
                     tie = kTieNone;
                     hash = kFnvOffset;
-                    wave_lds_fence();
+                    rt_wave_lds_fence();
 #pragma unroll
                     for (int s = 0; s < S; ++s) {
                         T[s] = 0.0;
@@ -305,7 +262,7 @@ __global__ __launch_bounds__(kBlock, subwave_min_waves(S, SCHED)) void rt_subwav
                         if (k < M) {
                             const double p0 = rt_exp1_wave(key0, key1, traj, net_id, (uint32_t)k,
                                                            0u, &ws->slow_logs, sc);
-                            const double an = sw_propensity(rt_const(it->net.react)[k],
+                            const double an = rt_propensity_mem(rt_const(it->net.react)[k],
                                                             rt_const(it->net.c)[k], X);
                             const double in = 1.0 / an;
 #pragma unroll
@@ -336,6 +293,9 @@ __global__ __launch_bounds__(kBlock, subwave_min_waves(S, SCHED)) void rt_subwav
             // started groups compute first gaps, groups past a breakpoint
             // solve again; the others repeat their (idempotent) pass
             if (__ballot(stop || brk) != 0ull) continue;
+            // the event is applied below
+            if (near_tie && li == 0) atomicAdd(&ws->near_ties, 1ull);
+            if (clamped) atomicAdd(&ws->clamps, 1ull);
         }
         // ---- the event: jump, dependency flags, fresh draw by the owner lane
         mu = kmin;
@@ -353,7 +313,7 @@ __global__ __launch_bounds__(kBlock, subwave_min_waves(S, SCHED)) void rt_subwav
             nk[mu] = nm + 1u;
             E = rt_exp1_wave(key0, key1, traj, net_id, (uint32_t)mu, nm + 1u, &ws->slow_logs, sc);
         }
-        wave_lds_fence();
+        rt_wave_lds_fence();
         t = t_new;
         delta = d1;
         ++fired;

@@ -19,18 +19,9 @@
 
 #include "internal.h"
 #include "rt_device.h"
+#include "rt_wave.h"
 
 namespace {
-
-constexpr uint32_t kTieNone = 0xFFFFFFFFu;
-constexpr unsigned long long kFnvOffset = 0xcbf29ce484222325ull;
-constexpr unsigned long long kFnvPrime = 0x100000001b3ull;
-
-// RN((double)h) for h < 2^64: both halves convert exactly, one rounding.
-__device__ __forceinline__ double u64_to_f64(uint64_t h)
-{
-    return fma((double)(uint32_t)(h >> 32), 0x1p32, (double)(uint32_t)h);
-}
 
 // X[j] for a wave-uniform j (a species index of the network): a switch
 // becomes scalar branches, so X stays in registers instead of being copied
@@ -51,24 +42,13 @@ __device__ __forceinline__ int32_t pick(const int32_t (&X)[NT], int j)
     return X[0];
 }
 
-// h_k(X) of Eq. 2 with the reaction kind fixed per channel (uniform branch).
+// a_k of Eq. 1-2 with the reaction kind fixed per channel (uniform branch)
+// and X in registers.
 template <int NT>
 __device__ __forceinline__ double propensity(int kind, int s0, int s1, double c,
                                              const int32_t (&X)[NT])
 {
-    uint64_t h;
-    if (kind == RT_H_ZERO) {
-        h = 1;
-    } else if (kind == RT_H_ONE) {
-        // h < 2^32: its conversion is exact without the two-part form
-        return c * (double)(uint32_t)pick(X, s0);
-    } else if (kind == RT_H_PAIR) {
-        uint32_t x = (uint32_t)pick(X, s0);
-        h = ((uint64_t)x * (uint32_t)(x - 1u)) >> 1;   // x = 0 gives 0
-    } else {
-        h = (uint64_t)(uint32_t)pick(X, s0) * (uint32_t)pick(X, s1);
-    }
-    return c * u64_to_f64(h);
+    return rt_propensity(kind, s0, s1, c, [&](int j) { return pick<NT>(X, j); });
 }
 
 // Collects one lane's writes to one 64-byte line in its LDS buffer and
@@ -221,15 +201,16 @@ __global__ __launch_bounds__(256, thread_min_waves(MT, NT, METHOD, SCHED)) void 
             double d1 = __builtin_inf(), d2 = __builtin_inf();
             int mu = 0;
             if constexpr (METHOD == RTSSA_METHOD_RANDOM_TIME) {
+                rt_min2 sel{__builtin_inf(), __builtin_inf(), 0};
 #pragma unroll
                 for (int k = 0; k < MT; ++k) {
                     const double raw = (Pk[k] - T[k]) * inv[k];
                     const double d = a[k] == 0.0 ? __builtin_inf() : fmax(raw, 0.0);
-                    const bool lt = d < d1;
-                    d2 = fmin(d2, fmax(d1, d));            // the two smallest of {d1, d2, d}
-                    d1 = fmin(d1, d);
-                    mu = lt ? k : mu;
+                    rt_min2_push(sel, d, k);
                 }
+                d1 = sel.d1;
+                d2 = sel.d2;
+                mu = sel.k;
             } else {
                 // direct method: total rate, one block for the waiting time and
                 // the search (padding channels add +0 and are never reached)
@@ -276,28 +257,30 @@ __global__ __launch_bounds__(256, thread_min_waves(MT, NT, METHOD, SCHED)) void 
             }
             const bool event = live && !term && !brk;     // this pass may apply an event
             const bool near_tie = METHOD == RTSSA_METHOD_RANDOM_TIME && event &&
-                                  d2 - d1 <= 1e-12 * d1;
+                                  rt_near_tie(d1, d2);
             // a zero gap may have been clamped from a negative raw gap
             const bool rare = !live || term || brk || near_tie ||
                               (METHOD == RTSSA_METHOD_RANDOM_TIME && d1 == 0.0) || !ok ||
                               s_next < t_new;
             if (__builtin_expect(__ballot(rare) != 0ull, 0)) {
+                // Counted once per event: when another lane of the wave stops or
+                // meets a breakpoint, this lane repeats its pass below without
+                // applying its event, so the counters are bumped only once the
+                // event is known to be applied (or, for a near-tie, when the
+                // event ends the trajectory by an overflow, as the oracle counts
+                // it); tie and the samples are idempotent.
+                bool clamped = false;
                 if (event) {
-                    if (near_tie) {
-                        atomicAdd(&ws->near_ties, 1ull);
-                        tie = tie == kTieNone ? fired : tie;
-                    }
+                    if (near_tie) tie = tie == kTieNone ? fired : tie;
                     while (s_next < t_new) {
                         if (it->samples) write_sample(g, false);
                         ++g;
                         s_next = g < it->G ? it->s[g] : __builtin_inf();
                     }
                     if (METHOD == RTSSA_METHOD_RANDOM_TIME && ok && d1 == 0.0) {
-                        bool clamped = false;
 #pragma unroll
                         for (int k = 0; k < MT; ++k)
                             clamped = mu == k ? (Pk[k] - T[k]) * inv[k] < 0.0 : clamped;
-                        if (clamped) atomicAdd(&ws->clamps, 1ull);
                     }
                 }
                 if (SCHED && brk) {
@@ -318,6 +301,7 @@ __global__ __launch_bounds__(256, thread_min_waves(MT, NT, METHOD, SCHED)) void 
                     }
                 }
                 const bool stop = !live || term || (!ok && !brk);
+                if (near_tie && stop) atomicAdd(&ws->near_ties, 1ull);   // event && !ok
                 if (stop && !fresh) {
                     // end of the trajectory
                     const int st = capped ? RTSSA_TRAJ_MAX_FIRINGS
@@ -400,6 +384,9 @@ __global__ __launch_bounds__(256, thread_min_waves(MT, NT, METHOD, SCHED)) void 
                 }
                 // started lanes (and lanes past a breakpoint) compute their gaps
                 if (__ballot(stop || brk) != 0ull) continue;
+                // the event is applied below
+                if (near_tie) atomicAdd(&ws->near_ties, 1ull);
+                if (clamped) atomicAdd(&ws->clamps, 1ull);
             }
             if constexpr (METHOD == RTSSA_METHOD_DIRECT) {
 #pragma unroll
@@ -448,8 +435,12 @@ __global__ __launch_bounds__(256, thread_min_waves(MT, NT, METHOD, SCHED)) void 
 
 // Prepares one launch: clears the counters of ws and `extra` (item counters),
 // sets the Philox key (from key_src when given, so that a captured graph can
-// be replayed with new seeds), and for a single run stores its item
-// descriptor and unit range.
+// be replayed with new seeds), and for a single run checks its sample grid
+// and stores its item descriptor and unit range.  A grid that is not
+// non-decreasing within [0, t_end] leaves the run with no work (R = 0 in the
+// stored descriptor), marks every trajectory RTSSA_TRAJ_NOT_RUN and sets
+// ws->bad_input, so the simulation kernels that follow exit at once and the
+// host learns of it without reading the grid itself.
 __global__ void rt_setup_kernel(rt_ws* ws, unsigned long long* extra, int64_t n_extra,
                                 uint32_t key0, uint32_t key1, const uint32_t* key_src,
                                 rt_item_dev item, rt_item_dev* item_dst, int64_t* unit_start,
@@ -458,16 +449,30 @@ __global__ void rt_setup_kernel(rt_ws* ws, unsigned long long* extra, int64_t n_
     const int64_t i0 = threadIdx.x + (int64_t)blockIdx.x * blockDim.x;
     const int64_t stride = (int64_t)blockDim.x * gridDim.x;
     for (int64_t i = i0; i < n_extra; i += stride) extra[i] = 0ull;
+    bool bad = false;
+    if (item_dst && blockIdx.x == 0) {             // uniform over the block
+        for (int g = threadIdx.x; g < item.G; g += blockDim.x) {
+            const double s = item.s[g];
+            bad = bad || !(s >= 0.0 && s <= item.t_end) || (g > 0 && s < item.s[g - 1]);
+        }
+        bad = __syncthreads_or(bad);
+        if (bad && item.status)
+            for (int64_t r = threadIdx.x; r < R; r += blockDim.x)
+                item.status[r] = (uint8_t)RTSSA_TRAJ_NOT_RUN;
+    }
     if (i0 == 0) {
         ws->firings = ws->near_ties = ws->clamps = ws->slow_logs = 0ull;
         for (int q = 0; q < 4; ++q) ws->status_count[q] = 0ull;
         ws->next_unit = 0ull;
+        ws->bad_input = bad ? 1ull : 0ull;
         ws->key0 = key_src ? key_src[0] : key0;
         ws->key1 = key_src ? key_src[1] : key1;
         if (item_dst) {
-            *item_dst = item;
+            rt_item_dev it = item;
+            if (bad) it.R = 0;
+            *item_dst = it;
             unit_start[0] = 0;
-            unit_start[1] = R;
+            unit_start[1] = bad ? 0 : R;
         }
     }
 }

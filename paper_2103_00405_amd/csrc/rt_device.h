@@ -4,7 +4,12 @@
 #define RT_LOG_CONST __constant__
 #include <hip/hip_runtime.h>
 
+#include "internal.h"
 #include "rt_math.h"
+
+constexpr uint32_t kTieNone = 0xFFFFFFFFu;                 // tie_step of a path without near-ties
+constexpr unsigned long long kFnvOffset = 0xcbf29ce484222325ull;   // seq_hash start
+constexpr unsigned long long kFnvPrime = 0x100000001b3ull;         // seq_hash multiplier
 
 // Read-only launch data (network tables, item descriptors, prefix sums, the
 // sample grid) read through the constant address space: the compiler may
@@ -24,6 +29,71 @@ template <typename T>
 __device__ __forceinline__ rt_cptr<T> rt_const(const T* p)
 {
     return (rt_cptr<T>)p;
+}
+
+// ---------------------------------------------------------------------
+// Arithmetic of one channel and of the selection, shared by every kernel.
+
+// RN((double)h) for h < 2^64: both halves convert exactly, one rounding.
+__device__ __forceinline__ double rt_u64_to_f64(uint64_t h)
+{
+    return fma((double)(uint32_t)(h >> 32), 0x1p32, (double)(uint32_t)h);
+}
+
+// a_k = RN(c_k RN(h_k(X))) of Eq. 1-2 with h_k = prod_j C(X_j, sigma_jk)
+// exact in 64-bit integers (C(X, 2) = X(X - 1) / 2); kind, s0 and s1 come
+// from the reactant table (RT_H_*), x(j) reads species j.  One-species h is
+// below 2^32 and converts exactly without the two-part form.
+template <class XGet>
+__device__ __forceinline__ double rt_propensity(int kind, int s0, int s1, double c, XGet x)
+{
+    uint64_t h;
+    if (kind == RT_H_ZERO) {
+        h = 1;
+    } else if (kind == RT_H_ONE) {
+        return c * (double)(uint32_t)x(s0);
+    } else if (kind == RT_H_PAIR) {
+        const uint32_t v = (uint32_t)x(s0);
+        h = ((uint64_t)v * (uint32_t)(v - 1u)) >> 1;   // v = 0 gives 0
+    } else {
+        h = (uint64_t)(uint32_t)x(s0) * (uint32_t)x(s1);
+    }
+    return c * rt_u64_to_f64(h);
+}
+
+// The same with X in memory (LDS) and the packed reactant-table entry
+// rr = (s0 | kind << 29, s1).
+__device__ __forceinline__ double rt_propensity_mem(int2 rr, double c, const int32_t* X)
+{
+    return rt_propensity((int)((uint32_t)rr.x >> 29), rr.x & RT_SPECIES_MASK, rr.y, c,
+                         [&](int j) { return X[j]; });
+}
+
+// The near-tie rule (Eq. 4 gives ties probability zero; in binary64 the two
+// smallest gaps d1 <= d2 can still round within reach of each other):
+// RN(d2 - d1) <= RN(1e-12 d1).
+__device__ __forceinline__ bool rt_near_tie(double d1, double d2)
+{
+    return d2 - d1 <= 1e-12 * d1;
+}
+
+// Orders the wavefront's LDS accesses (the hardware completes them in order
+// for one wavefront; this keeps the compiler from reordering them).
+__device__ __forceinline__ void rt_wave_lds_fence()
+{
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+}
+
+// Index of the item owning global unit u: unit_start[i] <= u < unit_start[i+1].
+__device__ __forceinline__ int rt_find_item(rt_cptr<int64_t> unit_start, int count, int64_t u)
+{
+    int lo = 0, hi = count;   // unit_start[lo] <= u < unit_start[hi]
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (unit_start[mid] <= u) lo = mid; else hi = mid;
+    }
+    return lo;
 }
 
 // RN(-ln u) for the wave's active lanes.  The fast phase runs in every lane;

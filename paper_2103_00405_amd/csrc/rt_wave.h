@@ -125,3 +125,29 @@ __device__ __forceinline__ rt_min2 rt_min2_allreduce(rt_min2 v)
     if (W >= 64) v = rt_min2_swap_step<32>(v);
     return v;
 }
+
+// A lane that pushed its slots s (channel lane + s L) in increasing order
+// names its channel: slot -> lane + slot L (empty stays empty).
+__device__ __forceinline__ rt_min2 rt_min2_slot_to_channel(rt_min2 v, int lane, int log2L)
+{
+    v.k = v.k == 0x7FFFFFFF ? v.k : lane + (v.k << log2L);
+    return v;
+}
+
+// All-reduce over a workgroup of L = 64 W threads: the wavefront all-reduce,
+// then the W wavefront results through LDS (wave_min[W]) behind one
+// workgroup barrier, which every thread of the group must reach; every lane
+// reads partial (lane mod W), so the groups of W lanes all reduce the same W
+// values and every thread returns the same result.
+template <int L>
+__device__ __forceinline__ rt_min2 rt_min2_group_allreduce(rt_min2 v, rt_min2* wave_min)
+{
+    constexpr int W = L / 64;
+    v = rt_min2_allreduce<64>(v);
+    if constexpr (W > 1) {
+        if ((threadIdx.x & 63u) == 0) wave_min[threadIdx.x >> 6] = v;
+    }
+    __syncthreads();
+    if constexpr (W > 1) v = rt_min2_allreduce<W>(wave_min[threadIdx.x & (W - 1)]);
+    return v;
+}

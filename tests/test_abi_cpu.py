@@ -172,4 +172,4 @@ def test_null_arguments_rejected():
     assert L.rtssa_network_create(1, 1, None, None, None, None, None, None, None, None) == -1
     assert L.rtssa_simulate(None, None, 0, 1.0, None, 0, 1, 0, 0, 1, None, 0, 0, 0, None, None,
                             None, None, None, None, None, None, None, None) == -1
-    assert L.rtssa_score_grad(None, None, None, 0, 0, 1, None, None, None) == -1
+    assert L.rtssa_score_grad(None, None, None, 0, 0, 1, None, None, None, 0, None) == -1
