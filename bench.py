@@ -29,20 +29,40 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-# Issue-slot count of one firing of the method for a 3-channel, 2-species
-# network on CDNA (full-rate VALU op = 1 slot; 32-bit integer products and
-# v_rcp_f64 = 4 slots).  Derivation per item:
-#   gaps 3x(sub, mul, max, cmp, 2 sel) 18; argmin with second minimum 15;
-#   near-tie, time, termination and sample checks 6; internal-time update 9;
-#   jump with overflow check 10; firing counts 6; Philox4x32-10 10x(2
-#   products x4 + 2 xor3) 100; 53-bit uniform 8; correctly rounded log fast
-#   phase 55; P refresh 8; three propensities with reciprocals 51.
-ALG_SLOTS_PER_FIRING_LV = 286
-# Per firing of an M-channel network in the workgroup mapping: per channel
-# T update (1), gap (sub, mul, max, cmp, 2 sel = 6), argmin with second
-# minimum (5); plus the draw (~163 as above) and about 20 dependent
-# propensities with reciprocals (~17 each).
-def alg_slots_group(M, deps=20):
+# Algorithmic issue slots of one firing of a 3-channel, 2-species network
+# (full-rate VALU op = 1 slot; 32-bit integer products and v_rcp_f64 = 4):
+# per channel sub, mul, fma and about three compares or selects; the fired
+# channel's propensities with one division each (~13); one Philox4x32-10
+# block (~100 instructions, 20 multi-pass products), the 53-bit uniform (~6),
+# the correctly rounded log's fast path (~30) and bookkeeping (~15): about
+# 200 instructions = 240-270 slots, taken as 255.  This is the figure the
+# roofline fraction uses.
+ALG_SLOTS_PER_FIRING_LV = 255
+# The same firing itemised for this kernel's own code (reported beside it):
+# gaps 3x(sub, mul, max, cmp, 2 sel) 18; argmin with second minimum 15;
+# near-tie, time, termination and sample checks 6; internal-time update 9;
+# jump with overflow check 10; firing counts 6; Philox4x32-10 10x(2 products
+# x4 + 2 xor3) 100; 53-bit uniform 8; correctly rounded log fast phase 55; P
+# refresh 8; three propensities with reciprocals 51.
+ITEMISED_SLOTS_PER_FIRING_LV = 286
+# Instructions the profiler counts per firing of the headline kernel
+# (SQ_INSTS_VALU x 64 / firings; profiles/rt_thread_kernel_lv_ensemble_sq_counters.md).
+ISSUED_VALU_PER_FIRING_LV = 327
+
+
+# Algorithmic lane-ops of one firing of an M-channel network in the eager
+# form: per channel about 3 FP64 operations (T update, P - T, times 1/a) and 3
+# compares or selects (clamp, dead-channel test, argmin), the wavefront and
+# workgroup argmin (~600), about 20 dependent propensities (~13 each) and the
+# draw with its log (~150): 25k at M = 4000.  The roofline fraction uses it.
+def alg_lane_ops_eager(M, deps=20):
+    return 6 * M + 600 + 13 * deps + 150
+
+
+# The same firing itemised for the workgroup kernel's code (reported beside
+# it): per channel T update (1), gap (sub, mul, max, cmp, 2 sel = 6), argmin
+# with second minimum (5); the draw (~163) and the dependents (~17 each).
+def itemised_slots_group(M, deps=20):
     return 12 * M + 163 + 17 * deps
 
 
@@ -266,7 +286,7 @@ def bench_direct(api, W, steps=2, warmup=1, R=1 << 20):
 def bench_large(api, W, steps, warmup, cpu_s=0.0):
     w = W.large_random()
     r = run_ensemble(api, w, steps, warmup)
-    slots = alg_slots_group(w.net.M)
+    slots = alg_lane_ops_eager(w.net.M)
     ach = slots * r["firings_per_step"] / r["kernel_s"]
     cpu = None
     if cpu_s > 0:
@@ -283,7 +303,9 @@ def bench_large(api, W, steps, warmup, cpu_s=0.0):
             "mapping": "workgroup", "block": r["stats"]["block"], "grid": r["stats"]["grid"],
             "roofline": {"bound": "alu", "achieved": ach / 1e12, "peak": PEAK_LANE_SLOTS / 1e12,
                          "unit": "Tslot/s", "frac": ach / PEAK_LANE_SLOTS,
-                         "slots_per_firing": slots, "kernel_ms": r["kernel_s"] * 1e3}}
+                         "slots_per_firing": slots,
+                         "itemised_slots_per_firing": itemised_slots_group(w.net.M),
+                         "kernel_ms": r["kernel_s"] * 1e3}}
 
 
 def bench_large_lazy(api, W, steps, warmup, eager_value=None):
@@ -556,7 +578,11 @@ def main():
                      "frac": achieved / PEAK_LANE_SLOTS, "traffic": LV_TRAFFIC_BYTES_PER_LAUNCH,
                      "traffic_unit": "B per launch",
                      "kernel": "rt_thread_kernel<3,2>", "kernel_ms": r["kernel_s"] * 1e3,
-                     "slots_per_firing": ALG_SLOTS_PER_FIRING_LV},
+                     "slots_per_firing": ALG_SLOTS_PER_FIRING_LV,
+                     "itemised_slots_per_firing": ITEMISED_SLOTS_PER_FIRING_LV,
+                     "frac_itemised": ITEMISED_SLOTS_PER_FIRING_LV * r["firings_per_step"] /
+                     r["kernel_s"] / PEAK_LANE_SLOTS,
+                     "issued_valu_per_firing_profiled": ISSUED_VALU_PER_FIRING_LV},
         "firings_per_step": r["firings_per_step"],
         "near_ties": st["near_ties"],
         "slow_logs": st["slow_logs"],
