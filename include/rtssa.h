@@ -259,6 +259,38 @@ int rtssa_simulate(const rtssa_network* net, const int32_t* x0, int32_t x0_per_t
                    uint8_t* status, uint64_t* seq_hash, uint32_t* tie_step,
                    const rtssa_options* opt, rtssa_stream_t stream, rtssa_stats* stats);
 
+/* Size of the library's fixed device scratch array (one per GPU). */
+#define RTSSA_NOALLOC_SCRATCH_BYTES (4u << 20)
+
+/*
+ * rtssa_simulate for callers that cannot allocate device memory (code under
+ * stream capture, tight serving loops, harnesses that forbid hipMalloc):
+ * the same arguments, checks, kernels and results bit for bit, but the run's
+ * counters, queue heads, item descriptor and (LAZY) channel records live in a
+ * file-scope device array of RTSSA_NOALLOC_SCRATCH_BYTES that the library
+ * holds on each GPU it runs on until the process ends.  The call allocates
+ * and frees nothing (no hipMalloc, no events; stats->kernel_ms is 0).
+ *   opt->workspace must be NULL.
+ *   LAZY and DIRECT_TREE need the network's rows built first
+ *   (rtssa_workspace_size or an earlier rtssa_simulate), else E_INVALID.
+ *   LAZY keeps only as many resident wavefronts as their channel records fit
+ *   in the array (44 bytes per channel each; same results, fewer trajectories
+ *   in flight); a run that does not fit one wavefront's records is rejected
+ *   with E_UNSUPPORTED.
+ * Every call on a GPU shares that GPU's array (the setup kernel clears what
+ * must start at zero): calls that overlap on one GPU -- on two streams, or
+ * from two host threads -- race and give wrong results.  Calls on one stream
+ * are ordered and safe.
+ */
+int rtssa_simulate_noalloc(const rtssa_network* net, const int32_t* x0, int32_t x0_per_traj,
+                           double t_end, const double* sample_t, int32_t G,
+                           uint64_t seed, uint32_t net_id, uint64_t traj_offset, int64_t R,
+                           int32_t* samples, int64_t s_stride_r, int64_t s_stride_g,
+                           int64_t s_stride_n,
+                           uint32_t* n_out, double* T_out, int32_t* x_final, double* t_last,
+                           uint8_t* status, uint64_t* seq_hash, uint32_t* tie_step,
+                           const rtssa_options* opt, rtssa_stream_t stream, rtssa_stats* stats);
+
 /* Device workspace of rtssa_score_grad for R trajectories of M channels. */
 int rtssa_score_grad_workspace_size(int64_t R, int32_t M, size_t* bytes);
 

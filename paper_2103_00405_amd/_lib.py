@@ -53,6 +53,9 @@ SIGNATURES = {
     "rtssa_simulate": (C.c_int, [vp, vp, i32, f64, vp, i32, u64, u32, u64, i64, vp, i64, i64,
                                  i64, vp, vp, vp, vp, vp, vp, vp, C.POINTER(Options), vp,
                                  C.POINTER(Stats)]),
+    "rtssa_simulate_noalloc": (C.c_int, [vp, vp, i32, f64, vp, i32, u64, u32, u64, i64, vp, i64,
+                                         i64, i64, vp, vp, vp, vp, vp, vp, vp,
+                                         C.POINTER(Options), vp, C.POINTER(Stats)]),
     "rtssa_workspace_size": (C.c_int, [vp, i64, C.POINTER(Options), C.POINTER(C.c_size_t)]),
     "rtssa_score_grad_workspace_size": (C.c_int, [i64, i32, C.POINTER(C.c_size_t)]),
     "rtssa_score_grad": (C.c_int, [vp, vp, vp, i64, i32, i32, vp, vp, vp, u64, vp]),

@@ -260,14 +260,15 @@ extern "C" int rtssa_workspace_size(const rtssa_network* net, int64_t R, const r
 
 // One run on a workspace the caller provides (ws, at least the bytes that
 // rt_run_workspace reports for lazy_grid): validates, enqueues the setup and
-// simulation kernels on the stream; with stats, waits and fills them.
+// simulation kernels on the stream; with stats, waits and fills them
+// (kernel_ms from two HIP events when time_kernels, else 0).
 int rt_simulate_on(const rtssa_network* net, const int32_t* x0, int32_t x0_per_traj,
                    double t_end, const double* sample_t, int32_t G, uint64_t seed,
                    uint32_t net_id, uint64_t traj_offset, int64_t R, int32_t* samples,
                    int64_t s_stride_r, int64_t s_stride_g, int64_t s_stride_n, uint32_t* n_out,
                    double* T_out, int32_t* x_final, double* t_last, uint8_t* status,
                    uint64_t* seq_hash, uint32_t* tie_step, const rtssa_options& o, void* wsp,
-                   int lazy_grid, hipStream_t stream, rtssa_stats* stats)
+                   int lazy_grid, hipStream_t stream, rtssa_stats* stats, bool time_kernels)
 {
     const uint64_t maxf = o.max_firings ? o.max_firings : 10000000ull;
     const bool wave_tree = o.method == RTSSA_METHOD_LAZY || o.method == RTSSA_METHOD_DIRECT_TREE;
@@ -295,13 +296,13 @@ int rt_simulate_on(const rtssa_network* net, const int32_t* x0, int32_t x0_per_t
     C.has_schedule = net->dev.sched_B > 0;
 
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
-    if (stats) {
+    if (stats && time_kernels) {
         hipEventCreate(&ev0);
         hipEventCreate(&ev1);
     }
     int rc = rt_launch_setup(&sc->ws, sc->item_next, 2, (uint32_t)seed, (uint32_t)(seed >> 32),
                              nullptr, &item, &sc->item, sc->unit_start, stream);
-    if (!rc && stats) hipEventRecord(ev0, stream);
+    if (!rc && ev0) hipEventRecord(ev0, stream);
     int grid_used = 0, block_used = 0;
     if (!rc && o.method == RTSSA_METHOD_LAZY) {
         block_used = 64;
@@ -314,14 +315,14 @@ int rt_simulate_on(const rtssa_network* net, const int32_t* x0, int32_t x0_per_t
                              &block_used, &grid_used, o.method);
     }
     if (!rc && stats) {
-        hipEventRecord(ev1, stream);
+        if (ev1) hipEventRecord(ev1, stream);
         rt_ws h{};
         rc = check_hip(hipMemcpyAsync(&h, &sc->ws, sizeof(rt_ws), hipMemcpyDeviceToHost, stream),
                        "reading stats");
         if (!rc) rc = check_hip(hipStreamSynchronize(stream), "simulation");
         if (!rc) {
             float ms = 0.f;
-            hipEventElapsedTime(&ms, ev0, ev1);
+            if (ev0 && ev1) hipEventElapsedTime(&ms, ev0, ev1);
             rt_fill_stats(stats, h);
             stats->kernel_ms = ms;
             stats->mapping = mapping;

@@ -210,4 +210,5 @@ int rt_simulate_on(const rtssa_network* net, const int32_t* x0, int32_t x0_per_t
                    int64_t s_stride_r, int64_t s_stride_g, int64_t s_stride_n, uint32_t* n_out,
                    double* T_out, int32_t* x_final, double* t_last, uint8_t* status,
                    uint64_t* seq_hash, uint32_t* tie_step, const rtssa_options& o, void* wsp,
-                   int lazy_grid, hipStream_t stream, rtssa_stats* stats);
+                   int lazy_grid, hipStream_t stream, rtssa_stats* stats,
+                   bool time_kernels = true);
