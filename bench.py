@@ -112,8 +112,10 @@ def cpu_baseline(w, target_s):
     o = oracle.simulate(w.net, w.x0, w.t_end, w.sample_t, w.seed, R, threads=threads)
     dt = time.perf_counter() - t0
     fir = int(o["stats"]["firings"])
+    # cores = the threads the oracle used (one std::thread each, at most the
+    # 16-core CPU share of the GPU host); host_cores = what the host reports
     return {"value": fir / dt, "unit": "firings/s", "cores": oracle.threads_used(threads, R),
-            "kind": "oracle",
+            "host_cores": os.cpu_count(), "kind": "oracle",
             "sample": "first %d of the %d trajectories (%d firings, %.1f s)" % (R, w.R, fir, dt)}
 
 
@@ -431,6 +433,16 @@ BATCH_MAX_FIRINGS = 100_000     # per trajectory; 5x the 2e4 the t_end is set fo
 LAZY_ABOVE_M = 512              # batched networks above this many channels run the lazy form
 
 
+def batch_jobs(api, wl):
+    """Jobs of the batched workload: networks above LAZY_ABOVE_M channels run
+    the lazy form (a class of its own, launched first), the others the eager
+    mappings; the per-network launches use the same method per network."""
+    return [dict(net=api.Network(w.net), x0=w.x0, t_end=w.t_end, sample_t=w.sample_t, R=w.R,
+                 net_id=w.net_id,
+                 method=api.METHOD_LAZY if w.net.M > LAZY_ABOVE_M else api.METHOD_RANDOM_TIME)
+            for w in wl]
+
+
 def bench_batched(api, W, steps=2, n_nets=4096, solo_sample=32, tune_samples=16, cpu_s=0.0):
     """4096 random networks (M log-uniform in [3, 2048], N = M/4, 64
     trajectories each, t_end for about 2e4 firings) in one captured launch per
@@ -447,13 +459,7 @@ def bench_batched(api, W, steps=2, n_nets=4096, solo_sample=32, tune_samples=16,
     import torch
     t0 = time.perf_counter()
     wl = W.batch_networks(n_nets)
-    # networks above LAZY_ABOVE_M channels run the lazy form (its own class,
-    # launched first), the others the eager mappings; the per-network launches
-    # below use the same method per network
-    jobs = [dict(net=api.Network(w.net), x0=w.x0, t_end=w.t_end, sample_t=w.sample_t, R=w.R,
-                 net_id=w.net_id,
-                 method=api.METHOD_LAZY if w.net.M > LAZY_ABOVE_M else api.METHOD_RANDOM_TIME)
-            for w in wl]
+    jobs = batch_jobs(api, wl)
     log("batched: %d networks generated in %.1f s" % (n_nets, time.perf_counter() - t0))
     want = ("samples", "n", "T", "x_final", "status")
     b0 = api.Batch(jobs, want=want, max_firings=BATCH_MAX_FIRINGS)

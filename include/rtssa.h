@@ -211,10 +211,12 @@ int rtssa_network_set_schedule(rtssa_network* net, int32_t B, const double* time
  * Device workspace, in bytes, of one rtssa_simulate call of this network with
  * R trajectories and these options (opt may be NULL): the run's counters and
  * work-queue heads, plus, for LAZY, one slice of channel records per resident
- * wavefront (about 44 bytes per channel each).  For LAZY and DIRECT_TREE it
- * also builds the network's fixed-stride rows if they are not built yet
- * (synchronous; they are allocated once per network), so that a later call
- * with a caller workspace allocates nothing.  No stream work otherwise.
+ * wavefront (about 44 bytes per channel each).  For LAZY, DIRECT_TREE and the
+ * random-time workgroup mapping it also builds the network's fixed-stride
+ * rows (its jumps and dependency lists, about 256 bytes per channel) if they
+ * are not built yet (synchronous; they are allocated once per network), so
+ * that a later call with a caller workspace allocates nothing.  No stream
+ * work otherwise.
  */
 int rtssa_workspace_size(const rtssa_network* net, int64_t R, const rtssa_options* opt,
                          size_t* bytes);
@@ -245,10 +247,11 @@ int rtssa_workspace_size(const rtssa_network* net, int64_t R, const rtssa_option
  * without waiting.
  * opt may be NULL (defaults).  With opt->workspace the call allocates
  * nothing and synchronises nothing unless stats is given, so it can be
- * captured into a caller's hipGraph (for LAZY and DIRECT_TREE the network's
- * rows must have been built by rtssa_workspace_size or an earlier run, else
- * RTSSA_E_INVALID); without it a workspace of rtssa_workspace_size() bytes
- * is allocated stream-ordered and freed after the launch.
+ * captured into a caller's hipGraph (for LAZY, DIRECT_TREE and the
+ * workgroup mapping the network's rows must have been built by
+ * rtssa_workspace_size or an earlier run, else RTSSA_E_INVALID); without it
+ * a workspace of rtssa_workspace_size() bytes is allocated stream-ordered
+ * and freed after the launch.
  */
 int rtssa_simulate(const rtssa_network* net, const int32_t* x0, int32_t x0_per_traj,
                    double t_end, const double* sample_t, int32_t G,
@@ -271,8 +274,9 @@ int rtssa_simulate(const rtssa_network* net, const int32_t* x0, int32_t x0_per_t
  * holds on each GPU it runs on until the process ends.  The call allocates
  * and frees nothing (no hipMalloc, no events; stats->kernel_ms is 0).
  *   opt->workspace must be NULL.
- *   LAZY and DIRECT_TREE need the network's rows built first
- *   (rtssa_workspace_size or an earlier rtssa_simulate), else E_INVALID.
+ *   LAZY, DIRECT_TREE and the workgroup mapping need the network's rows
+ *   built first (rtssa_workspace_size or an earlier rtssa_simulate), else
+ *   E_INVALID.
  *   LAZY keeps only as many resident wavefronts as their channel records fit
  *   in the array (44 bytes per channel each; same results, fewer trajectories
  *   in flight); a run that does not fit one wavefront's records is rejected
@@ -367,6 +371,11 @@ int rtssa_batch_run(rtssa_batch* batch, uint64_t seed, int32_t use_graph, rtssa_
  * trajectories and largest channel count. */
 int rtssa_batch_info(const rtssa_batch* batch, int32_t cls, int32_t* mapping, int32_t* lanes,
                      int32_t* n_items, int64_t* trajectories, int32_t* max_M);
+/* Items of class cls (indices into the creation array, in the class's
+ * queue order: heaviest first): *count receives the class's item count and
+ * the first min(capacity, count) indices are written to items (may be NULL). */
+int rtssa_batch_class_items(const rtssa_batch* batch, int32_t cls, int32_t* items,
+                            int32_t capacity, int32_t* count);
 int rtssa_batch_destroy(rtssa_batch* batch);
 
 /* Autotuner: for every size class among the items (networks beyond the
@@ -405,8 +414,13 @@ void rtssa_debug_neglog_fast_host(uint64_t m, double* yh, double* yl);
  * order; RTSSA_MAP_WAVE: groups of lanes = 2..64 lanes of a wavefront, lane l
  * holding channels l + s lanes, reduced by lane exchanges; RTSSA_MAP_WORKGROUP:
  * one workgroup of lanes = 64..1024 threads per row, wavefronts merged through
- * LDS.  Outputs are device memory: mu int32 [count], v1 and v2 float64
- * [count], near uint8 [count]. */
+ * LDS; RTSSA_DEBUG_MAP_WORKGROUP_LDS: the selection of the workgroup kernel
+ * that keeps the propensities in LDS (lane minima, then a smallest-value
+ * reduction per wavefront and one merge through LDS), whose v2 is exact
+ * whenever the near-tie test can hold and otherwise a value no smaller than
+ * the true second smallest and out of its reach.  Outputs are device memory:
+ * mu int32 [count], v1 and v2 float64 [count], near uint8 [count]. */
+#define RTSSA_DEBUG_MAP_WORKGROUP_LDS 4
 int rtssa_debug_select(const double* v, int32_t M, int64_t count, int32_t mapping,
                        int32_t lanes, int32_t* mu, double* v1, double* v2, uint8_t* near,
                        rtssa_stream_t stream);

@@ -63,6 +63,7 @@ SIGNATURES = {
                                      C.POINTER(vp)]),
     "rtssa_batch_run": (C.c_int, [vp, u64, i32, vp, C.POINTER(Stats)]),
     "rtssa_batch_info": (C.c_int, [vp, i32, vp, vp, vp, vp, vp]),
+    "rtssa_batch_class_items": (C.c_int, [vp, i32, vp, i32, C.POINTER(i32)]),
     "rtssa_batch_destroy": (C.c_int, [vp]),
     "rtssa_autotune": (C.c_int, [C.POINTER(BatchItem), i32, i32, C.c_char_p, vp]),
     "rtssa_debug_neglog": (C.c_int, [vp, vp, vp, i64, i32, vp]),

@@ -321,6 +321,14 @@ class Batch:
                             trajectories=r.value, max_M=mm.value))
         return out
 
+    def class_items(self, cls):
+        """Item indices of class ``cls`` in queue order (heaviest first)."""
+        n = C.c_int32()
+        check(lib().rtssa_batch_class_items(self._h, int(cls), None, 0, C.byref(n)))
+        out = (C.c_int32 * max(1, n.value))()
+        check(lib().rtssa_batch_class_items(self._h, int(cls), out, n.value, C.byref(n)))
+        return [int(out[i]) for i in range(n.value)]
+
     def close(self):
         """Release the batch's device descriptors, streams and graph (its
         networks may then take a new rate schedule)."""

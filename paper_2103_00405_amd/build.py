@@ -16,8 +16,8 @@ LIB = os.path.join(HERE, "librtssa.so")
 BUILD_DIR = os.path.join(HERE, "_build")
 ARCH = os.environ.get("RTSSA_ARCH", "gfx950")
 
-HIP_SOURCES = ["kernels_thread.hip", "kernels_group.hip", "kernels_subwave.hip", "kernels_lazy.hip",
-               "kernels_misc.hip", "noalloc.hip"]
+HIP_SOURCES = ["kernels_thread.hip", "kernels_group.hip", "kernels_group_lds.hip",
+               "kernels_subwave.hip", "kernels_lazy.hip", "kernels_misc.hip", "noalloc.hip"]
 CPP_SOURCES = ["api.cpp", "network.cpp", "batch.cpp", "host_shim.cpp"]
 
 

@@ -87,6 +87,10 @@ int rt_launch_class(int mapping, int max_M, int max_N, int max_nu, const rt_clas
             return rt_fail(RTSSA_E_INVALID, "group size must be 64, 128, 256, 512 or 1024");
         if (max_nu > 64) return rt_fail(RTSSA_E_UNSUPPORTED, "a reaction changes more than 64 species");
         *block_used = L;
+        // propensities in LDS and one barrier per firing where its LDS fits,
+        // else every channel's state in registers
+        if (rt_group_lds_kernel_for(max_M, max_N, L, C.has_schedule != 0))
+            return rt_launch_group_lds(max_M, max_N, C, L, grid, stream, grid_used);
         return rt_launch_group(max_M, max_N, max_M, C, L, grid, stream, grid_used);
     }
     return rt_fail(RTSSA_E_INVALID, "unknown mapping");
@@ -166,6 +170,26 @@ void rt_fill_stats(rtssa_stats* stats, const rt_ws& h)
     for (int q = 0; q < 4; ++q) stats->status_count[q] += h.status_count[q];
 }
 
+
+int rt_run_rows(const rtssa_network* net, const rtssa_options& o)
+{
+    if (o.method == RTSSA_METHOD_LAZY || o.method == RTSSA_METHOD_DIRECT_TREE) return 1;
+    if (o.method != RTSSA_METHOD_RANDOM_TIME) return 0;
+    const int mapping = o.mapping == RTSSA_MAP_AUTO ? rt_auto_mapping(net) : o.mapping;
+    return mapping == RTSSA_MAP_WORKGROUP && net->M > 0 ? 2 : 0;
+}
+
+bool rt_rows_ready(const rtssa_network* net, int rows)
+{
+    return rows == 0 || (net->lazy_block && (rows < 2 || net->group_block));
+}
+
+int rt_rows_prepare(rtssa_network* net, int rows)
+{
+    if (rows >= 2) return rt_group_rows_prepare(net);
+    if (rows == 1) return rt_lazy_prepare(net);
+    return RTSSA_OK;
+}
 
 int rt_check_method(const rtssa_network* net, const rtssa_options& o, bool want_T,
                            bool want_tie)
@@ -250,10 +274,8 @@ extern "C" int rtssa_workspace_size(const rtssa_network* net, int64_t R, const r
     if (opt) o = *opt;
     int rc = rt_check_method(net, o, false, false);
     if (rc) return rc;
-    if (o.method == RTSSA_METHOD_LAZY || o.method == RTSSA_METHOD_DIRECT_TREE) {
-        rc = rt_lazy_prepare(const_cast<rtssa_network*>(net));
-        if (rc) return rc;
-    }
+    rc = rt_rows_prepare(const_cast<rtssa_network*>(net), rt_run_rows(net, o));
+    if (rc) return rc;
     int lazy_grid = 0;
     return rt_run_workspace(net, R, o, 0, bytes, &lazy_grid);
 }
@@ -351,12 +373,12 @@ int rt_simulate_checks(const rtssa_network* net, const int32_t* x0, int32_t x0_p
     if (rc) return rc;
     rc = rt_check_method(net, o, T_out != nullptr, tie_step != nullptr);
     if (rc) return rc;
-    const bool wave_tree = o.method == RTSSA_METHOD_LAZY || o.method == RTSSA_METHOD_DIRECT_TREE;
-    if (wave_tree && R > 0) {
-        if (!may_build_rows && !net->lazy_block)
-            return rt_fail(RTSSA_E_INVALID, "the tree methods need the network's rows built "
-                                            "first (rtssa_workspace_size)");
-        rc = rt_lazy_prepare(const_cast<rtssa_network*>(net));
+    const int rows = rt_run_rows(net, o);
+    if (rows && R > 0) {
+        if (!may_build_rows && !rt_rows_ready(net, rows))
+            return rt_fail(RTSSA_E_INVALID, "the tree methods and the workgroup mapping need the "
+                                            "network's rows built first (rtssa_workspace_size)");
+        rc = rt_rows_prepare(const_cast<rtssa_network*>(net), rows);
         if (rc) return rc;
     }
     return RTSSA_OK;

@@ -168,8 +168,16 @@ static int batch_create(const rtssa_batch_item* items, int32_t count, const rtss
         }
     }
     std::map<class_key, std::vector<int>> groups;
-    for (int i = 0; i < count; ++i)
-        if (items[i].R > 0) groups[classify(items[i].net, items[i].method, plan, o)].push_back(i);
+    for (int i = 0; i < count; ++i) {
+        if (items[i].R <= 0) continue;
+        const class_key key = classify(items[i].net, items[i].method, plan, o);
+        if (key.mapping == RTSSA_MAP_WORKGROUP && key.method == RTSSA_METHOD_RANDOM_TIME) {
+            // the workgroup kernels read the network's fixed-stride records
+            const int rc = rt_group_rows_prepare(const_cast<rtssa_network*>(items[i].net));
+            if (rc) return rt_fail(rc, "item " + std::to_string(i) + ": " + rtssa_last_error());
+        }
+        groups[key].push_back(i);
+    }
 
     rtssa_batch* B = new rtssa_batch();
     B->items.assign(items, items + count);
@@ -397,6 +405,18 @@ extern "C" int rtssa_batch_info(const rtssa_batch* B, int32_t cls, int32_t* mapp
     if (n_items) *n_items = (int32_t)c.members.size();
     if (trajectories) *trajectories = c.units;
     if (max_M) *max_M = c.max_M;
+    return RTSSA_OK;
+}
+
+extern "C" int rtssa_batch_class_items(const rtssa_batch* B, int32_t cls, int32_t* items,
+                                       int32_t capacity, int32_t* count)
+{
+    if (!B || !count) return rt_fail(RTSSA_E_INVALID, "batch and count are required");
+    if (cls < 0 || cls >= (int)B->classes.size()) return rt_fail(RTSSA_E_INVALID, "no such class");
+    const auto& m = B->classes[cls].members;
+    *count = (int32_t)m.size();
+    if (items)
+        for (int32_t i = 0; i < std::min<int32_t>(capacity, (int32_t)m.size()); ++i) items[i] = m[i];
     return RTSSA_OK;
 }
 

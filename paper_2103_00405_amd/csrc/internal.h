@@ -46,6 +46,13 @@ struct rt_net_dev {
     const int32_t* touch_more;
     const int2* nu_fixed;
     int32_t nu_stride;
+    // workgroup mapping, fixed-stride dependency records (built on first
+    // use): grow[mu*64 + q] = (k, react[k].x, react[k].y, w) for q = 0 (k = mu,
+    // w = the number of channels of D(mu) other than mu) and q >= 1 (the q-th
+    // other channel, k = -1 past the end; q = 1: w = the CSR position of the
+    // 64th other channel, dep_ptr[mu+1] if none); growc[mu*64 + q] = c_k
+    const int4* grow;
+    const double* growc;
 };
 
 struct rtssa_network {
@@ -59,6 +66,7 @@ struct rtssa_network {
     void* dev_block = nullptr;  // one allocation holding every device table
     void* sched_block = nullptr;  // device copy of the rate schedule (times, rates)
     void* lazy_block = nullptr;   // the lazy form's fixed-stride rows
+    void* group_block = nullptr;  // the workgroup mapping's dependency records
     int32_t batch_refs = 0;       // batch items holding this network's device pointers
     rt_net_dev dev{};
 };
@@ -176,6 +184,19 @@ bool rt_group_supported(int M, int L);
 size_t rt_group_lds_bytes(int N, int M, int L);
 int rt_launch_subwave(int max_M, const rt_class_dev& C, int L, int grid, hipStream_t stream,
                       int* grid_used);
+// the workgroup mapping with the propensities in LDS (kernels_group_lds.hip):
+// the kernel for a class, or nullptr when its LDS does not fit; it reads the
+// network's fixed-stride rows (rt_lazy_prepare), which every item must have
+const void* rt_group_lds_kernel_for(int M, int max_N, int L, bool sched);
+size_t rt_group_lds2_bytes(int N, int L, int S);
+int rt_launch_group_lds(int M, int max_N, const rt_class_dev& C, int L, int grid,
+                        hipStream_t stream, int* grid_used);
+// the fixed-stride rows a run of this network with these options reads:
+// 0 none, 1 the lazy form's rows (tree methods), 2 those and the workgroup
+// mapping's dependency records (random-time workgroup mapping)
+int rt_run_rows(const rtssa_network* net, const rtssa_options& o);
+bool rt_rows_ready(const rtssa_network* net, int rows);
+int rt_rows_prepare(rtssa_network* net, int rows);
 // the lazy form (one wavefront per trajectory, LDS tree)
 // workspace: NULL to allocate it stream-ordered for this launch, else at
 // least rt_lazy_workspace_bytes(grid, max_M) bytes for the grid that
@@ -191,6 +212,8 @@ int rt_launch_dmtree(const rt_class_dev& C, int max_N, int max_M, int grid, int6
                      hipStream_t stream, int* grid_used);
 // builds and uploads the lazy form's rows of a network once (network.cpp)
 int rt_lazy_prepare(rtssa_network* net);
+// the same plus the workgroup mapping's dependency records (network.cpp)
+int rt_group_rows_prepare(rtssa_network* net);
 int rt_subwave_slots(int M, int L);
 int rt_subwave_lanes(int M);
 

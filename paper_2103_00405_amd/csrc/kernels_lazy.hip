@@ -129,21 +129,10 @@ __device__ __forceinline__ void lazy_store(const lazy_tree& tr, int l, int j, co
     tr.kk[l][j] = v.k;
 }
 
-__device__ __forceinline__ double lazy_min_f64(double a, double b) { return b < a ? b : a; }
+__device__ __forceinline__ double lazy_min_f64(double a, double b) { return rt_min_sel(a, b); }
 
 // Smallest value over the wavefront.
-__device__ __forceinline__ double lazy_wave_min(double v)
-{
-    v = lazy_min_f64(v, rt_dpp_f64<0xB1>(v));            // quad_perm [1,0,3,2]
-    v = lazy_min_f64(v, rt_dpp_f64<0x4E>(v));            // quad_perm [2,3,0,1]
-    v = lazy_min_f64(v, rt_dpp_f64<0x141>(v));           // row_half_mirror
-    v = lazy_min_f64(v, rt_dpp_f64<0x140>(v));           // row_mirror
-    double q;
-    double p = rt_swap_f64<16>(v, q);
-    v = lazy_min_f64(p, q);
-    p = rt_swap_f64<32>(v, q);
-    return lazy_min_f64(p, q);
-}
+__device__ __forceinline__ double lazy_wave_min(double v) { return rt_wave_min_f64(v); }
 
 // The smaller of two entries from anywhere in the wavefront; on equal values
 // the lower channel (the order of a cross-lane reduction is not channel order).

@@ -167,6 +167,28 @@ __global__ __launch_bounds__(L) void rt_debug_sel_group_kernel(
     if (tid == 0) debug_sel_store(r, loc, mu, v1, v2, near);
 }
 
+// workgroup mapping with the propensities in LDS: the lane's two smallest
+// values, then the selection in two single-value reductions
+template <int L>
+__global__ __launch_bounds__(L) void rt_debug_sel_group_lds_kernel(
+    const double* v, int32_t M, int64_t count, int32_t* mu, double* v1, double* v2, uint8_t* near)
+{
+    __shared__ rt_sel_part part[16];
+    const int tid = threadIdx.x;
+    const int64_t r = blockIdx.x;
+    double d1 = __builtin_inf(), d2 = __builtin_inf();
+    int ks = 0;
+    for (int s = 0; tid + s * L < M; ++s) {
+        const double d = v[r * M + tid + s * L];
+        const bool lt = d < d1;
+        d2 = fmin(d2, fmax(d1, d));
+        d1 = fmin(d1, d);
+        ks = lt ? s : ks;
+    }
+    const rt_min2 sel = rt_select_group<L>(d1, d2, tid + ks * L, part);
+    if (tid == 0) debug_sel_store(r, sel, mu, v1, v2, near);
+}
+
 typedef void (*debug_sel_t)(const double*, int32_t, int64_t, int32_t*, double*, double*, uint8_t*);
 
 }  // namespace
@@ -200,6 +222,17 @@ int rt_launch_debug_select(const double* v, int32_t M, int64_t count, int32_t ma
             case 256: k = rt_debug_sel_group_kernel<256>; break;
             case 512: k = rt_debug_sel_group_kernel<512>; break;
             case 1024: k = rt_debug_sel_group_kernel<1024>; break;
+            default: return rt_fail(RTSSA_E_INVALID, "workgroup size must be 64..1024, a power of 2");
+        }
+        block = lanes;
+        blocks = count;
+    } else if (mapping == RTSSA_DEBUG_MAP_WORKGROUP_LDS) {
+        switch (lanes) {
+            case 64: k = rt_debug_sel_group_lds_kernel<64>; break;
+            case 128: k = rt_debug_sel_group_lds_kernel<128>; break;
+            case 256: k = rt_debug_sel_group_lds_kernel<256>; break;
+            case 512: k = rt_debug_sel_group_lds_kernel<512>; break;
+            case 1024: k = rt_debug_sel_group_lds_kernel<1024>; break;
             default: return rt_fail(RTSSA_E_INVALID, "workgroup size must be 64..1024, a power of 2");
         }
         block = lanes;

@@ -180,13 +180,14 @@ extern "C" int rtssa_network_create(int32_t N, int32_t M, const int32_t* react_p
 extern "C" int rtssa_network_destroy(rtssa_network* net)
 {
     if (!net) return RTSSA_OK;
-    if (net->dev_block || net->sched_block || net->lazy_block) {
+    if (net->dev_block || net->sched_block || net->lazy_block || net->group_block) {
         int cur = -1;
         hipGetDevice(&cur);
         if (net->device >= 0 && cur != net->device) hipSetDevice(net->device);
         if (net->dev_block) hipFree(net->dev_block);
         if (net->sched_block) hipFree(net->sched_block);
         if (net->lazy_block) hipFree(net->lazy_block);
+        if (net->group_block) hipFree(net->group_block);
         if (cur >= 0 && cur != net->device) hipSetDevice(cur);
     }
     delete net;
@@ -247,6 +248,73 @@ int rt_lazy_prepare(rtssa_network* net)
     return RTSSA_OK;
 }
 
+// The rates of the dependency records, in record order (c of the record's
+// channel, 0 past a row's end).
+static void group_record_rates(const rtssa_network* net, std::vector<double>& rc_c)
+{
+    const int M = net->M;
+    rc_c.assign((size_t)std::max(M, 1) * 64, 0.0);
+    for (int mu = 0; mu < M; ++mu) {
+        double* rowc = rc_c.data() + (size_t)mu * 64;
+        rowc[0] = net->c[mu];
+        int n_other = 0;
+        for (int q = net->dep_ptr[mu]; q < net->dep_ptr[mu + 1]; ++q) {
+            const int k = net->dep_idx[q];
+            if (k == mu) continue;
+            if (n_other < 63) rowc[1 + n_other] = net->c[k];
+            ++n_other;
+        }
+    }
+}
+
+int rt_group_rows_prepare(rtssa_network* net)
+{
+    int rc = rt_lazy_prepare(net);
+    if (rc || net->group_block) return rc;
+    const int M = net->M;
+    const size_t rows = (size_t)std::max(M, 1);
+    std::vector<int4> rec(rows * 64, make_int4(-1, 0, 0, 0));
+    std::vector<double> rc_c;
+    group_record_rates(net, rc_c);
+    for (int mu = 0; mu < M; ++mu) {
+        int4* row = rec.data() + (size_t)mu * 64;
+        row[0] = make_int4(mu, net->react[mu].x, net->react[mu].y, 0);
+        int n_other = 0, more = net->dep_ptr[mu + 1];
+        for (int q = net->dep_ptr[mu]; q < net->dep_ptr[mu + 1]; ++q) {
+            const int k = net->dep_idx[q];
+            if (k == mu) continue;
+            if (n_other < 63) row[1 + n_other] = make_int4(k, net->react[k].x, net->react[k].y, 0);
+            else if (n_other == 63) more = q;
+            ++n_other;
+        }
+        row[0].w = n_other;
+        row[1].w = more;
+    }
+    const size_t rb = rec.size() * sizeof(int4), cb = rc_c.size() * sizeof(double);
+    const size_t coff = (rb + 255) / 256 * 256;
+    struct device_guard {
+        int prev = -1;
+        explicit device_guard(int d)
+        {
+            if (d >= 0 && hipGetDevice(&prev) == hipSuccess && prev != d) hipSetDevice(d);
+            else prev = -1;
+        }
+        ~device_guard() { if (prev >= 0) hipSetDevice(prev); }
+    } guard(net->device);
+    void* blk = nullptr;
+    if (hipMalloc(&blk, coff + cb) != hipSuccess)
+        return rt_fail(RTSSA_E_NOMEM, "device allocation of the dependency records failed");
+    if (hipMemcpy(blk, rec.data(), rb, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy((char*)blk + coff, rc_c.data(), cb, hipMemcpyHostToDevice) != hipSuccess) {
+        hipFree(blk);
+        return rt_fail(RTSSA_E_HIP, "copy of the dependency records failed");
+    }
+    net->group_block = blk;
+    net->dev.grow = (const int4*)blk;
+    net->dev.growc = (const double*)((char*)blk + coff);
+    return RTSSA_OK;
+}
+
 extern "C" int rtssa_network_set_rates(rtssa_network* net, const double* c)
 {
     if (!net || (!c && net->M > 0)) return rt_fail(RTSSA_E_INVALID, "NULL argument");
@@ -259,6 +327,15 @@ extern "C" int rtssa_network_set_rates(rtssa_network* net, const double* c)
         hipMemcpy((void*)net->dev.c, net->c.data(), sizeof(double) * net->M,
                   hipMemcpyHostToDevice) != hipSuccess)
         return rt_fail(RTSSA_E_HIP, "copy of rates failed");
+    if (net->group_block) {
+        // the dependency records carry each channel's rate: rewrite those in
+        // place (their address may be held by a batch)
+        std::vector<double> rc_c;
+        group_record_rates(net, rc_c);
+        if (hipMemcpy((void*)net->dev.growc, rc_c.data(), rc_c.size() * sizeof(double),
+                      hipMemcpyHostToDevice) != hipSuccess)
+            return rt_fail(RTSSA_E_HIP, "copy of rates failed");
+    }
     return RTSSA_OK;
 }
 

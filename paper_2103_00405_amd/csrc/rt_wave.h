@@ -151,3 +151,101 @@ __device__ __forceinline__ rt_min2 rt_min2_group_allreduce(rt_min2 v, rt_min2* w
     if constexpr (W > 1) v = rt_min2_allreduce<W>(wave_min[threadIdx.x & (W - 1)]);
     return v;
 }
+
+// ---------------------------------------------------------------------
+// Selection in two single-value reductions, for a workgroup whose lanes hold
+// lane-local (d1, d2, channel): d1 <= d2 the two smallest gaps of the lane
+// (>= 0 or +inf, never NaN), channel the lowest one holding d1.  The
+// smallest gap and its channel are exact; the second smallest is carried
+// only where it can decide the near-tie rule: a part's d2 is exact when it
+// lies within reach of the part's d1 (d2 <= d1 + 2 RN(1e-12 d1)), else +inf.
+// The returned d2 is then exact whenever the near-tie test can hold, and
+// otherwise no smaller than the true second minimum and out of reach, so
+// rt_near_tie(d1, d2) decides exactly as on the true values.
+
+__device__ __forceinline__ double rt_min_sel(double a, double b) { return b < a ? b : a; }
+
+// Smallest value over the wavefront, in every lane.
+__device__ __forceinline__ double rt_wave_min_f64(double v)
+{
+    v = rt_min_sel(v, rt_dpp_f64<0xB1>(v));              // quad_perm [1,0,3,2]
+    v = rt_min_sel(v, rt_dpp_f64<0x4E>(v));              // quad_perm [2,3,0,1]
+    v = rt_min_sel(v, rt_dpp_f64<0x141>(v));             // row_half_mirror
+    v = rt_min_sel(v, rt_dpp_f64<0x140>(v));             // row_mirror
+    double q;
+    double p = rt_swap_f64<16>(v, q);
+    v = rt_min_sel(p, q);
+    p = rt_swap_f64<32>(v, q);
+    return rt_min_sel(p, q);
+}
+
+struct rt_sel_part {
+    double d1, d2;
+    int32_t k, pad;
+};
+
+// The wavefront's part (every lane of the wavefront active).
+__device__ __forceinline__ rt_sel_part rt_select_wave(double d1, double d2, int32_t ch)
+{
+    const int lane = (int)(threadIdx.x & 63u);
+    rt_sel_part p;
+    p.d1 = rt_wave_min_f64(d1);
+    p.pad = 0;
+    const unsigned long long own = __ballot(d1 == p.d1);
+    if (__builtin_expect(__popcll(own) == 1, 1)) {
+        const int ol = __ffsll((long long)own) - 1;
+        p.k = __builtin_amdgcn_readlane(ch, ol);
+        // candidates for the second smallest: the owner's second, every
+        // other lane's smallest; reduced only when one is within reach
+        const double cand = lane == ol ? d2 : d1;
+        const double reach = p.d1 + 2.0 * (1e-12 * p.d1);
+        p.d2 = __builtin_inf();
+        if (p.d1 != __builtin_inf() && __ballot(cand <= reach) != 0ull)
+            p.d2 = rt_wave_min_f64(cand);
+    } else {
+        // several lanes hold the smallest value (or every value is +inf): the
+        // lowest channel among them; the second smallest equals the smallest
+        unsigned long long m = own;
+        int32_t k = 0x7FFFFFFF;
+        while (m) {
+            const int l = __ffsll((long long)m) - 1;
+            k = min(k, (int32_t)__builtin_amdgcn_readlane(ch, l));
+            m &= m - 1ull;
+        }
+        p.k = k;
+        p.d2 = p.d1;
+    }
+    return p;
+}
+
+// The workgroup's selection (L = 64 W threads, all reaching the one barrier
+// inside; part: W entries of LDS, not read by another selection until every
+// thread has passed this one's barrier).  Every thread returns the same.
+template <int L>
+__device__ __forceinline__ rt_min2 rt_select_group(double d1, double d2, int32_t ch,
+                                                   rt_sel_part* part)
+{
+    constexpr int W = L / 64;
+    const rt_sel_part p = rt_select_wave(d1, d2, ch);
+    if constexpr (W == 1) {
+        __syncthreads();
+        return rt_min2{p.d1, p.d2, p.k};
+    } else {
+        if ((threadIdx.x & 63u) == 0) part[threadIdx.x >> 6] = p;
+        __syncthreads();
+        // merge the parts in wavefront order; a part that loses gives its
+        // smallest value to the candidates for the second smallest
+        rt_sel_part b = part[0];
+        double others = __builtin_inf();
+#pragma unroll
+        for (int w = 1; w < W; ++w) {
+            const rt_sel_part q = part[w];
+            const bool better = q.d1 < b.d1 || (q.d1 == b.d1 && q.k < b.k);
+            others = rt_min_sel(others, better ? b.d1 : q.d1);
+            b.d1 = better ? q.d1 : b.d1;
+            b.d2 = better ? q.d2 : b.d2;
+            b.k = better ? q.k : b.k;
+        }
+        return rt_min2{b.d1, rt_min_sel(b.d2, others), b.k};
+    }
+}

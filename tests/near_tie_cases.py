@@ -98,3 +98,43 @@ def exact_first_gaps(P, c, h):
         inv = float(1 / Fraction(a))
         out.append(float(Fraction(Pk) * Fraction(inv)))
     return out
+
+
+def plant_first_firing_clamp(spec, x0, seed, traj, net_id, i, j):
+    """Copy of spec with c_i, c_j set so that trajectory ``traj`` starts with
+    an exact tie between channels i < j (i fires, the lower channel) and the
+    unfired channel j's internal time then overshoots its next firing time:
+    RN(a_j gap) > P_j, so that its next raw gap is negative and is clamped to
+    0 (counted).  Returns (spec, gap)."""
+    assert 0 <= i < j < int(spec.M)
+    h = first_h(spec, x0)
+    assert h[i] > 0 and h[j] > 0, "both channels must be able to fire at x0"
+    P = [oracle.exp1(seed, traj, net_id, k, 0) for k in range(int(spec.M))]
+    c = np.array(spec.c, dtype=np.float64).copy()
+    others = [first_gap(P[k], c[k], h[k]) for k in range(int(spec.M)) if k not in (i, j)]
+    finite = [g for g in others if g < math.inf]
+    target = (min(finite) if finite else 1.0) / 8.0
+    ci = P[i] / target / float(h[i])
+    for _ in range(4096):                     # neighbours of c_i
+        gi = first_gap(P[i], ci, h[i])
+        # a rate of j whose gap equals gi (a larger rate gives a smaller gap)
+        cand = P[j] / gi / float(h[j])
+        for _ in range(64):
+            gj = first_gap(P[j], cand, h[j])
+            if gj == gi:
+                break
+            cand = math.nextafter(cand, math.inf if gj > gi else 0.0)
+        if first_gap(P[j], cand, h[j]) == gi:
+            # every neighbouring rate with the same gap, on both sides
+            lo = cand
+            while first_gap(P[j], math.nextafter(lo, 0.0), h[j]) == gi:
+                lo = math.nextafter(lo, 0.0)
+            cj = lo
+            while first_gap(P[j], cj, h[j]) == gi:
+                if (cj * float(h[j])) * gi > P[j]:
+                    c[i] = ci
+                    c[j] = cj
+                    return W.with_rates(spec, c), gi
+                cj = math.nextafter(cj, math.inf)
+        ci = math.nextafter(ci, math.inf)
+    raise AssertionError("no rates found for a planted clamp")

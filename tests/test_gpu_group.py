@@ -167,3 +167,30 @@ def test_large_random_network_full_trajectories():
         assert np.array_equal(_np(g["n"][sl]).view(np.uint32), ref["n"])
         assert np.array_equal(_np(g["T"][sl]).view(np.uint64), ref["T"].view(np.uint64))
         assert np.array_equal(_np(g["seq_hash"][sl]).view(np.uint64), ref["seq_hash"])
+
+
+def test_workgroup_mapping_sees_new_rates():
+    """The workgroup kernel reads each dependent channel's rate from the
+    network's dependency records: after rtssa_network_set_rates a run must
+    use the new rates (oracle on the new rates, bit for bit), in a single run
+    and in a batch created before the change."""
+    api = _api()
+    spec, x0 = _net(150, 700, 41)
+    net = api.Network(spec)
+    t_end = _t_end_for(spec, x0, 800)
+    grid = np.linspace(0.0, t_end, 5)
+    g0 = api.simulate(net, x0, t_end, grid, 24, seed=3, with_hash=True, mapping=3)
+    assert g0["stats"]["mapping"] == 3
+    b = api.Batch([dict(net=net, x0=x0, t_end=t_end, sample_t=grid, R=24, net_id=0)],
+                  with_hash=True)
+    c2 = np.asarray(spec.c) * np.exp(np.random.default_rng(5).uniform(-1.0, 1.0, spec.M))
+    net.set_rates(c2)
+    spec2 = W.with_rates(spec, c2)
+    ref = oracle.simulate(spec2, x0, t_end, grid, 3, 24)
+    g1 = api.simulate(net, x0, t_end, grid, 24, seed=3, with_hash=True, mapping=3)
+    torch.cuda.synchronize()
+    _assert_same(g1, ref)
+    b.run(seed=3)
+    torch.cuda.synchronize()
+    _assert_same(b.outputs[0], ref, stats=False)
+    assert not np.array_equal(_np(g0["n"]), _np(g1["n"]))

@@ -22,7 +22,8 @@ import pytest
 import oracle
 from paper_2103_00405_amd import workloads as W
 
-from near_tie_cases import exact_first_gaps, first_h, plant_first_firing_tie
+from near_tie_cases import (exact_first_gaps, first_h, plant_first_firing_clamp,
+                             plant_first_firing_tie)
 
 INF = math.inf
 T12 = 1e-12        # the binary64 nearest to 10^-12
@@ -188,6 +189,30 @@ def test_planted_tie_counted_at_first_firing(M, i, j, exact):
         o2 = oracle.simulate(spec, x0, gap * 1.5, [gap * 1.5], seed, 2, net_id=net_id,
                              traj_offset=traj + 1, lazy=lazy)
         assert (o2["tie_step"] == oracle.TIE_NONE).all()
+
+
+@pytest.mark.parametrize("M,i,j", [(3, 0, 2), (8, 1, 6), (300, 255, 256)])
+def test_planted_clamp_counted_at_second_firing(M, i, j):
+    """An exact first-firing tie in which the unfired channel j overshoots:
+    with exact rationals, RN(a_j gap) > P_j; the oracle fires i, then j with
+    a zero gap (its negative raw gap clamped), counts one clamp, and time
+    does not advance at the second firing."""
+    seed, traj, net_id = 5, 3, 7
+    rng = np.random.default_rng(M * 31 + i)
+    spec = W.random_network(max(2, M // 2), M, rng, order_p=(0.3, 0.7, 0.0), logc=(-1.0, 0.5))
+    x0 = rng.integers(5, 60, size=spec.N).astype(np.int32)
+    spec, gap = plant_first_firing_clamp(spec, x0, seed, traj, net_id, i, j)
+    h = first_h(spec, x0)
+    P = [oracle.exp1(seed, traj, net_id, k, 0) for k in range(M)]
+    g = exact_first_gaps(P, spec.c, h)
+    assert g[i] == g[j] == gap and min(g) == gap
+    a_j = float(Fraction(spec.c[j]) * Fraction(float(h[j])))
+    assert float(Fraction(a_j) * Fraction(gap)) > P[j]          # T_j after firing i
+    o = oracle.simulate(spec, x0, 1.0, [], seed, 1, net_id=net_id, traj_offset=traj,
+                        max_firings=2)
+    assert o["n"][0, i] == 1 and o["n"][0, j] == 1 and o["n"][0].sum() == 2
+    assert o["stats"]["clamps"] == 1 and o["tie_step"][0] == 0
+    assert o["t_last"][0] == gap
 
 
 def pin_failures(L):
