@@ -430,7 +430,7 @@ def bench_gradient(api, W, reps=3):
 
 
 BATCH_MAX_FIRINGS = 100_000     # per trajectory; 5x the 2e4 the t_end is set for
-LAZY_ABOVE_M = 512              # batched networks above this many channels run the lazy form
+LAZY_ABOVE_M = 256              # batched networks above this many channels run the lazy form
 
 
 def batch_jobs(api, wl):

@@ -363,9 +363,12 @@ int rtssa_batch_run(rtssa_batch* batch, uint64_t seed, int32_t use_graph, rtssa_
                     rtssa_stats* stats);
 /* Items may choose their method: RANDOM_TIME items are classed by mapping as
  * above; LAZY and DIRECT_TREE items (each with the same conditions as in
- * rtssa_simulate) form classes of their own, run one wavefront per trajectory
- * (reported as mapping RTSSA_MAP_WAVE, 64 lanes); the lazy form's channel
- * workspace is allocated by rtssa_batch_create.  opt->method must be 0. */
+ * rtssa_simulate) form classes of their own, one per method and power-of-two
+ * channel range (M <= 64, 65..128, 129..256, ...: each class's LDS tree is
+ * sized for its own networks), run one wavefront per trajectory (reported as
+ * mapping RTSSA_MAP_WAVE, 64 lanes) and are launched first, largest range
+ * first; the lazy form's channel workspace is allocated by
+ * rtssa_batch_create.  opt->method must be 0. */
 /* cls < 0: *n_items receives the number of classes; else the class's
  * mapping, lanes per trajectory (1 for the thread mapping), items,
  * trajectories and largest channel count. */

@@ -26,16 +26,18 @@ namespace {
 
 struct class_key {
     int mapping;    // RTSSA_MAP_*
-    int a, b;       // thread: padded (M, N); wave / workgroup: lanes per trajectory, 0
+    int a, b;       // thread: padded (M, N); wave / workgroup: lanes per trajectory, 0;
+                    // tree methods: 64, the power-of-two channel range
     int method;     // RTSSA_METHOD_*: the tree methods have classes of their own
     // Class order is launch order.  The tree methods' classes (long, one
     // wavefront per trajectory) go first: launched after the others they
     // start late and set the step time (2.63 s against 3.25 s per step on
-    // 4096 random networks with the lazy form above 512 channels); the
-    // random-time classes follow, lightest first.
+    // 4096 random networks with the lazy form above 512 channels), largest
+    // channel range first; the random-time classes follow, lightest first.
     bool operator<(const class_key& o) const
     {
         if (method != o.method) return method > o.method;
+        if (method != RTSSA_METHOD_RANDOM_TIME) return b > o.b;
         return mapping != o.mapping ? mapping < o.mapping : (a != o.a ? a < o.a : b < o.b);
     }
 };
@@ -70,10 +72,20 @@ int plan_lookup(const std::vector<plan_entry>& plan, int mapping, int M)
     return 0;
 }
 
+// The tree methods' classes: one per power-of-two channel range (at least 64),
+// so that each class's LDS tree, and with it the number of wavefronts a CU
+// holds, is sized for its own networks rather than the largest of the batch.
+int tree_range(int M)
+{
+    int r = 64;
+    while (r < M) r <<= 1;
+    return r;
+}
+
 class_key classify(const rtssa_network* net, int method, const std::vector<plan_entry>& plan,
                    const rtssa_options& o)
 {
-    if (method != RTSSA_METHOD_RANDOM_TIME) return {RTSSA_MAP_WAVE, 64, 0, method};
+    if (method != RTSSA_METHOD_RANDOM_TIME) return {RTSSA_MAP_WAVE, 64, tree_range(net->M), method};
     int mapping = o.mapping ? o.mapping : rt_auto_mapping(net);
     if (mapping == RTSSA_MAP_THREAD && rt_thread_supported(net->M, net->N))
         return {RTSSA_MAP_THREAD, pad_thread_m(net->M), pad_thread_n(net->N), 0};

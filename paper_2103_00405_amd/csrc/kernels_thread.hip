@@ -201,12 +201,26 @@ __global__ __launch_bounds__(256, thread_min_waves(MT, NT, METHOD, SCHED)) void 
             double d1 = __builtin_inf(), d2 = __builtin_inf();
             int mu = 0;
             if constexpr (METHOD == RTSSA_METHOD_RANDOM_TIME) {
+                // A frozen channel (a_k = 0, 1/a_k = +inf) gives +inf while
+                // P_k > T_k, so the raw gaps are the gaps unless one is negative
+                // (clamped to 0) or a frozen channel has P_k <= T_k (NaN, -inf):
+                // then, rarely, the wavefront takes the exact form.
                 rt_min2 sel{__builtin_inf(), __builtin_inf(), 0};
+                bool bad = false;
 #pragma unroll
                 for (int k = 0; k < MT; ++k) {
                     const double raw = (Pk[k] - T[k]) * inv[k];
-                    const double d = a[k] == 0.0 ? __builtin_inf() : fmax(raw, 0.0);
-                    rt_min2_push(sel, d, k);
+                    bad = bad || !(raw >= 0.0);
+                    rt_min2_push(sel, raw, k);
+                }
+                if (__builtin_expect(__ballot(bad) != 0ull, 0)) {
+                    sel = rt_min2{__builtin_inf(), __builtin_inf(), 0};
+#pragma unroll
+                    for (int k = 0; k < MT; ++k) {
+                        const double raw = (Pk[k] - T[k]) * inv[k];
+                        const double d = a[k] == 0.0 ? __builtin_inf() : fmax(raw, 0.0);
+                        rt_min2_push(sel, d, k);
+                    }
                 }
                 d1 = sel.d1;
                 d2 = sel.d2;
