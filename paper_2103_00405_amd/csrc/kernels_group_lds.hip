@@ -28,9 +28,10 @@
 // event needs no second barrier.  The draws E(k, n + 1) a channel will need
 // are kept per slot; after a firing the slot's next draw is refilled later,
 // for many slots of a wavefront at once (one Philox4x32-10 block and one
-// logarithm per lane), and drawn on the spot only when the channel fires
-// again before its refill.  Every value is the one of the contract: the
-// schedule of the refills changes no result.
+// logarithm per lane), at once when the channel fires again before its
+// refill.  Refills run between issuing mu's row loads and using them.  Every
+// value is the one of the contract: the schedule of the refills changes no
+// result.
 //
 // With piecewise-constant rates (Eq. 28), a next firing past the next rate
 // breakpoint b instead runs every clock to b at the old rates and recomputes
@@ -61,16 +62,19 @@ __global__ __launch_bounds__(L, g2_min_waves(S)) void rt_group_lds_kernel(rt_cla
 {
     constexpr int W = L / 64;
     constexpr int LOG2L = __builtin_ctz(L);
-    extern __shared__ __align__(16) double2 g2_lds[];
+    extern __shared__ __align__(16) double g2_lds[];
     __shared__ g2_shared sh;
     rt_ws* const ws = C.ws;
     const uint32_t key0 = ws->key0, key1 = ws->key1;
     const rt_cptr<int64_t> unit_start = rt_const(C.unit_start);
     const int64_t total = unit_start[C.count];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    double2* const ai = g2_lds;                                   // [L S] (a_k, 1/a_k)
+    // a_k and 1/a_k as two arrays, so that a wavefront reading either for its
+    // slots touches consecutive 8-byte words (no bank conflicts)
+    double* const pa = g2_lds;                                    // [L S] a_k
+    double* const pinv = g2_lds + L * S;                          // [L S] 1/a_k
     const int Npad = (C.max_N + 3) & ~3;
-    int32_t* const Xb = (int32_t*)(g2_lds + L * S);               // [2][Npad]
+    int32_t* const Xb = (int32_t*)(g2_lds + 2 * L * S);           // [2][Npad]
     uint32_t* sc = sh.log_scratch[wave];
 
     double T[S], P[S], En[S];
@@ -134,7 +138,8 @@ __global__ __launch_bounds__(L, g2_min_waves(S)) void rt_group_lds_kernel(rt_cla
             const double e0 = rt_neglog_wave(m0, false, &ws->slow_logs, sc);
             const double p1 = rt_neglog_wave(m1, false, &ws->slow_logs, sc);
             const double p0 = live ? e0 : __builtin_inf();
-            ai[k] = make_double2(an, in);
+            pa[k] = an;
+            pinv[k] = in;
 #pragma unroll
             for (int s = 0; s < S; ++s) {
                 P[s] = s == s1 ? p0 : P[s];
@@ -163,10 +168,9 @@ __global__ __launch_bounds__(L, g2_min_waves(S)) void rt_group_lds_kernel(rt_cla
             bool bad = false;
 #pragma unroll
             for (int s = 0; s < S; ++s) {
-                const double2 v = ai[tid + s * L];
-                const double raw = (P[s] - T[s]) * v.y;
+                const double raw = (P[s] - T[s]) * pinv[tid + s * L];
                 bad = bad || !(raw >= 0.0);
-                const bool lt = raw < d1;
+                const bool lt = raw < d1;          // the lower slot wins equal values
                 d2 = fmin(d2, fmax(d1, raw));
                 d1 = fmin(d1, raw);
                 ks = lt ? s : ks;
@@ -177,9 +181,8 @@ __global__ __launch_bounds__(L, g2_min_waves(S)) void rt_group_lds_kernel(rt_cla
                 ks = 0;
 #pragma unroll
                 for (int s = 0; s < S; ++s) {
-                    const double2 v = ai[tid + s * L];
-                    const double raw = (P[s] - T[s]) * v.y;
-                    const double d = v.x == 0.0 ? __builtin_inf() : fmax(raw, 0.0);
+                    const double raw = (P[s] - T[s]) * pinv[tid + s * L];
+                    const double d = pa[tid + s * L] == 0.0 ? __builtin_inf() : fmax(raw, 0.0);
                     const bool lt = d < d1;
                     d2 = fmin(d2, fmax(d1, d));
                     d1 = fmin(d1, d);
@@ -201,7 +204,7 @@ __global__ __launch_bounds__(L, g2_min_waves(S)) void rt_group_lds_kernel(rt_cla
                 // propensity takes the next piece's rates (Eq. 28 again)
                 const double db = b_next - t;
 #pragma unroll
-                for (int s = 0; s < S; ++s) T[s] = fma(ai[tid + s * L].x, db, T[s]);
+                for (int s = 0; s < S; ++s) T[s] = fma(pa[tid + s * L], db, T[s]);
                 t = b_next;
                 crate = rt_const(net.sched_c) + (size_t)piece * M;
                 ++piece;
@@ -211,7 +214,8 @@ __global__ __launch_bounds__(L, g2_min_waves(S)) void rt_group_lds_kernel(rt_cla
                     const int k = tid + s1 * L;
                     if (k < M) {
                         const double an = rt_propensity_mem(react[k], crate[k], Xc);
-                        ai[k] = make_double2(an, 1.0 / an);
+                        pa[k] = an;
+                        pinv[k] = 1.0 / an;
                     }
                 }
                 continue;
@@ -225,6 +229,28 @@ __global__ __launch_bounds__(L, g2_min_waves(S)) void rt_group_lds_kernel(rt_cla
             const int4 gr = grow[mu * 64 + lane];
             const double gc = growc[mu * 64 + lane];
             const int2 nv = nu_fixed[mu * nu_stride + min(lane, nu_stride - 1)];
+            // ---- draws, while the rows load: a wavefront refills one waiting
+            // slot per lane once enough lanes have one, and at once when it
+            // owns mu and mu's next draw E(mu, n_mu + 1) is still waiting (the
+            // owner lane then takes that slot)
+            const int owner = mu & (L - 1);
+            const int sm = mu >> LOG2L;                     // uniform slot of mu
+            const bool need = wave == (owner >> 6) &&
+                              __builtin_amdgcn_readlane((int)((pending >> sm) & 1u), owner & 63);
+            if (need || __popcll(__ballot(pending != 0u)) >= kRefillLanes) {
+                const bool has = pending != 0u;
+                const int s1 = (need && tid == owner) ? sm : (has ? __builtin_ctz(pending) : 0);
+                uint32_t n1 = 0u;
+#pragma unroll
+                for (int s = 0; s < S; ++s) n1 = s == s1 ? nk[s] : n1;
+                const uint64_t m = has ? rt_draw_m53(key0, key1, traj, net_id,
+                                                     (uint32_t)(tid + s1 * L), n1 + 1u)
+                                       : 0x1FFFFFFFFFFFFFull;
+                const double E = rt_neglog_wave(m, false, &ws->slow_logs, sc);
+#pragma unroll
+                for (int s = 0; s < S; ++s) En[s] = (has && s == s1) ? E : En[s];
+                pending &= ~(has ? 1u << s1 : 0u);
+            }
             const int n_other = __builtin_amdgcn_readlane(gr.w, 0);
             const int kd = gr.x;
             const bool mine = kd >= 0 && ((kd & (L - 1)) >> 6) == wave;
@@ -252,44 +278,27 @@ __global__ __launch_bounds__(L, g2_min_waves(S)) void rt_group_lds_kernel(rt_cla
             if (__ballot(!okl) != 0ull) { st = RTSSA_TRAJ_OVERFLOW; break; }
             // ---- internal clocks (Eq. 15), the fired channel's firing time and
             // next draw (Eq. 26)
-            const int owner = mu & (L - 1);
-            const int sm = mu >> LOG2L;                     // uniform slot of mu
             bool clamped = false;
             if (d1 == 0.0 && tid == owner) {
                 // a zero gap: was it clamped from a negative raw gap?
 #pragma unroll
                 for (int s = 0; s < S; ++s)
-                    if (s == sm) clamped = (P[s] - T[s]) * ai[mu].y < 0.0;
+                    if (s == sm) clamped = (P[s] - T[s]) * pinv[mu] < 0.0;
             }
             // (a_k as read by the pass: this wavefront writes its channels'
             // entries only below)
 #pragma unroll
-            for (int s = 0; s < S; ++s) T[s] = fma(ai[tid + s * L].x, d1, T[s]);
-            if (wave == (owner >> 6)) {
-                const int ol = owner & 63;
-                uint32_t nm = 0u, pbit = 0u;
-                double en = 0.0;
+            for (int s = 0; s < S; ++s) T[s] = fma(pa[tid + s * L], d1, T[s]);
+            if (tid == owner) {
 #pragma unroll
                 for (int s = 0; s < S; ++s)
-                    if (s == sm) { nm = nk[s]; pbit = (pending >> s) & 1u; en = En[s]; }
-                nm = (uint32_t)__builtin_amdgcn_readlane((int)nm, ol);
-                double E = en;
-                if (__builtin_amdgcn_readlane((int)pbit, ol)) {
-                    // fired again before its refill: draw it now
-                    E = rt_exp1_uniform(key0, key1, traj, net_id, (uint32_t)mu, nm + 1u,
-                                        &ws->slow_logs, sc);
-                }
-                if (tid == owner) {
-#pragma unroll
-                    for (int s = 0; s < S; ++s)
-                        if (s == sm) {
-                            T[s] = P[s];
-                            P[s] = P[s] + E;
-                            nk[s] = nm + 1u;
-                        }
-                    pending |= 1u << sm;
-                    if (clamped) atomicAdd(&ws->clamps, 1ull);
-                }
+                    if (s == sm) {
+                        T[s] = P[s];
+                        P[s] = P[s] + En[s];
+                        ++nk[s];
+                    }
+                pending |= 1u << sm;
+                if (clamped) atomicAdd(&ws->clamps, 1ull);
             }
             // ---- X + v_mu into the other buffer (wavefront 0): that buffer
             // holds X before the previous firing, so the previous firing's
@@ -313,7 +322,8 @@ __global__ __launch_bounds__(L, g2_min_waves(S)) void rt_group_lds_kernel(rt_cla
                 if (mine) {
                     const double an = rt_propensity((int)((uint32_t)rr.x >> 29),
                                                     rr.x & RT_SPECIES_MASK, rr.y, cr, xnew);
-                    ai[kd] = make_double2(an, 1.0 / an);
+                    pa[kd] = an;
+                    pinv[kd] = 1.0 / an;
                 }
                 if (n_other > 63) {
                     // the rest of D(mu) from its 64th other channel on
@@ -326,7 +336,8 @@ __global__ __launch_bounds__(L, g2_min_waves(S)) void rt_group_lds_kernel(rt_cla
                             const double an = rt_propensity((int)((uint32_t)r2.x >> 29),
                                                             r2.x & RT_SPECIES_MASK, r2.y,
                                                             crate[k2], xnew);
-                            ai[k2] = make_double2(an, 1.0 / an);
+                            pa[k2] = an;
+                            pinv[k2] = 1.0 / an;
                         }
                     }
                 }
@@ -335,22 +346,6 @@ __global__ __launch_bounds__(L, g2_min_waves(S)) void rt_group_lds_kernel(rt_cla
             t = t_new;
             hash = (hash ^ (unsigned long long)(uint32_t)mu) * kFnvPrime;
             if (fired >= C.max_firings) { st = RTSSA_TRAJ_MAX_FIRINGS; break; }
-            // ---- refills: once enough lanes have a slot waiting, every such
-            // lane computes the next draw of its lowest waiting slot
-            if (__popcll(__ballot(pending != 0u)) >= kRefillLanes) {
-                const bool has = pending != 0u;
-                const int s1 = has ? __builtin_ctz(pending) : 0;
-                uint32_t n1 = 0u;
-#pragma unroll
-                for (int s = 0; s < S; ++s) n1 = s == s1 ? nk[s] : n1;
-                const uint64_t m = has ? rt_draw_m53(key0, key1, traj, net_id,
-                                                     (uint32_t)(tid + s1 * L), n1 + 1u)
-                                       : 0x1FFFFFFFFFFFFFull;
-                const double E = rt_neglog_wave(m, false, &ws->slow_logs, sc);
-#pragma unroll
-                for (int s = 0; s < S; ++s) En[s] = (has && s == s1) ? E : En[s];
-                pending &= pending - 1u;
-            }
         }
 
         // ---- end of the trajectory (after a capped firing wavefront 0's
@@ -370,7 +365,7 @@ __global__ __launch_bounds__(L, g2_min_waves(S)) void rt_group_lds_kernel(rt_cla
             const int k = tid + s * L;
             if (k < M) {
                 // OK / ABSORBED: the propensities in force since the last event
-                if (good) T[s] = fma(ai[k].x, dt, T[s]);
+                if (good) T[s] = fma(pa[k], dt, T[s]);
                 if (it->n_out) it->n_out[r * M + k] = nk[s];
                 if (it->T_out) it->T_out[r * M + k] = T[s];
             }
