@@ -166,9 +166,16 @@ __global__ __launch_bounds__(L, g2_min_waves(S)) void rt_group_lds_kernel(rt_cla
             double d1 = __builtin_inf(), d2 = __builtin_inf();
             int ks = 0;
             bool bad = false;
+            // every slot's 1/a_k read at once (the scheduling barrier keeps the
+            // compiler from interleaving the reads with the arithmetic and
+            // waiting on each in turn)
+            double iv[S];
+#pragma unroll
+            for (int s = 0; s < S; ++s) iv[s] = pinv[tid + s * L];
+            __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
             for (int s = 0; s < S; ++s) {
-                const double raw = (P[s] - T[s]) * pinv[tid + s * L];
+                const double raw = (P[s] - T[s]) * iv[s];
                 bad = bad || !(raw >= 0.0);
                 const bool lt = raw < d1;          // the lower slot wins equal values
                 d2 = fmin(d2, fmax(d1, raw));
@@ -287,8 +294,14 @@ __global__ __launch_bounds__(L, g2_min_waves(S)) void rt_group_lds_kernel(rt_cla
             }
             // (a_k as read by the pass: this wavefront writes its channels'
             // entries only below)
+            {
+                double av[S];
 #pragma unroll
-            for (int s = 0; s < S; ++s) T[s] = fma(pa[tid + s * L], d1, T[s]);
+                for (int s = 0; s < S; ++s) av[s] = pa[tid + s * L];
+                __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+                for (int s = 0; s < S; ++s) T[s] = fma(av[s], d1, T[s]);
+            }
             if (tid == owner) {
 #pragma unroll
                 for (int s = 0; s < S; ++s)
@@ -320,8 +333,20 @@ __global__ __launch_bounds__(L, g2_min_waves(S)) void rt_group_lds_kernel(rt_cla
                     return v;
                 };
                 if (mine) {
-                    const double an = rt_propensity((int)((uint32_t)rr.x >> 29),
-                                                    rr.x & RT_SPECIES_MASK, rr.y, cr, xnew);
+                    // both reactant counts after the jump in one sweep over
+                    // v_mu, then h without branching on the lanes' kinds
+                    const int kind = (int)((uint32_t)rr.x >> 29);
+                    const int s0 = rr.x & RT_SPECIES_MASK, s1 = rr.y;
+                    int32_t v0 = 0, v1 = 0;
+                    if (kind != RT_H_ZERO) v0 = Xc[s0];
+                    if (kind == RT_H_TWO) v1 = Xc[s1];
+                    for (int q = 0; q < nu_stride; ++q) {
+                        const int sq = __builtin_amdgcn_readlane(nv.x, q);
+                        const int dq = __builtin_amdgcn_readlane(nv.y, q);
+                        v0 += sq == s0 ? dq : 0;
+                        v1 += sq == s1 ? dq : 0;
+                    }
+                    const double an = rt_propensity_counts(kind, (uint32_t)v0, (uint32_t)v1, cr);
                     pa[kd] = an;
                     pinv[kd] = 1.0 / an;
                 }

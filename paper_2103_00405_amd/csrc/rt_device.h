@@ -61,6 +61,20 @@ __device__ __forceinline__ double rt_propensity(int kind, int s0, int s1, double
     return c * rt_u64_to_f64(h);
 }
 
+// The same from the reactant counts v0 = X_s0 and v1 = X_s1 (read only as
+// the kind needs them), as selects rather than branches: lanes of one
+// wavefront holding channels of different kinds take one path.  One-species h
+// converts exactly either way, so the value is the one above.
+__device__ __forceinline__ double rt_propensity_counts(int kind, uint32_t v0, uint32_t v1, double c)
+{
+    const uint64_t pair = ((uint64_t)v0 * (uint32_t)(v0 - 1u)) >> 1;
+    const uint64_t two = (uint64_t)v0 * v1;
+    const uint64_t h = kind == RT_H_ZERO ? 1ull
+                     : kind == RT_H_ONE ? (uint64_t)v0
+                     : kind == RT_H_PAIR ? pair : two;
+    return c * rt_u64_to_f64(h);
+}
+
 // The same with X in memory (LDS) and the packed reactant-table entry
 // rr = (s0 | kind << 29, s1).
 __device__ __forceinline__ double rt_propensity_mem(int2 rr, double c, const int32_t* X)

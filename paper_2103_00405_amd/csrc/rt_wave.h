@@ -218,6 +218,19 @@ __device__ __forceinline__ rt_sel_part rt_select_wave(double d1, double d2, int3
     return p;
 }
 
+// The union of two parts: b wins on a smaller d1 or an equal one with a
+// lower channel; the loser's d1 joins the candidates for the second smallest.
+__device__ __forceinline__ rt_sel_part rt_sel_merge(const rt_sel_part& a, const rt_sel_part& b)
+{
+    const bool bw = (b.d1 < a.d1) | ((b.d1 == a.d1) & (b.k < a.k));
+    rt_sel_part r;
+    r.d1 = bw ? b.d1 : a.d1;
+    r.k = bw ? b.k : a.k;
+    r.d2 = rt_min_sel(bw ? b.d2 : a.d2, bw ? a.d1 : b.d1);
+    r.pad = 0;
+    return r;
+}
+
 // The workgroup's selection (L = 64 W threads, all reaching the one barrier
 // inside; part: W entries of LDS, not read by another selection until every
 // thread has passed this one's barrier).  Every thread returns the same.
@@ -233,19 +246,14 @@ __device__ __forceinline__ rt_min2 rt_select_group(double d1, double d2, int32_t
     } else {
         if ((threadIdx.x & 63u) == 0) part[threadIdx.x >> 6] = p;
         __syncthreads();
-        // merge the parts in wavefront order; a part that loses gives its
-        // smallest value to the candidates for the second smallest
-        rt_sel_part b = part[0];
-        double others = __builtin_inf();
+        // every part at once, merged as a tree (the merge is commutative)
+        rt_sel_part q[W];
 #pragma unroll
-        for (int w = 1; w < W; ++w) {
-            const rt_sel_part q = part[w];
-            const bool better = q.d1 < b.d1 || (q.d1 == b.d1 && q.k < b.k);
-            others = rt_min_sel(others, better ? b.d1 : q.d1);
-            b.d1 = better ? q.d1 : b.d1;
-            b.d2 = better ? q.d2 : b.d2;
-            b.k = better ? q.k : b.k;
-        }
-        return rt_min2{b.d1, rt_min_sel(b.d2, others), b.k};
+        for (int w = 0; w < W; ++w) q[w] = part[w];
+#pragma unroll
+        for (int h = 1; h < W; h <<= 1)
+#pragma unroll
+            for (int w = 0; w + h < W; w += 2 * h) q[w] = rt_sel_merge(q[w], q[w + h]);
+        return rt_min2{q[0].d1, q[0].d2, q[0].k};
     }
 }
