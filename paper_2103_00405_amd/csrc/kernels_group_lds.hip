@@ -303,13 +303,24 @@ __global__ __launch_bounds__(L, g2_min_waves(S)) void rt_group_lds_kernel(rt_cla
                 for (int s = 0; s < S; ++s) T[s] = fma(av[s], d1, T[s]);
             }
             if (tid == owner) {
+                if constexpr (!SCHED) {
+                    // (sm is uniform: the compiler indexes the register arrays
+                    // directly rather than selecting over every slot)
+                    const double pm = P[sm];
+                    T[sm] = pm;
+                    P[sm] = pm + En[sm];
+                    ++nk[sm];
+                } else {
+                    // (with the schedule's registers the indexed form would
+                    // move the arrays to scratch memory)
 #pragma unroll
-                for (int s = 0; s < S; ++s)
-                    if (s == sm) {
-                        T[s] = P[s];
-                        P[s] = P[s] + En[s];
-                        ++nk[s];
-                    }
+                    for (int s = 0; s < S; ++s)
+                        if (s == sm) {
+                            T[s] = P[s];
+                            P[s] = P[s] + En[s];
+                            ++nk[s];
+                        }
+                }
                 pending |= 1u << sm;
                 if (clamped) atomicAdd(&ws->clamps, 1ull);
             }
