@@ -76,11 +76,14 @@ __device__ __forceinline__ double rt_propensity_counts(int kind, uint32_t v0, ui
 }
 
 // The same with X in memory (LDS) and the packed reactant-table entry
-// rr = (s0 | kind << 29, s1).
+// rr = (s0 | kind << 29, s1), in the select form.
 __device__ __forceinline__ double rt_propensity_mem(int2 rr, double c, const int32_t* X)
 {
-    return rt_propensity((int)((uint32_t)rr.x >> 29), rr.x & RT_SPECIES_MASK, rr.y, c,
-                         [&](int j) { return X[j]; });
+    const int kind = (int)((uint32_t)rr.x >> 29);
+    int32_t v0 = 0, v1 = 0;
+    if (kind != RT_H_ZERO) v0 = X[rr.x & RT_SPECIES_MASK];
+    if (kind == RT_H_TWO) v1 = X[rr.y];
+    return rt_propensity_counts(kind, (uint32_t)v0, (uint32_t)v1, c);
 }
 
 // The near-tie rule (Eq. 4 gives ties probability zero; in binary64 the two
