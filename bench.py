@@ -446,7 +446,7 @@ def batch_jobs(api, wl):
 def bench_batched(api, W, steps=2, n_nets=4096, solo_sample=32, tune_samples=16, cpu_s=0.0):
     """4096 random networks (M log-uniform in [3, 2048], N = M/4, 64
     trajectories each, t_end for about 2e4 firings) in one captured launch per
-    size class -- the networks above 512 channels in the lazy form, the others
+    size class -- the networks above LAZY_ABOVE_M channels in the lazy form, the others
     with lane counts chosen by the autotuner -- against one rtssa_simulate
     launch per network with the same method.  Networks whose rates grow with the state can run far
     past 2e4 firings; every trajectory is capped at 1e5 firings (status
