@@ -212,7 +212,7 @@ int rtssa_network_set_schedule(rtssa_network* net, int32_t B, const double* time
  * R trajectories and these options (opt may be NULL): the run's counters and
  * work-queue heads, plus, for LAZY, one slice of channel records per resident
  * wavefront (about 44 bytes per channel each).  For LAZY, DIRECT_TREE and the
- * random-time workgroup mapping it also builds the network's fixed-stride
+ * random-time sub-wave and workgroup mappings it also builds the network's fixed-stride
  * rows (its jumps and dependency lists, about 256 bytes per channel) if they
  * are not built yet (synchronous; they are allocated once per network), so
  * that a later call with a caller workspace allocates nothing.  No stream
@@ -248,7 +248,7 @@ int rtssa_workspace_size(const rtssa_network* net, int64_t R, const rtssa_option
  * opt may be NULL (defaults).  With opt->workspace the call allocates
  * nothing and synchronises nothing unless stats is given, so it can be
  * captured into a caller's hipGraph (for LAZY, DIRECT_TREE and the
- * workgroup mapping the network's rows must have been built by
+ * sub-wave and workgroup mappings the network's rows must have been built by
  * rtssa_workspace_size or an earlier run, else RTSSA_E_INVALID); without it
  * a workspace of rtssa_workspace_size() bytes is allocated stream-ordered
  * and freed after the launch.
@@ -274,7 +274,7 @@ int rtssa_simulate(const rtssa_network* net, const int32_t* x0, int32_t x0_per_t
  * holds on each GPU it runs on until the process ends.  The call allocates
  * and frees nothing (no hipMalloc, no events; stats->kernel_ms is 0).
  *   opt->workspace must be NULL.
- *   LAZY, DIRECT_TREE and the workgroup mapping need the network's rows
+ *   LAZY, DIRECT_TREE and the sub-wave and workgroup mappings need the network's rows
  *   built first (rtssa_workspace_size or an earlier rtssa_simulate), else
  *   E_INVALID.
  *   LAZY keeps only as many resident wavefronts as their channel records fit

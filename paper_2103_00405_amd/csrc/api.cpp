@@ -176,7 +176,8 @@ int rt_run_rows(const rtssa_network* net, const rtssa_options& o)
     if (o.method == RTSSA_METHOD_LAZY || o.method == RTSSA_METHOD_DIRECT_TREE) return 1;
     if (o.method != RTSSA_METHOD_RANDOM_TIME) return 0;
     const int mapping = o.mapping == RTSSA_MAP_AUTO ? rt_auto_mapping(net) : o.mapping;
-    return mapping == RTSSA_MAP_WORKGROUP && net->M > 0 ? 2 : 0;
+    if (net->M <= 0) return 0;
+    return mapping == RTSSA_MAP_WORKGROUP ? 2 : (mapping == RTSSA_MAP_WAVE ? 1 : 0);
 }
 
 bool rt_rows_ready(const rtssa_network* net, int rows)

@@ -183,9 +183,13 @@ static int batch_create(const rtssa_batch_item* items, int32_t count, const rtss
     for (int i = 0; i < count; ++i) {
         if (items[i].R <= 0) continue;
         const class_key key = classify(items[i].net, items[i].method, plan, o);
-        if (key.mapping == RTSSA_MAP_WORKGROUP && key.method == RTSSA_METHOD_RANDOM_TIME) {
-            // the workgroup kernels read the network's fixed-stride records
-            const int rc = rt_group_rows_prepare(const_cast<rtssa_network*>(items[i].net));
+        if (key.method == RTSSA_METHOD_RANDOM_TIME &&
+            (key.mapping == RTSSA_MAP_WORKGROUP || key.mapping == RTSSA_MAP_WAVE)) {
+            // the workgroup kernels read the network's fixed-stride records,
+            // the sub-wave kernel its jump and touch rows
+            rtssa_network* n = const_cast<rtssa_network*>(items[i].net);
+            const int rc = key.mapping == RTSSA_MAP_WORKGROUP ? rt_group_rows_prepare(n)
+                                                              : rt_lazy_prepare(n);
             if (rc) return rt_fail(rc, "item " + std::to_string(i) + ": " + rtssa_last_error());
         }
         groups[key].push_back(i);

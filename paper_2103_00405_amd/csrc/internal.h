@@ -192,7 +192,8 @@ size_t rt_group_lds2_bytes(int N, int L, int S);
 int rt_launch_group_lds(int M, int max_N, const rt_class_dev& C, int L, int grid,
                         hipStream_t stream, int* grid_used);
 // the fixed-stride rows a run of this network with these options reads:
-// 0 none, 1 the lazy form's rows (tree methods), 2 those and the workgroup
+// 0 none, 1 the lazy form's rows (tree methods; the random-time sub-wave
+// mapping), 2 those and the workgroup
 // mapping's dependency records (random-time workgroup mapping)
 int rt_run_rows(const rtssa_network* net, const rtssa_options& o);
 bool rt_rows_ready(const rtssa_network* net, int rows);

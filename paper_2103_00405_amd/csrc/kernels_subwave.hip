@@ -9,7 +9,9 @@
 // wavefront advance in lockstep, one firing per pass, but each group runs its
 // own trajectory: the expensive per-firing tail (one Philox block and one
 // correctly rounded logarithm for the fired channel, Eq. 26) runs in one lane
-// per group, so a wavefront pays it once for 64 / L firings.  There are no
+// per group, so a wavefront pays it once for 64 / L firings, and it runs
+// while the fired channel's fixed-stride rows (its jump and the channels of
+// D(mu), the lazy form's rows) load in one round trip.  There are no
 // workgroup barriers: a group lives inside one wavefront, whose LDS accesses
 // complete in program order.
 //
@@ -41,6 +43,9 @@ __global__ __launch_bounds__(kBlock, subwave_min_waves(S, SCHED)) void rt_subwav
 {
     constexpr unsigned long long kGroupBits = L == 64 ? ~0ull : ((1ull << L) - 1ull);
     rt_ws* const ws = C.ws;
+    // Issue priority over other kernels' wavefronts sharing a CU (batches):
+    // below the thread mapping's, above the lazy and workgroup kernels'.
+    __builtin_amdgcn_s_setprio(2);
     const uint32_t key0 = ws->key0, key1 = ws->key1;
     const int tid = threadIdx.x, li = tid % L, lane = tid & 63;
     const unsigned long long gmask = kGroupBits << (lane - li);
@@ -135,18 +140,36 @@ __global__ __launch_bounds__(kBlock, subwave_min_waves(S, SCHED)) void rt_subwav
         const bool brk = SCHED && live && b_next < t_end && t_new > b_next;
         const bool term = !brk && (absorbed || t_new > t_end);
         const bool event = live && !term && !brk;
-        // ---- the jump v_mu, checked against [0, 2^31 - 1] by lanes < |v_mu|
-        int nb = 0, ne = 0;
-        if (event) {
-            const rt_cptr<int32_t> nu_ptr = rt_const(net->nu_ptr);
-            nb = nu_ptr[kmin];
-            ne = nu_ptr[kmin + 1];
+        // ---- the fired channel's fixed-stride rows, one round trip: its jump
+        // (lane li < nu_stride: entry li) and its touch row (lane li: the 64 / L
+        // consecutive entries from li 64 / L; entry 0 counts the channels of
+        // D(kmin) other than kmin, entries 1..63 name them, -1 past the end)
+        constexpr int kTE = 64 / L;                         // touch entries per lane
+        const int kr = event ? kmin : 0;                    // row 0 exists (M >= 1)
+        const int nu_stride = net->nu_stride;
+        const int2 nv = rt_const(net->nu_fixed)[kr * nu_stride + min(li, nu_stride - 1)];
+        int32_t tch[kTE];
+        {
+            const rt_cptr<int32_t> row = rt_const(net->touch) + (size_t)kr * 64 + li * kTE;
+#pragma unroll
+            for (int e = 0; e < kTE; ++e) tch[e] = row[e];
         }
+        // the fired channel's next Exp(1) (Eq. 26) in its owner lane, while
+        // the rows load (discarded if the event is not applied in this pass)
+        uint32_t nm_new = 0;
+        double E_new = 0.0;
+        if (event && li == (kmin & (L - 1))) {
+            nm_new = nk[kmin] + 1u;
+            E_new = rt_exp1_wave(key0, key1, traj, net_id, (uint32_t)kmin, nm_new,
+                                 &ws->slow_logs, sc);
+        }
+        // ---- the jump v_mu, checked against [0, 2^31 - 1] by lanes < |v_mu|
         int32_t xv = 0, xs = 0;
         bool okl = true;
-        if (li < ne - nb) {
-            xs = rt_const(net->nu_sp)[nb + li];
-            const int64_t v = (int64_t)X[xs] + rt_const(net->nu_dl)[nb + li];
+        const bool has_nu = event && li < nu_stride && nv.x >= 0;
+        if (has_nu) {
+            xs = nv.x;
+            const int64_t v = (int64_t)X[xs] + nv.y;
             okl = v >= 0 && v <= 0x7FFFFFFF;
             xv = (int32_t)v;
         }
@@ -299,19 +322,29 @@ __global__ __launch_bounds__(kBlock, subwave_min_waves(S, SCHED)) void rt_subwav
         }
         // ---- the event: jump, dependency flags, fresh draw by the owner lane
         mu = kmin;
-        if (li < ne - nb) X[xs] = xv;
+        if (has_nu) X[xs] = xv;
+        // stale bits: mu itself (its propensity may read a species it
+        // changes) and the channels of its touch row
+        if (li == 0) atomicOr(&stale_w[mu & (L - 1)], 1u << (mu >> LOG2L));
+#pragma unroll
+        for (int e = 0; e < kTE; ++e) {
+            const int kk = tch[e];
+            if (li * kTE + e > 0 && kk >= 0) atomicOr(&stale_w[kk & (L - 1)], 1u << (kk >> LOG2L));
+        }
         {
-            const rt_cptr<int32_t> dep_ptr = rt_const(net->dep_ptr);
-            const int db = dep_ptr[mu], de = dep_ptr[mu + 1];
-            for (int q = db + li; q < de; q += L) {
-                const int kk = rt_const(net->dep_idx)[q];
-                atomicOr(&stale_w[kk & (L - 1)], 1u << (kk >> LOG2L));
+            // more than 63 others: the rest of the CSR list D(mu) (rare)
+            const int n_other = __shfl(tch[0], lane - li, 64);
+            if (n_other > 63) {
+                const int de = rt_const(net->dep_ptr)[mu + 1];
+                for (int q = rt_const(net->touch_more)[mu] + li; q < de; q += L) {
+                    const int kk = rt_const(net->dep_idx)[q];
+                    atomicOr(&stale_w[kk & (L - 1)], 1u << (kk >> LOG2L));
+                }
             }
         }
         if (li == (mu & (L - 1))) {
-            const uint32_t nm = nk[mu];
-            nk[mu] = nm + 1u;
-            E = rt_exp1_wave(key0, key1, traj, net_id, (uint32_t)mu, nm + 1u, &ws->slow_logs, sc);
+            nk[mu] = nm_new;
+            E = E_new;
         }
         rt_wave_lds_fence();
         t = t_new;

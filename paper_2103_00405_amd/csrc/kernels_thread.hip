@@ -104,6 +104,11 @@ template <int MT, int NT, int METHOD, bool SCHED>
 __global__ __launch_bounds__(256, thread_min_waves(MT, NT, METHOD, SCHED)) void rt_thread_kernel(rt_class_dev C)
 {
     rt_ws* const ws = C.ws;
+    // Issue priority of this kernel's wavefronts over other kernels' sharing a
+    // CU (a batch runs class kernels side by side): a small network's class is
+    // bound by its longest trajectories, one lane each, so its wavefronts go
+    // first; alone on the device every wavefront has the same priority.
+    __builtin_amdgcn_s_setprio(3);
     const uint32_t key0 = ws->key0, key1 = ws->key1;
     __shared__ uint32_t log_scratch[4][RT_LOG_SCRATCH];     // one slice per wave
     uint32_t* sc = log_scratch[threadIdx.x >> 6];
