@@ -48,6 +48,8 @@ namespace {
 constexpr int kFanLog = 3;               // children per node: 2^kFanLog
 constexpr int kFan = 1 << kFanLog;
 constexpr int kMaxLevels = 64 / kFan;    // one lane per sibling in lazy_second
+constexpr int kTopPer = 8;               // top-level entries per lane
+constexpr int kTopMax = 64 * kTopPer;    // the tree stops at a level this small
 
 struct rt_lazy_rec {                     // a channel's state in the workspace
     double T, s, P, a;
@@ -171,15 +173,41 @@ __device__ __forceinline__ lazy_min lazy_wave_argmin(lazy_min v)
     return lazy_swap_step<32>(v);
 }
 
-// The top level (at most 64 entries, lane e holds entry e) and its reduction
-// to the next event: the smallest tau and its channel.
-__device__ __forceinline__ lazy_min lazy_top_entry(const double* top_d, const int32_t* top_k,
-                                                   int top_cnt, bool leaves_on_top, int lane)
+// The top level (at most kTopMax entries; lane l holds entries l + 64 i) as
+// the lane's smallest entry (channel order wins ties: a lane's entries come in
+// channel order), the lane's second smallest and the index of its smallest;
+// the wavefront argmin of the lanes' smallest is the next event.
+struct lazy_top {
+    lazy_min m;
+    double d2;
+    int e1;
+};
+
+__device__ __forceinline__ lazy_top lazy_top_scan(const double* top_d, const int32_t* top_k,
+                                                  int top_cnt, bool leaves_on_top, int lane)
 {
-    const int e = min(lane, top_cnt - 1);
-    const double d = top_d[e];
-    const int k = leaves_on_top ? lane : top_k[e];
-    return lazy_min{lane < top_cnt ? d : __builtin_inf(), lane < top_cnt ? k : 0x7FFFFFFF};
+    double dv[kTopPer];
+    int32_t kv[kTopPer];
+#pragma unroll
+    for (int i = 0; i < kTopPer; ++i) {
+        const int e = lane + 64 * i;
+        dv[i] = __builtin_inf();
+        kv[i] = 0x7FFFFFFF;
+        if (e < top_cnt) {
+            dv[i] = top_d[e];
+            kv[i] = leaves_on_top ? e : top_k[e];
+        }
+    }
+    lazy_top r{lazy_min{__builtin_inf(), 0x7FFFFFFF}, __builtin_inf(), -1};
+#pragma unroll
+    for (int i = 0; i < kTopPer; ++i) {
+        const bool lt = dv[i] < r.m.d;
+        r.d2 = rt_min_sel(r.d2, lt ? r.m.d : dv[i]);
+        r.m.d = lt ? dv[i] : r.m.d;
+        r.m.k = lt ? kv[i] : r.m.k;
+        r.e1 = lt ? lane + 64 * i : r.e1;
+    }
+    return r;
 }
 
 // The second smallest tau over all leaves: every leaf but mu lies in the
@@ -190,8 +218,7 @@ __device__ __forceinline__ lazy_min lazy_top_entry(const double* top_d, const in
 // in LDS so that the per-lane level index does not turn into a private-memory
 // array); every lane also takes top-level entry `lane` unless it is mu's.
 __device__ __forceinline__ double lazy_second(const char* region, const uint32_t* level_off,
-                                              int top, int mu, const lazy_min& top_entry,
-                                              int lane)
+                                              int top, int mu, const lazy_top& tp, int lane)
 {
     double sib = __builtin_inf();
     if (top > 0) {
@@ -200,7 +227,9 @@ __device__ __forceinline__ double lazy_second(const char* region, const uint32_t
         const double x = ((const double*)(region + level_off[lev]))[(jl & ~(kFan - 1)) + i];
         sib = (lane >> kFanLog) < top && i != (jl & (kFan - 1)) ? x : __builtin_inf();
     }
-    const double own = lane == (mu >> (kFanLog * top)) ? __builtin_inf() : top_entry.d;
+    // the top level's entries but mu's ancestor (the smallest of its lane)
+    const int anc = mu >> (kFanLog * top);
+    const double own = lane == (anc & 63) && tp.e1 == anc ? tp.d2 : tp.m.d;
     return lazy_wave_min(lazy_min_f64(sib, own));
 }
 
@@ -271,8 +300,9 @@ __global__ __launch_bounds__(64) void rt_lazy_kernel(rt_class_dev C, rt_lazy_rec
 
         // LDS: X [N, padded to 4], the leaves, then the node levels 1 .. top
         // (sizes ceil(previous / 8)); the top level is the first with at
-        // most 64 entries (the leaves themselves when M <= 64), reduced to
-        // the next event by one wavefront argmin.  Every level index below is
+        // most kTopMax entries (the leaves themselves when M <= kTopMax),
+        // scanned kTopPer entries per lane and reduced to the next event by
+        // one wavefront argmin.  Every level index below is
         // a compile-time constant after unrolling.
         lazy_tree tr;
         int32_t* X = dyn_lds;
@@ -282,7 +312,7 @@ __global__ __launch_bounds__(64) void rt_lazy_kernel(rt_class_dev C, rt_lazy_rec
             tr.d[0] = (double*)p;
             tr.kk[0] = (int32_t*)p;                      // unused (leaves carry no channel)
             p += 8 * padf(tr.cnt[0]);
-            int top_l = tr.cnt[0] <= 64 ? 0 : -1;
+            int top_l = tr.cnt[0] <= kTopMax ? 0 : -1;
 #pragma unroll
             for (int l = 1; l <= kMaxLevels; ++l) {
                 tr.cnt[l] = (tr.cnt[l - 1] + kFan - 1) >> kFanLog;
@@ -290,7 +320,7 @@ __global__ __launch_bounds__(64) void rt_lazy_kernel(rt_class_dev C, rt_lazy_rec
                 tr.d[l] = (double*)p;
                 tr.kk[l] = (int32_t*)(p + 8 * P);
                 p += 12 * P;
-                if (top_l < 0 && tr.cnt[l] <= 64) top_l = l;
+                if (top_l < 0 && tr.cnt[l] <= kTopMax) top_l = l;
             }
             tr.top = top_l;
         }
@@ -342,8 +372,8 @@ __global__ __launch_bounds__(64) void rt_lazy_kernel(rt_class_dev C, rt_lazy_rec
 
         // the next event: the top level's argmin, kept in registers (every
         // lane holds it) and recomputed at the end of each tree update
-        lazy_min top_e = lazy_top_entry(top_d, top_k, top_cnt, top == 0, lane);
-        lazy_min root = lazy_wave_argmin(top_e);
+        lazy_top top_e = lazy_top_scan(top_d, top_k, top_cnt, top == 0, lane);
+        lazy_min root = lazy_wave_argmin(top_e.m);
         double root_tau = root.d;
         int root_ch = root.k;
         double t = 0.0, s_next = it->G > 0 ? rt_const(it->s)[0] : __builtin_inf();
@@ -385,8 +415,8 @@ __global__ __launch_bounds__(64) void rt_lazy_kernel(rt_class_dev C, rt_lazy_rec
                         lazy_store(tr, l, j, lazy_node(tr, l, j));
                     rt_wave_lds_fence();
                 }
-                top_e = lazy_top_entry(top_d, top_k, top_cnt, top == 0, lane);
-                root = lazy_wave_argmin(top_e);
+                top_e = lazy_top_scan(top_d, top_k, top_cnt, top == 0, lane);
+                root = lazy_wave_argmin(top_e.m);
                 root_tau = root.d;
                 root_ch = root.k;
                 continue;
@@ -484,8 +514,8 @@ __global__ __launch_bounds__(64) void rt_lazy_kernel(rt_class_dev C, rt_lazy_rec
                     }
                 }
             }
-            top_e = lazy_top_entry(top_d, top_k, top_cnt, top == 0, lane);
-            root = lazy_wave_argmin(top_e);
+            top_e = lazy_top_scan(top_d, top_k, top_cnt, top == 0, lane);
+            root = lazy_wave_argmin(top_e.m);
             root_tau = root.d;
             root_ch = root.k;
             if (lane == 0) nks[mu] = nm + 1u;
@@ -792,8 +822,8 @@ static size_t tree_lds_bytes(int N, int M, int top_max)
     return 0;
 }
 
-// the lazy form's tree stops at a top level of at most 64 entries
-size_t rt_lazy_lds_bytes(int N, int M) { return tree_lds_bytes(N, M, 64); }
+// the lazy form's tree stops at a top level of at most kTopMax entries
+size_t rt_lazy_lds_bytes(int N, int M) { return tree_lds_bytes(N, M, kTopMax); }
 
 // the sum tree goes up to its single root
 static size_t dmtree_lds_bytes(int N, int M) { return tree_lds_bytes(N, M, 1); }
