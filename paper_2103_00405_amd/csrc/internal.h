@@ -204,8 +204,11 @@ int rt_rows_prepare(rtssa_network* net, int rows);
 // rt_lazy_grid returns (the same grid the launch then uses)
 int rt_launch_lazy(const rt_class_dev& C, int max_N, int max_M, int grid, int64_t units,
                    hipStream_t stream, int* grid_used, void* workspace = nullptr);
-// sched: the class has a rate schedule (C.has_schedule), which picks the kernel
-int rt_lazy_grid(int max_N, int max_M, int grid, int64_t units, bool sched, int* grid_out);
+// sched: the class has a rate schedule (C.has_schedule), which picks the kernel;
+// max_per_cu > 0 caps the resident wavefronts per CU of a grid the call sizes
+// (a batch's lazy classes leave room for the classes running beside them)
+int rt_lazy_grid(int max_N, int max_M, int grid, int64_t units, bool sched, int* grid_out,
+                 int max_per_cu = 0);
 size_t rt_lazy_workspace_bytes(int grid, int max_M);
 size_t rt_lazy_lds_bytes(int N, int M);
 // the direct method on a sum tree (same mapping and layout as the lazy form)

@@ -830,7 +830,8 @@ static size_t dmtree_lds_bytes(int N, int M) { return tree_lds_bytes(N, M, 1); }
 
 // The lazy kernel's grid: the requested one, or the resident wavefronts
 // (LDS-limited) of the device, never more than the trajectories.
-int rt_lazy_grid(int max_N, int max_M, int grid, int64_t units, bool sched, int* grid_out)
+int rt_lazy_grid(int max_N, int max_M, int grid, int64_t units, bool sched, int* grid_out,
+                 int max_per_cu)
 {
     const void* fn = sched ? (const void*)rt_lazy_kernel<true> : (const void*)rt_lazy_kernel<false>;
     const size_t lds = rt_lazy_lds_bytes(max_N, max_M);
@@ -852,6 +853,7 @@ int rt_lazy_grid(int max_N, int max_M, int grid, int64_t units, bool sched, int*
         if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, 64, lds) != hipSuccess ||
             per_cu < 1)
             per_cu = 1;
+        if (max_per_cu > 0) per_cu = std::min(per_cu, max_per_cu);
         grid = cus * per_cu;
     }
     if ((int64_t)grid > units) grid = (int)std::max<int64_t>(units, 1);
