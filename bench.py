@@ -73,7 +73,7 @@ PEAK_LANE_SLOTS = 256 * 4 * 16 * CLOCK_HZ   # CUs x SIMDs x lanes x clock = 3.93
 # from two rocprofv3 counter passes (FETCH_SIZE, WRITE_SIZE) scaled by the same
 # counters on a 1 GiB copy (factors 2.0 and 1.0).  Valid for the kernel as
 # profiled; set to None when the kernel changes until it is measured again.
-LV_TRAFFIC_BYTES_PER_LAUNCH = 1.327e+09
+LV_TRAFFIC_BYTES_PER_LAUNCH = 1.329e+09
 
 
 def parse():
