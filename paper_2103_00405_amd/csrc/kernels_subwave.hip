@@ -158,10 +158,11 @@ __global__ __launch_bounds__(kBlock, subwave_min_waves(S, SCHED)) void rt_subwav
         // the rows load (discarded if the event is not applied in this pass)
         uint32_t nm_new = 0;
         double E_new = 0.0;
+        bool slow_new = false;                              // counted when applied
         if (event && li == (kmin & (L - 1))) {
             nm_new = nk[kmin] + 1u;
-            E_new = rt_exp1_wave(key0, key1, traj, net_id, (uint32_t)kmin, nm_new,
-                                 &ws->slow_logs, sc);
+            E_new = rt_neglog_wave(rt_draw_m53(key0, key1, traj, net_id, (uint32_t)kmin, nm_new),
+                                   false, nullptr, sc, &slow_new);
         }
         // ---- the jump v_mu, checked against [0, 2^31 - 1] by lanes < |v_mu|
         int32_t xv = 0, xs = 0;
@@ -345,6 +346,7 @@ __global__ __launch_bounds__(kBlock, subwave_min_waves(S, SCHED)) void rt_subwav
         if (li == (mu & (L - 1))) {
             nk[mu] = nm_new;
             E = E_new;
+            if (slow_new) atomicAdd(&ws->slow_logs, 1ull);
         }
         rt_wave_lds_fence();
         t = t_new;

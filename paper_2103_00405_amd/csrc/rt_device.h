@@ -115,10 +115,13 @@ __device__ __forceinline__ int rt_find_item(rt_cptr<int64_t> unit_start, int cou
 
 // RN(-ln u) for the wave's active lanes.  The fast phase runs in every lane;
 // lanes whose rounding it cannot certify (about one draw in 2^17) take turns
-// on the wave's LDS slice sc (RT_LOG_SCRATCH words) for the accurate phase
-// and add one to the device counter *slow.
+// on the wave's LDS slice sc (RT_LOG_SCRATCH words) for the accurate phase;
+// each such lane adds one to the device counter *slow, or, with slow = NULL,
+// sets *took_slow instead (for a draw that may be discarded and counted only
+// once it is used).
 __device__ __forceinline__ double rt_neglog_wave(uint64_t m, bool force_accurate,
-                                                 unsigned long long* slow, uint32_t* sc)
+                                                 unsigned long long* slow, uint32_t* sc,
+                                                 bool* took_slow = nullptr)
 {
     int e, i;
     double z;
@@ -131,6 +134,7 @@ __device__ __forceinline__ double rt_neglog_wave(uint64_t m, bool force_accurate
         y = yh;
         need = !rt_rounding_certain(yh, yl);
     }
+    if (took_slow) *took_slow = need;
     unsigned long long pending = __ballot(need);
     if (__builtin_expect(pending != 0ull, 0)) {
         const int me = (int)(threadIdx.x & 63u);
@@ -138,7 +142,7 @@ __device__ __forceinline__ double rt_neglog_wave(uint64_t m, bool force_accurate
             const int lane = __ffsll((long long)pending) - 1;
             if (lane == me) {
                 y = rt_neglog_accurate(e, i, z, sc);
-                atomicAdd(slow, 1ull);
+                if (slow) atomicAdd(slow, 1ull);
             }
             pending &= pending - 1ull;
         }
