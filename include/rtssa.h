@@ -213,7 +213,8 @@ int rtssa_network_set_schedule(rtssa_network* net, int32_t B, const double* time
  * work-queue heads, plus, for LAZY, one slice of channel records per resident
  * wavefront (about 44 bytes per channel each).  For LAZY, DIRECT_TREE and the
  * random-time sub-wave and workgroup mappings it also builds the network's fixed-stride
- * rows (its jumps and dependency lists, about 256 bytes per channel) if they
+ * rows (its jumps and dependency lists, about 256 bytes per channel; for the
+ * workgroup mapping also 64 dependency records of 32 bytes per channel) if they
  * are not built yet (synchronous; they are allocated once per network), so
  * that a later call with a caller workspace allocates nothing.  No stream
  * work otherwise.

@@ -50,9 +50,12 @@ struct rt_net_dev {
     // use): grow[mu*64 + q] = (k, react[k].x, react[k].y, w) for q = 0 (k = mu,
     // w = the number of channels of D(mu) other than mu) and q >= 1 (the q-th
     // other channel, k = -1 past the end; q = 1: w = the CSR position of the
-    // 64th other channel, dep_ptr[mu+1] if none); growc[mu*64 + q] = c_k
+    // 64th other channel, dep_ptr[mu+1] if none); growc[mu*64 + q] = c_k;
+    // gdel[mu*64 + q] = the change of the record's reactant species s0, s1
+    // under v_mu (0 for a species the record's kind does not read)
     const int4* grow;
     const double* growc;
+    const int2* gdel;
 };
 
 struct rtssa_network {

@@ -18,7 +18,8 @@
 //   event   every wavefront loads mu's fixed-stride rows (its jump v_mu and
 //           the records of the channels D(mu) reading a changed species --
 //           Gibson & Bruck's dependency graph, cited in section 5 -- with
-//           their reactants and rates: one round trip), checks the jump, advances
+//           their reactants, rates and the reactants' changes under v_mu:
+//           one round trip), checks the jump, advances
 //           its own internal clocks (Eq. 15: T_k += a_k Delta; T_mu = P_mu and
 //           P_mu += E, Eq. 26), and recomputes (a_k, 1/a_k) of the channels
 //           of D(mu) it owns, from X + v_mu; wavefront 0 writes X + v_mu into
@@ -100,6 +101,7 @@ __global__ __launch_bounds__(L, g2_min_waves(S)) void rt_group_lds_kernel(rt_cla
         const rt_cptr<int32_t> dep_ptr = rt_const(net.dep_ptr), dep_idx = rt_const(net.dep_idx);
         const rt_cptr<int4> grow = rt_const(net.grow);
         const rt_cptr<double> growc = rt_const(net.growc);
+        const rt_cptr<int2> gdel = rt_const(net.gdel);
         const rt_cptr<int2> nu_fixed = rt_const(net.nu_fixed);
         const int nu_stride = net.nu_stride;
         const rt_cptr<double> grid_s = rt_const(it->s);
@@ -232,9 +234,11 @@ __global__ __launch_bounds__(L, g2_min_waves(S)) void rt_group_lds_kernel(rt_cla
             // ---- mu's rows, one round trip: the jump (lane q: entry q) and
             // the dependency records (lane 0: mu itself, whose propensity may
             // read a species it changes; lane q >= 1: the q-th other channel
-            // of D(mu) or k = -1), each with its reactants and rate
+            // of D(mu) or k = -1), each with its reactants, rate and the
+            // change of those reactants under v_mu
             const int4 gr = grow[mu * 64 + lane];
             const double gc = growc[mu * 64 + lane];
+            const int2 dd = gdel[mu * 64 + lane];
             const int2 nv = nu_fixed[mu * nu_stride + min(lane, nu_stride - 1)];
             // ---- draws, while the rows load: a wavefront refills one waiting
             // slot per lane once enough lanes have one, and at once when it
@@ -344,19 +348,14 @@ __global__ __launch_bounds__(L, g2_min_waves(S)) void rt_group_lds_kernel(rt_cla
                     return v;
                 };
                 if (mine) {
-                    // both reactant counts after the jump in one sweep over
-                    // v_mu, then h without branching on the lanes' kinds
+                    // both reactant counts after the jump: X before it plus
+                    // the record's precomputed changes; h without branching
+                    // on the lanes' kinds
                     const int kind = (int)((uint32_t)rr.x >> 29);
                     const int s0 = rr.x & RT_SPECIES_MASK, s1 = rr.y;
                     int32_t v0 = 0, v1 = 0;
-                    if (kind != RT_H_ZERO) v0 = Xc[s0];
-                    if (kind == RT_H_TWO) v1 = Xc[s1];
-                    for (int q = 0; q < nu_stride; ++q) {
-                        const int sq = __builtin_amdgcn_readlane(nv.x, q);
-                        const int dq = __builtin_amdgcn_readlane(nv.y, q);
-                        v0 += sq == s0 ? dq : 0;
-                        v1 += sq == s1 ? dq : 0;
-                    }
+                    if (kind != RT_H_ZERO) v0 = Xc[s0] + dd.x;
+                    if (kind == RT_H_TWO) v1 = Xc[s1] + dd.y;
                     const double an = rt_propensity_counts(kind, (uint32_t)v0, (uint32_t)v1, cr);
                     pa[kd] = an;
                     pinv[kd] = 1.0 / an;

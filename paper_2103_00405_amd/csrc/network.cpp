@@ -274,24 +274,43 @@ int rt_group_rows_prepare(rtssa_network* net)
     const int M = net->M;
     const size_t rows = (size_t)std::max(M, 1);
     std::vector<int4> rec(rows * 64, make_int4(-1, 0, 0, 0));
+    std::vector<int2> del(rows * 64, make_int2(0, 0));
     std::vector<double> rc_c;
     group_record_rates(net, rc_c);
     for (int mu = 0; mu < M; ++mu) {
         int4* row = rec.data() + (size_t)mu * 64;
+        int2* drow = del.data() + (size_t)mu * 64;
+        // the change of species j under v_mu (each species once in the list)
+        auto change = [&](int j) {
+            for (int e = net->nu_ptr[mu]; e < net->nu_ptr[mu + 1]; ++e)
+                if (net->nu_sp[e] == j) return net->nu_dl[e];
+            return 0;
+        };
+        auto deltas = [&](int k) {
+            const int kind = (int)((uint32_t)net->react[k].x >> 29);
+            const int s0 = net->react[k].x & RT_SPECIES_MASK, s1 = net->react[k].y;
+            return make_int2(kind != RT_H_ZERO ? change(s0) : 0, kind == RT_H_TWO ? change(s1) : 0);
+        };
         row[0] = make_int4(mu, net->react[mu].x, net->react[mu].y, 0);
+        drow[0] = deltas(mu);
         int n_other = 0, more = net->dep_ptr[mu + 1];
         for (int q = net->dep_ptr[mu]; q < net->dep_ptr[mu + 1]; ++q) {
             const int k = net->dep_idx[q];
             if (k == mu) continue;
-            if (n_other < 63) row[1 + n_other] = make_int4(k, net->react[k].x, net->react[k].y, 0);
-            else if (n_other == 63) more = q;
+            if (n_other < 63) {
+                row[1 + n_other] = make_int4(k, net->react[k].x, net->react[k].y, 0);
+                drow[1 + n_other] = deltas(k);
+            } else if (n_other == 63) {
+                more = q;
+            }
             ++n_other;
         }
         row[0].w = n_other;
         row[1].w = more;
     }
     const size_t rb = rec.size() * sizeof(int4), cb = rc_c.size() * sizeof(double);
-    const size_t coff = (rb + 255) / 256 * 256;
+    const size_t db = del.size() * sizeof(int2);
+    const size_t coff = (rb + 255) / 256 * 256, doff = coff + (cb + 255) / 256 * 256;
     struct device_guard {
         int prev = -1;
         explicit device_guard(int d)
@@ -302,16 +321,18 @@ int rt_group_rows_prepare(rtssa_network* net)
         ~device_guard() { if (prev >= 0) hipSetDevice(prev); }
     } guard(net->device);
     void* blk = nullptr;
-    if (hipMalloc(&blk, coff + cb) != hipSuccess)
+    if (hipMalloc(&blk, doff + db) != hipSuccess)
         return rt_fail(RTSSA_E_NOMEM, "device allocation of the dependency records failed");
     if (hipMemcpy(blk, rec.data(), rb, hipMemcpyHostToDevice) != hipSuccess ||
-        hipMemcpy((char*)blk + coff, rc_c.data(), cb, hipMemcpyHostToDevice) != hipSuccess) {
+        hipMemcpy((char*)blk + coff, rc_c.data(), cb, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy((char*)blk + doff, del.data(), db, hipMemcpyHostToDevice) != hipSuccess) {
         hipFree(blk);
         return rt_fail(RTSSA_E_HIP, "copy of the dependency records failed");
     }
     net->group_block = blk;
     net->dev.grow = (const int4*)blk;
     net->dev.growc = (const double*)((char*)blk + coff);
+    net->dev.gdel = (const int2*)((char*)blk + doff);
     return RTSSA_OK;
 }
 
