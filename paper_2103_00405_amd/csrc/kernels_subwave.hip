@@ -33,10 +33,12 @@ namespace {
 
 constexpr int kBlock = 256;
 
-// Waves per SIMD the register allocation must allow: 8 slots of channel
-// state fit 3 (2 with a rate schedule's state); fewer slots are left to the
-// compiler (they land at 3).
-constexpr int subwave_min_waves(int S, bool SCHED) { return S >= 8 && !SCHED ? 3 : 2; }
+// Waves per SIMD the register allocation must allow: 2.  With 8 slots of
+// channel state, the fired channel's rows and its early draw, 3 waves would
+// spill to scratch (40-80 bytes per lane); at 2 the classes of 9-64 and
+// 65-128 channels of a 4096-network batch ran 20 and 15 % faster alone, the
+// 129-256 class 5 % slower.
+constexpr int subwave_min_waves(int, bool) { return 2; }
 
 template <int L, int S, bool SCHED>
 __global__ __launch_bounds__(kBlock, subwave_min_waves(S, SCHED)) void rt_subwave_kernel(rt_class_dev C)
