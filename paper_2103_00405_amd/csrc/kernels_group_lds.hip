@@ -208,6 +208,24 @@ __global__ __launch_bounds__(L, g2_min_waves(S)) void rt_group_lds_kernel(rt_cla
             const double t_new = t + d1;
             const int32_t* const Xc = Xb + (fired & 1u) * Npad;      // X after `fired` firings
             int32_t* const Xn = Xb + ((fired + 1u) & 1u) * Npad;     // the other buffer
+            // ---- mu's rows, one round trip: the jump (lane q: entry q) and
+            // the dependency records (lane 0: mu itself, whose propensity may
+            // read a species it changes; lane q >= 1: the q-th other channel
+            // of D(mu) or k = -1), each with its reactants, rate and the
+            // change of those reactants under v_mu.  Without a rate schedule
+            // they are issued before the end tests (row 0 when nothing can
+            // fire), which then run while they load.
+            const int mr = d1 == __builtin_inf() ? 0 : mu;
+            int4 gr;
+            double gc;
+            int2 dd, nv;
+            auto load_rows = [&]() {
+                gr = grow[mr * 64 + lane];
+                gc = growc[mr * 64 + lane];
+                dd = gdel[mr * 64 + lane];
+                nv = nu_fixed[mr * nu_stride + min(lane, nu_stride - 1)];
+            };
+            if constexpr (!SCHED) load_rows();
             if (SCHED && __builtin_amdgcn_readfirstlane(b_next < t_end && t_new > b_next)) {
                 // every clock runs to the breakpoint at the old rates; every
                 // propensity takes the next piece's rates (Eq. 28 again)
@@ -231,15 +249,7 @@ __global__ __launch_bounds__(L, g2_min_waves(S)) void rt_group_lds_kernel(rt_cla
             }
             if (d1 == __builtin_inf()) { st = RTSSA_TRAJ_ABSORBED; break; }
             if (t_new > t_end) { st = RTSSA_TRAJ_OK; break; }
-            // ---- mu's rows, one round trip: the jump (lane q: entry q) and
-            // the dependency records (lane 0: mu itself, whose propensity may
-            // read a species it changes; lane q >= 1: the q-th other channel
-            // of D(mu) or k = -1), each with its reactants, rate and the
-            // change of those reactants under v_mu
-            const int4 gr = grow[mu * 64 + lane];
-            const double gc = growc[mu * 64 + lane];
-            const int2 dd = gdel[mu * 64 + lane];
-            const int2 nv = nu_fixed[mu * nu_stride + min(lane, nu_stride - 1)];
+            if constexpr (SCHED) load_rows();
             // ---- draws, while the rows load: a wavefront refills one waiting
             // slot per lane once enough lanes have one, and at once when it
             // owns mu and mu's next draw E(mu, n_mu + 1) is still waiting (the
