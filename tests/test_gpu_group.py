@@ -117,6 +117,14 @@ def test_group_edge_cases():
         g = api.simulate(net, x0, 100.0, [1e-12, 100.0], 6, mapping=mapping, with_hash=True)
         ref = oracle.simulate(spec, x0, 100.0, [1e-12, 100.0], 1, 6)
         _assert_same(g, ref)
+    # a count that starts clear of the top and climbs to it: the first firings
+    # run without the jump's check, the last ones with it
+    x0 = np.array([2**31 - 200, 5], np.int32)
+    for mapping in (2, 3):
+        g = api.simulate(net, x0, 100.0, [1e-12, 100.0], 6, mapping=mapping, with_hash=True)
+        ref = oracle.simulate(spec, x0, 100.0, [1e-12, 100.0], 1, 6)
+        assert (np.asarray(ref["status"]) == 2).all()          # every trajectory overflows
+        _assert_same(g, ref)
     # firing cap and absorbing states, per-trajectory initial states
     spec2, x02 = _net(12, 30, 31)
     net2 = api.Network(spec2)
