@@ -176,7 +176,8 @@ int rt_run_rows(const rtssa_network* net, const rtssa_options& o)
     if (o.method == RTSSA_METHOD_LAZY || o.method == RTSSA_METHOD_DIRECT_TREE) return 1;
     if (o.method != RTSSA_METHOD_RANDOM_TIME) return 0;
     const int mapping = o.mapping == RTSSA_MAP_AUTO ? rt_auto_mapping(net) : o.mapping;
-    if (net->M <= 0) return 0;
+    // (also for M = 0: the kernels load the rows of channel 0 before they
+    // find that nothing can fire, and the tables then hold one empty row)
     return mapping == RTSSA_MAP_WORKGROUP ? 2 : (mapping == RTSSA_MAP_WAVE ? 1 : 0);
 }
 
@@ -377,8 +378,9 @@ int rt_simulate_checks(const rtssa_network* net, const int32_t* x0, int32_t x0_p
     const int rows = rt_run_rows(net, o);
     if (rows && R > 0) {
         if (!may_build_rows && !rt_rows_ready(net, rows))
-            return rt_fail(RTSSA_E_INVALID, "the tree methods and the workgroup mapping need the "
-                                            "network's rows built first (rtssa_workspace_size)");
+            return rt_fail(RTSSA_E_INVALID, "the tree methods and the sub-wave and workgroup "
+                                            "mappings need the network's rows built first "
+                                            "(rtssa_workspace_size)");
         rc = rt_rows_prepare(const_cast<rtssa_network*>(net), rows);
         if (rc) return rc;
     }

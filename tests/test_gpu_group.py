@@ -109,6 +109,16 @@ def test_mappings_agree_on_the_same_network():
 
 def test_group_edge_cases():
     api = _api()
+    # no channels, in the mappings chosen explicitly: every trajectory is
+    # absorbed at t = 0
+    spec0 = W.from_reactions(2, [])
+    net0 = api.Network(spec0)
+    x00 = np.array([3, 4], np.int32)
+    for mapping in (2, 3):
+        g = api.simulate(net0, x00, 1.0, [0.0, 1.0], 5, mapping=mapping, with_hash=True)
+        ref = oracle.simulate(spec0, x00, 1.0, [0.0, 1.0], 1, 5)
+        _assert_same(g, ref)
+        assert (_np(g["status"]) == 1).all()
     # overflow stops before the jump
     spec = W.from_reactions(2, [({0: 1}, {0: 2}, 1.0), ({1: 1}, {}, 1.0)])
     net = api.Network(spec)
