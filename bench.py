@@ -447,7 +447,8 @@ def bench_batched(api, W, steps=2, n_nets=4096, solo_sample=32, tune_samples=16,
     """4096 random networks (M log-uniform in [3, 2048], N = M/4, 64
     trajectories each, t_end for about 2e4 firings) in one captured launch per
     size class -- the networks above LAZY_ABOVE_M channels in the lazy form, the others
-    with lane counts chosen by the autotuner -- against one rtssa_simulate
+    with lane counts chosen by the autotuner, each class's networks queued by
+    the firings of a pilot run with another seed -- against one rtssa_simulate
     launch per network with the same method.  Networks whose rates grow with the state can run far
     past 2e4 firings; every trajectory is capped at 1e5 firings (status
     MAX_FIRINGS, counted), in the batch and in the per-network launches alike.
@@ -471,7 +472,16 @@ def bench_batched(api, W, steps=2, n_nets=4096, solo_sample=32, tune_samples=16,
         plan_text = open(plan).read().strip().splitlines()
         del b0
         b = api.Batch(jobs, want=want, max_firings=BATCH_MAX_FIRINGS, plan_path=plan)
-    log("batched: autotuned in %.1f s: %s" % (tune_s, "; ".join(plan_text)))
+        log("batched: autotuned in %.1f s: %s" % (tune_s, "; ".join(plan_text)))
+        # a run with another seed gives each network's work; the batch is then
+        # rebuilt with those weights so that every class queue starts its
+        # longest networks first (the timed runs draw seed 1)
+        st = b.run(seed=2)
+        log("batched pilot (seed 2): %.1f ms, %d firings" % (st["kernel_ms"], st["firings"]))
+        for j, o in zip(jobs, b.outputs):
+            j["weight"] = float(o["n"].to(torch.int64).sum())
+        del b
+        b = api.Batch(jobs, want=want, max_firings=BATCH_MAX_FIRINGS, plan_path=plan)
     st = b.run(seed=1)                                   # captures the graph
     log("batched warmup: %.1f ms, %d firings" % (st["kernel_ms"], st["firings"]))
     torch.cuda.synchronize()

@@ -354,6 +354,11 @@ typedef struct {
     uint8_t* status;
     uint64_t* seq_hash;
     uint32_t* tie_step;
+    /* The item's work for scheduling only (0: M x R): within a class the
+     * items go to the device queue heaviest first, so that long runs start
+     * early; e.g. the firings of a previous run of the same item.  Changes no
+     * result.  Negative or non-finite: RTSSA_E_INVALID. */
+    double weight;
 } rtssa_batch_item;
 
 typedef struct rtssa_batch rtssa_batch;

@@ -39,7 +39,8 @@ class BatchItem(C.Structure):
                 ("sample_t", vp), ("net_id", u32), ("method", i32), ("traj_offset", u64),
                 ("R", i64), ("samples", vp), ("s_stride_r", i64), ("s_stride_g", i64),
                 ("s_stride_n", i64), ("n_out", vp), ("T_out", vp), ("x_final", vp),
-                ("t_last", vp), ("status", vp), ("seq_hash", vp), ("tie_step", vp)]
+                ("t_last", vp), ("status", vp), ("seq_hash", vp), ("tie_step", vp),
+                ("weight", f64)]
 
 
 SIGNATURES = {

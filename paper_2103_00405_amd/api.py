@@ -237,7 +237,9 @@ class Batch:
     (captured once into a hipGraph and replayed).  ``jobs`` is a list of dicts
     with keys net (Network), x0, t_end, sample_t, R and optionally net_id,
     traj_offset, method (METHOD_RANDOM_TIME, METHOD_LAZY or
-    METHOD_DIRECT_TREE; the last has no T or tie_step); outputs are allocated
+    METHOD_DIRECT_TREE; the last has no T or tie_step) and weight (the job's
+    expected work, e.g. its firings in an earlier run: orders each class's
+    queue, heaviest first, and changes no result; default M x R); outputs are allocated
     here (per job: samples, n, T, x_final, t_last, status, seq_hash, tie_step)
     and returned by ``run``."""
 
@@ -283,6 +285,7 @@ class Batch:
             it.method = method
             it.traj_offset = int(j.get("traj_offset", 0))
             it.R = R
+            it.weight = float(j.get("weight", 0.0))
             it.samples = smp.data_ptr() if smp is not None and smp.numel() else None
             it.s_stride_r, it.s_stride_g, it.s_stride_n = st
             for k, f in (("n", "n_out"), ("T", "T_out"), ("x_final", "x_final"),

@@ -16,6 +16,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <cmath>
 #include <map>
 #include <string>
 #include <vector>
@@ -163,6 +164,8 @@ static int batch_create(const rtssa_batch_item* items, int32_t count, const rtss
         if (!rc && b.R > 0) rc = rt_check_grid_host(b.sample_t, b.G, b.t_end);
         const std::string at = "item " + std::to_string(i) + ": ";
         if (rc) return rt_fail(rc, at + rtssa_last_error());
+        if (!(b.weight >= 0.0) || !std::isfinite(b.weight))
+            return rt_fail(RTSSA_E_INVALID, at + "weight must be finite and >= 0");
         if (b.method != RTSSA_METHOD_RANDOM_TIME && b.method != RTSSA_METHOD_LAZY &&
             b.method != RTSSA_METHOD_DIRECT_TREE)
             return rt_fail(RTSSA_E_UNSUPPORTED, at + "batched items run RANDOM_TIME, LAZY or "
@@ -203,10 +206,14 @@ static int batch_create(const rtssa_batch_item* items, int32_t count, const rtss
         rtssa_batch_class c;
         c.key = kv.first;
         c.members = kv.second;
-        // heaviest items first so the tail of the queue holds short work
-        std::stable_sort(c.members.begin(), c.members.end(), [&](int x, int y) {
-            return (double)items[x].net->M * items[x].R > (double)items[y].net->M * items[y].R;
-        });
+        // heaviest items first so the tail of the queue holds short work (the
+        // caller's weight, else M x R)
+        auto work = [&](int x) {
+            return items[x].weight > 0.0 ? items[x].weight
+                                         : (double)items[x].net->M * items[x].R;
+        };
+        std::stable_sort(c.members.begin(), c.members.end(),
+                         [&](int x, int y) { return work(x) > work(y); });
         for (int i : c.members) {
             c.max_M = std::max(c.max_M, items[i].net->M);
             c.max_N = std::max(c.max_N, items[i].net->N);

@@ -173,3 +173,38 @@ def test_null_arguments_rejected():
     assert L.rtssa_simulate(None, None, 0, 1.0, None, 0, 1, 0, 0, 1, None, 0, 0, 0, None, None,
                             None, None, None, None, None, None, None, None) == -1
     assert L.rtssa_score_grad(None, None, None, 0, 0, 1, None, None, None, 0, None) == -1
+
+
+def test_struct_layouts_match_header(tmp_path):
+    """The binding's ctypes structures have the header's field offsets and
+    sizes (a C program built against include/rtssa.h prints them)."""
+    import shutil
+    import subprocess
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no C compiler")
+    structs = {"rtssa_stats": _lib.Stats, "rtssa_options": _lib.Options,
+               "rtssa_batch_item": _lib.BatchItem}
+    lines = ['#include <stddef.h>', '#include <stdio.h>', '#include "rtssa.h"',
+             'int main(void) {']
+    for cname, py in structs.items():
+        lines.append('printf("%s sizeof %%zu\\n", sizeof(%s));' % (cname, cname))
+        for f in py._fields_:
+            lines.append('printf("%s %s %%zu\\n", offsetof(%s, %s));'
+                         % (cname, f[0], cname, f[0]))
+    lines += ['return 0;', '}']
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.run([cc, "-std=c11", "-I", os.path.join(ROOT, "include"), str(src), "-o",
+                    str(exe)], check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout
+    got = {}
+    for ln in out.split("\n"):
+        if ln:
+            c, f, v = ln.split()
+            got[(c, f)] = int(v)
+    for cname, py in structs.items():
+        assert got[(cname, "sizeof")] == C.sizeof(py), cname
+        for f in py._fields_:
+            assert got[(cname, f[0])] == getattr(py, f[0]).offset, (cname, f[0])

@@ -143,3 +143,31 @@ def test_batch_with_per_item_methods():
                                          j["R"], tree=True, **kw)
         assert np.array_equal(b.outputs[i]["n"].cpu().numpy().view(np.uint32), ref["n"])
         assert np.array_equal(b.outputs[i]["samples"].cpu().numpy(), ref["samples"])
+
+
+def test_weights_order_queues_and_keep_bits():
+    """Per-item weights (here the firings of a run with another seed) order
+    each class's queue heaviest first and change no output; a negative or
+    non-finite weight is rejected."""
+    api = _api()
+    jobs = _jobs(api, n_nets=30, seed=12)
+    b0 = api.Batch(jobs, with_hash=True)
+    b0.run(seed=21)
+    torch.cuda.synchronize()
+    for j, o in zip(jobs, b0.outputs):
+        j["weight"] = float(o["n"].to(torch.int64).sum())
+    ref = [{k: v.clone() for k, v in o.items()} for o in b0.outputs]
+    b1 = api.Batch(jobs, with_hash=True)
+    for ci in range(len(b1.classes())):
+        w = [jobs[i]["weight"] for i in b1.class_items(ci)]
+        assert w == sorted(w, reverse=True), (ci, w)
+    b1.run(seed=21)
+    torch.cuda.synchronize()
+    for r, o in zip(ref, b1.outputs):
+        for k in KEYS:
+            assert torch.equal(r[k], o[k]), k
+    for bad in (-1.0, float("nan"), float("inf")):
+        jj = [dict(j) for j in jobs[:3]]
+        jj[1]["weight"] = bad
+        with pytest.raises(api._lib.RtssaError, match="weight"):
+            api.Batch(jj)
