@@ -15,28 +15,31 @@
 // Layout.  The wavefront's LDS region holds the species counts X and a
 // minimum tree over the tau_k: the leaves are tau_k (M doubles); a node of
 // level l >= 1 holds the smallest tau over its kFan children of level l - 1
-// and that tau's channel.  Levels are built up to the first with at most 64
-// entries (the leaves themselves when M <= 64); that top level is reduced to
-// the next event by one wavefront argmin (DPP and permlane steps), which
-// every lane keeps in registers.  Each level is stored as two arrays (tau,
-// channel) padded to a multiple of kFan entries with empty values, so that a
-// node's children are read with a few 16-byte loads and no bounds tests;
-// merges use selects, not branches.  Fan-out 8 measured faster than 16.  The
-// second smallest tau (for the near-tie count only) is the smallest over the
+// and that tau's channel.  Levels are built up to the first with at most 512
+// entries (the leaves themselves when M <= 512); each lane scans its entries
+// of that top level (up to 8, only the 64-entry chunks that exist) and one
+// wavefront min reduction plus a ballot gives the next event, which every
+// lane keeps in registers.  Each level is stored as two arrays (tau, channel)
+// padded to a multiple of kFan entries with empty values, so that a node's
+// children are read with a few 16-byte loads and no bounds tests; merges use
+// selects, not branches.  Fan-out 8 measured faster than 16.  The near-tie
+// test (a count only) needs the second smallest tau, the smallest over the
 // siblings of mu's leaf and of its ancestors below the top level and over the
-// top level's other entries, taken while the firing's global loads are in
-// flight.  The channels' T_k, s_k, P_k, a_k (32 bytes), n_k and the spare word
-// of their last Philox block live in a global workspace, one slice per
-// wavefront of the grid.
+// top level's other entries; it is decided by one ballot while the firing's
+// global loads are in flight.  The channels' T_k, s_k, P_k, a_k (32 bytes),
+// n_k and the spare word of their last Philox block live in a global
+// workspace, one slice per wavefront of the grid.
 //
-// A firing: the argmin gives mu; the wavefront loads mu's fixed-stride rows
-// (its jump and the channels it touches, so that one load round trip
-// suffices before the records), checks and applies the jump, draws mu's next
-// Exp(1) with all lanes, then one lane per touched channel updates it and
-// writes its leaf; the touched leaves' ancestors are recomputed level by
-// level, one lane per touched channel (lanes that share an ancestor compute
-// the same node), and the top level is reduced again.  No workgroup barrier
-// is used: a wavefront's LDS accesses complete in program order.
+// A firing: the argmin gives mu; the wavefront loads mu's firing count and
+// kept word first, then mu's fixed-stride rows (its jump and the channels it
+// touches, so that one load round trip suffices before the records); mu's
+// next Exp(1) is drawn from wave-uniform values (the Philox rounds on the
+// scalar unit) while the records are on their way; the jump is checked and
+// applied, then one lane per touched channel updates it and writes its leaf;
+// the touched leaves' ancestors are recomputed level by level, one lane per
+// touched channel (lanes that share an ancestor compute the same node), and
+// the top level is reduced again.  No workgroup barrier is used: a
+// wavefront's LDS accesses complete in program order.
 #include <hip/hip_runtime.h>
 
 #include "internal.h"
@@ -47,9 +50,12 @@ namespace {
 
 constexpr int kFanLog = 3;               // children per node: 2^kFanLog
 constexpr int kFan = 1 << kFanLog;
-constexpr int kMaxLevels = 64 / kFan;    // one lane per sibling in lazy_second
+constexpr int kMaxLevels = 64 / kFan;    // the sum tree's levels above the leaves, at most
 constexpr int kTopPer = 8;               // top-level entries per lane
 constexpr int kTopMax = 64 * kTopPer;    // the tree stops at a level this small
+// the lazy form's levels above the leaves: 2 reach 512 x 8^2 = 32768 channels,
+// more than a wavefront's LDS holds
+constexpr int kLazyLevels = 2;
 
 struct rt_lazy_rec {                     // a channel's state in the workspace
     double T, s, P, a;
@@ -131,46 +137,25 @@ __device__ __forceinline__ void lazy_store(const lazy_tree& tr, int l, int j, co
     tr.kk[l][j] = v.k;
 }
 
-__device__ __forceinline__ double lazy_min_f64(double a, double b) { return rt_min_sel(a, b); }
-
-// Smallest value over the wavefront.
-__device__ __forceinline__ double lazy_wave_min(double v) { return rt_wave_min_f64(v); }
-
-// The smaller of two entries from anywhere in the wavefront; on equal values
-// the lower channel (the order of a cross-lane reduction is not channel order).
-__device__ __forceinline__ lazy_min lazy_merge_any(const lazy_min& a, const lazy_min& b)
+// The smallest entry (and its channel) over the wavefront, in every lane: the
+// smallest value by a min reduction, then the channel of the one lane holding
+// it; when several lanes hold it (or every value is +inf) the lowest of their
+// channels (the order of lanes is not channel order).
+__device__ __forceinline__ lazy_min lazy_wave_argmin(const lazy_min& v)
 {
-    const bool blt = b.d < a.d, eq = b.d == a.d;
-    return lazy_min{blt ? b.d : a.d, blt ? b.k : (eq ? min(a.k, b.k) : a.k)};
-}
-
-template <int CTRL>
-__device__ __forceinline__ lazy_min lazy_dpp_step(const lazy_min& v)
-{
-    return lazy_merge_any(v, lazy_min{rt_dpp_f64<CTRL>(v.d), rt_dpp<CTRL>(v.k)});
-}
-
-template <int ROWS>
-__device__ __forceinline__ lazy_min lazy_swap_step(const lazy_min& v)
-{
-    lazy_min p, q;
-    p.d = rt_swap_f64<ROWS>(v.d, q.d);
-    uint32_t pk, qk;
-    rt_swap<ROWS>((uint32_t)v.k, pk, qk);
-    p.k = (int32_t)pk;
-    q.k = (int32_t)qk;
-    return lazy_merge_any(p, q);
-}
-
-// The smallest entry (and its channel) over the wavefront, in every lane.
-__device__ __forceinline__ lazy_min lazy_wave_argmin(lazy_min v)
-{
-    v = lazy_dpp_step<0xB1>(v);                          // quad_perm [1,0,3,2]
-    v = lazy_dpp_step<0x4E>(v);                          // quad_perm [2,3,0,1]
-    v = lazy_dpp_step<0x141>(v);                         // row_half_mirror
-    v = lazy_dpp_step<0x140>(v);                         // row_mirror
-    v = lazy_swap_step<16>(v);
-    return lazy_swap_step<32>(v);
+    const double m = rt_wave_min_f64(v.d);
+    unsigned long long own = __ballot(v.d == m);
+    int32_t k;
+    if (__builtin_expect(__popcll(own) == 1, 1)) {
+        k = __builtin_amdgcn_readlane(v.k, __ffsll((long long)own) - 1);
+    } else {
+        k = 0x7FFFFFFF;
+        while (own) {
+            k = min(k, (int32_t)__builtin_amdgcn_readlane(v.k, __ffsll((long long)own) - 1));
+            own &= own - 1ull;
+        }
+    }
+    return lazy_min{m, k};
 }
 
 // The top level (at most kTopMax entries; lane l holds entries l + 64 i) as
@@ -193,14 +178,16 @@ __device__ __forceinline__ lazy_top lazy_top_scan(const double* top_d, const int
         const int e = lane + 64 * i;
         dv[i] = __builtin_inf();
         kv[i] = 0x7FFFFFFF;
-        if (e < top_cnt) {
+        if (64 * i < top_cnt && e < top_cnt) {
             dv[i] = top_d[e];
             kv[i] = leaves_on_top ? e : top_k[e];
         }
     }
     lazy_top r{lazy_min{__builtin_inf(), 0x7FFFFFFF}, __builtin_inf(), -1};
+    // chunks past the level's entries (the same in every lane) are skipped
 #pragma unroll
     for (int i = 0; i < kTopPer; ++i) {
+        if (64 * i >= top_cnt) break;
         const bool lt = dv[i] < r.m.d;
         r.d2 = rt_min_sel(r.d2, lt ? r.m.d : dv[i]);
         r.m.d = lt ? dv[i] : r.m.d;
@@ -210,15 +197,20 @@ __device__ __forceinline__ lazy_top lazy_top_scan(const double* top_d, const int
     return r;
 }
 
-// The second smallest tau over all leaves: every leaf but mu lies in the
-// group of mu's leaf, below a sibling of one of mu's ancestors under the top
-// level, or below another entry of the top level, so it is the smallest of
-// those values.  Lane kFan l + i reads sibling i at level l < top (level_off
-// holds each level's tau array as a byte offset into the LDS region, a table
-// in LDS so that the per-lane level index does not turn into a private-memory
-// array); every lane also takes top-level entry `lane` unless it is mu's.
-__device__ __forceinline__ double lazy_second(const char* region, const uint32_t* level_off,
-                                              int top, int mu, const lazy_top& tp, int lane)
+// The near-tie test of a firing (d1 = tau_mu - t).  The second smallest tau
+// over all leaves is the smallest of the candidates: every leaf but mu lies in
+// the group of mu's leaf, below a sibling of one of mu's ancestors under the
+// top level, or below another entry of the top level.  The test is monotone in
+// the second smallest (a larger value gives a larger rounded gap), so it holds
+// for it exactly when it holds for one of the candidates: each lane tests its
+// own and one ballot decides, with no reduction.  Lane kFan l + i reads
+// sibling i at level l < top (level_off holds each level's tau array as a
+// byte offset into the LDS region, a table in LDS so that the per-lane level
+// index does not turn into a private-memory array); every lane also takes its
+// own top-level minimum, or its second when it holds mu's ancestor.
+__device__ __forceinline__ bool lazy_near_tie(const char* region, const uint32_t* level_off,
+                                              int top, int mu, const lazy_top& tp, int lane,
+                                              double t, double d1)
 {
     double sib = __builtin_inf();
     if (top > 0) {
@@ -227,10 +219,9 @@ __device__ __forceinline__ double lazy_second(const char* region, const uint32_t
         const double x = ((const double*)(region + level_off[lev]))[(jl & ~(kFan - 1)) + i];
         sib = (lane >> kFanLog) < top && i != (jl & (kFan - 1)) ? x : __builtin_inf();
     }
-    // the top level's entries but mu's ancestor (the smallest of its lane)
     const int anc = mu >> (kFanLog * top);
     const double own = lane == (anc & 63) && tp.e1 == anc ? tp.d2 : tp.m.d;
-    return lazy_wave_min(lazy_min_f64(sib, own));
+    return __ballot(rt_near_tie(d1, rt_min_sel(sib, own) - t)) != 0ull;
 }
 
 // A touched channel's update (mu: fresh = true, T_mu = P_mu, P_mu += E;
@@ -265,7 +256,7 @@ __global__ __launch_bounds__(64) void rt_lazy_kernel(rt_class_dev C, rt_lazy_rec
 {
     extern __shared__ int32_t dyn_lds[];
     __shared__ uint32_t log_scratch[RT_LOG_SCRATCH];
-    __shared__ uint32_t level_off[kMaxLevels + 1];
+    __shared__ uint32_t level_off[kLazyLevels + 1];
     rt_ws* const ws = C.ws;
     const uint32_t key0 = ws->key0, key1 = ws->key1;
     const int lane = threadIdx.x;
@@ -281,7 +272,7 @@ __global__ __launch_bounds__(64) void rt_lazy_kernel(rt_class_dev C, rt_lazy_rec
     for (;;) {
         unsigned long long u = 0;
         if (lane == 0) u = atomicAdd(&ws->next_unit, 1ull);
-        u = __shfl(u, 0, 64);
+        u = rt_first_lane_u64(u);                        // lane 0's
         if ((int64_t)u >= total) break;
         const int item = __builtin_amdgcn_readfirstlane(rt_find_item(unit_start, C.count, (int64_t)u));
         const rt_cptr<rt_item_dev> it = rt_const(C.items) + item;
@@ -314,7 +305,7 @@ __global__ __launch_bounds__(64) void rt_lazy_kernel(rt_class_dev C, rt_lazy_rec
             p += 8 * padf(tr.cnt[0]);
             int top_l = tr.cnt[0] <= kTopMax ? 0 : -1;
 #pragma unroll
-            for (int l = 1; l <= kMaxLevels; ++l) {
+            for (int l = 1; l <= kLazyLevels; ++l) {
                 tr.cnt[l] = (tr.cnt[l - 1] + kFan - 1) >> kFanLog;
                 const int P = top_l < 0 ? padf(tr.cnt[l]) : 0;
                 tr.d[l] = (double*)p;
@@ -327,13 +318,13 @@ __global__ __launch_bounds__(64) void rt_lazy_kernel(rt_class_dev C, rt_lazy_rec
         const int top = tr.top;
         double* const leaves = tr.d[0];
 #pragma unroll
-        for (int l = 0; l <= kMaxLevels; ++l)
+        for (int l = 0; l <= kLazyLevels; ++l)
             if (lane == l) level_off[l] = (uint32_t)((char*)tr.d[l] - (char*)dyn_lds);
         const double* top_d = tr.d[0];
         const int32_t* top_k = tr.kk[0];
         int top_cnt = tr.cnt[0];
 #pragma unroll
-        for (int l = 1; l <= kMaxLevels; ++l) {
+        for (int l = 1; l <= kLazyLevels; ++l) {
             top_d = l == top ? tr.d[l] : top_d;
             top_k = l == top ? tr.kk[l] : top_k;
             top_cnt = l == top ? tr.cnt[l] : top_cnt;
@@ -345,7 +336,7 @@ __global__ __launch_bounds__(64) void rt_lazy_kernel(rt_class_dev C, rt_lazy_rec
         // padding entries (and the single leaf of an empty network) are empty
         for (int k = M + lane; k < padf(tr.cnt[0]); k += 64) leaves[k] = __builtin_inf();
 #pragma unroll
-        for (int l = 1; l <= kMaxLevels; ++l) {
+        for (int l = 1; l <= kLazyLevels; ++l) {
             if (l > top) break;
             for (int j = tr.cnt[l] + lane; j < padf(tr.cnt[l]); j += 64)
                 lazy_store(tr, l, j, lazy_min{__builtin_inf(), 0x7FFFFFFF});
@@ -364,7 +355,7 @@ __global__ __launch_bounds__(64) void rt_lazy_kernel(rt_class_dev C, rt_lazy_rec
         }
         rt_wave_lds_fence();
 #pragma unroll
-        for (int l = 1; l <= kMaxLevels; ++l) {
+        for (int l = 1; l <= kLazyLevels; ++l) {
             if (l > top) break;
             for (int j = lane; j < tr.cnt[l]; j += 64) lazy_store(tr, l, j, lazy_node(tr, l, j));
             rt_wave_lds_fence();
@@ -409,7 +400,7 @@ __global__ __launch_bounds__(64) void rt_lazy_kernel(rt_class_dev C, rt_lazy_rec
                                          &ws->clamps);
                 rt_wave_lds_fence();
 #pragma unroll
-                for (int l = 1; l <= kMaxLevels; ++l) {
+                for (int l = 1; l <= kLazyLevels; ++l) {
                     if (l > top) break;
                     for (int j = lane; j < tr.cnt[l]; j += 64)
                         lazy_store(tr, l, j, lazy_node(tr, l, j));
@@ -432,10 +423,12 @@ __global__ __launch_bounds__(64) void rt_lazy_kernel(rt_class_dev C, rt_lazy_rec
                 s_next = g < it->G ? rt_const(it->s)[g] : __builtin_inf();
             }
             // ---- every load of the firing is issued before any is used:
-            // mu's fixed-stride rows (the jump; the touched channels of the
-            // first round: lane 0 takes mu, lane q the q-th other channel of
-            // D(mu)), then their records and reaction data, and mu's firing
-            // count; lanes without a channel load mu's (valid, unused)
+            // mu's firing count and kept word, mu's fixed-stride rows (the
+            // jump; the touched channels of the first round: lane 0 takes mu,
+            // lane q the q-th other channel of D(mu)), then their records and
+            // reaction data; lanes without a channel load mu's (valid, unused)
+            const uint32_t nm_ld = nks[mu];
+            const unsigned long long w_ld = wnext[mu];
             const int n_other = touch[mu * 64];
             const int tv = touch[mu * 64 + lane];
             const int2 nv = nu_fixed[mu * nu_stride + min(lane, nu_stride - 1)];
@@ -446,23 +439,19 @@ __global__ __launch_bounds__(64) void rt_lazy_kernel(rt_class_dev C, rt_lazy_rec
             const rt_lazy_rec rc0 = recs[k];
             const int2 rr0 = react[k];
             const double c0 = cc[k];
-            const uint32_t nm_ld = nks[mu];
-            const unsigned long long w_ld = wnext[mu];
-            const uint32_t nm = mu == last_mu ? last_nm : nm_ld;
-            const unsigned long long w_odd = mu == last_mu ? last_w : w_ld;
+            // the same in every lane: the draw below runs on the scalar unit
+            const uint32_t nm =
+                __builtin_amdgcn_readfirstlane(mu == last_mu ? last_nm : nm_ld);
+            const unsigned long long w_odd = rt_first_lane_u64(mu == last_mu ? last_w : w_ld);
             // near-tie test (statistics only) while the loads are in flight
-            {
-                const double d1 = t_new - t;
-                const double d2 =
-                    lazy_second((const char*)dyn_lds, level_off, top, mu, top_e, lane) - t;
-                if (rt_near_tie(d1, d2)) {
-                    if (lane == 0) atomicAdd(&ws->near_ties, 1ull);
-                    tie = tie == kTieNone ? fired : tie;
-                }
+            if (lazy_near_tie((const char*)dyn_lds, level_off, top, mu, top_e, lane, t,
+                              t_new - t)) {
+                if (lane == 0) atomicAdd(&ws->near_ties, 1ull);
+                tie = tie == kTieNone ? fired : tie;
             }
-            // the fired channel's next Exp(1) (Eq. 26), drawn by every lane
-            // while the loads are in flight: draw n = nm + 1 takes the kept
-            // word when n is odd, else a new block whose odd word is kept
+            // the fired channel's next Exp(1) (Eq. 26) while the records are
+            // on their way: draw n = nm + 1 takes the kept word when n is
+            // odd, else a new block whose odd word is kept
             const uint32_t nd = nm + 1u;
             uint64_t word = w_odd;
             unsigned long long w_keep = w_odd;              // wnext[mu] after this firing
@@ -487,7 +476,7 @@ __global__ __launch_bounds__(64) void rt_lazy_kernel(rt_class_dev C, rt_lazy_rec
             // (lanes without a touched channel follow mu's path: they compute
             // and store the same values as lane 0)
 #pragma unroll
-            for (int l = 1; l <= kMaxLevels; ++l) {
+            for (int l = 1; l <= kLazyLevels; ++l) {
                 if (l > top) break;
                 const int j = k >> (kFanLog * l);
                 lazy_store(tr, l, j, lazy_node(tr, l, j));
@@ -506,7 +495,7 @@ __global__ __launch_bounds__(64) void rt_lazy_kernel(rt_class_dev C, rt_lazy_rec
                                               &leaves[k2], &ws->clamps);
                     rt_wave_lds_fence();
 #pragma unroll
-                    for (int l = 1; l <= kMaxLevels; ++l) {
+                    for (int l = 1; l <= kLazyLevels; ++l) {
                         if (l > top) break;
                         const int j = (k2 >= 0 ? k2 : mu) >> (kFanLog * l);
                         lazy_store(tr, l, j, lazy_node(tr, l, j));
@@ -807,14 +796,14 @@ __global__ __launch_bounds__(64) void rt_dmtree_kernel(rt_class_dev C)
 // LDS bytes of one trajectory: X, the leaves and the node levels up to the
 // first with at most top_max entries (arrays padded to kFan entries; the
 // leaves count as that level when top_max > 1, while the sum tree always has
-// a root level above them); 0 when that takes more than kMaxLevels levels.
-static size_t tree_lds_bytes(int N, int M, int top_max)
+// a root level above them); 0 when that takes more than max_levels levels.
+static size_t tree_lds_bytes(int N, int M, int top_max, int max_levels)
 {
     size_t n = (size_t)((N + 3) & ~3) * 4;
     int c = M > 0 ? M : 1;
     n += (size_t)((c + kFan - 1) & ~(kFan - 1)) * 8;
     if (top_max > 1 && c <= top_max) return n;
-    for (int l = 1; l <= kMaxLevels; ++l) {
+    for (int l = 1; l <= max_levels; ++l) {
         c = (c + kFan - 1) >> kFanLog;
         n += (size_t)((c + kFan - 1) & ~(kFan - 1)) * 12;
         if (c <= top_max) return n;
@@ -823,10 +812,10 @@ static size_t tree_lds_bytes(int N, int M, int top_max)
 }
 
 // the lazy form's tree stops at a top level of at most kTopMax entries
-size_t rt_lazy_lds_bytes(int N, int M) { return tree_lds_bytes(N, M, kTopMax); }
+size_t rt_lazy_lds_bytes(int N, int M) { return tree_lds_bytes(N, M, kTopMax, kLazyLevels); }
 
 // the sum tree goes up to its single root
-static size_t dmtree_lds_bytes(int N, int M) { return tree_lds_bytes(N, M, 1); }
+static size_t dmtree_lds_bytes(int N, int M) { return tree_lds_bytes(N, M, 1, kMaxLevels); }
 
 // The lazy kernel's grid: the requested one, or the resident wavefronts
 // (LDS-limited) of the device, never more than the trajectories.

@@ -165,6 +165,15 @@ __device__ __forceinline__ rt_min2 rt_min2_group_allreduce(rt_min2 v, rt_min2* w
 
 __device__ __forceinline__ double rt_min_sel(double a, double b) { return b < a ? b : a; }
 
+// A 64-bit value of the wavefront's first active lane, known to the compiler
+// as the same in every lane (so that what depends on it stays scalar).
+__device__ __forceinline__ unsigned long long rt_first_lane_u64(unsigned long long v)
+{
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
+    return ((unsigned long long)hi << 32) | lo;
+}
+
 // Smallest value over the wavefront, in every lane.
 __device__ __forceinline__ double rt_wave_min_f64(double v)
 {
