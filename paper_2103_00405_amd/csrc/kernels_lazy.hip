@@ -272,7 +272,11 @@ __global__ __launch_bounds__(64) void rt_lazy_kernel(rt_class_dev C, rt_lazy_rec
     for (;;) {
         unsigned long long u = 0;
         if (lane == 0) u = atomicAdd(&ws->next_unit, 1ull);
-        u = rt_first_lane_u64(u);                        // lane 0's
+        // lane 0's unit; broadcast by readfirstlane the compiler keeps what
+        // depends on it (the trajectory index, the fired channel's Philox
+        // block) on the scalar unit, which measured faster without a rate
+        // schedule and slower with one (whose loop holds more scalar state)
+        u = SCHED ? __shfl(u, 0, 64) : rt_first_lane_u64(u);
         if ((int64_t)u >= total) break;
         const int item = __builtin_amdgcn_readfirstlane(rt_find_item(unit_start, C.count, (int64_t)u));
         const rt_cptr<rt_item_dev> it = rt_const(C.items) + item;
@@ -439,10 +443,12 @@ __global__ __launch_bounds__(64) void rt_lazy_kernel(rt_class_dev C, rt_lazy_rec
             const rt_lazy_rec rc0 = recs[k];
             const int2 rr0 = react[k];
             const double c0 = cc[k];
-            // the same in every lane: the draw below runs on the scalar unit
-            const uint32_t nm =
-                __builtin_amdgcn_readfirstlane(mu == last_mu ? last_nm : nm_ld);
-            const unsigned long long w_odd = rt_first_lane_u64(mu == last_mu ? last_w : w_ld);
+            // the same in every lane (without a schedule the draw below then
+            // runs on the scalar unit)
+            const uint32_t nm_v = mu == last_mu ? last_nm : nm_ld;
+            const unsigned long long w_v = mu == last_mu ? last_w : w_ld;
+            const uint32_t nm = SCHED ? nm_v : __builtin_amdgcn_readfirstlane(nm_v);
+            const unsigned long long w_odd = SCHED ? w_v : rt_first_lane_u64(w_v);
             // near-tie test (statistics only) while the loads are in flight
             if (lazy_near_tie((const char*)dyn_lds, level_off, top, mu, top_e, lane, t,
                               t_new - t)) {
