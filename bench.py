@@ -75,6 +75,14 @@ PEAK_LANE_SLOTS = 256 * 4 * 16 * CLOCK_HZ   # CUs x SIMDs x lanes x clock = 3.93
 # profiled; set to None when the kernel changes until it is measured again.
 LV_TRAFFIC_BYTES_PER_LAUNCH = 1.329e+09
 
+# VALU instructions (wave64) of one step of the batched workload: SQ_INSTS_VALU
+# summed over the timed replay's ten class kernels in one rocprofv3 counter
+# pass.  At 4 cycles per instruction on 256 x 4 SIMDs the step cannot take
+# less than this many cycles' worth of issue; valid for the kernels and the
+# autotuner's plan as profiled, None when they change until measured again.
+BATCH_VALU_INSTR_PER_STEP = 6.277e+11
+SIMD_ISSUE_HZ = 256 * 4 * CLOCK_HZ / 4        # wave64 VALU instructions per second
+
 
 def parse():
     ap = argparse.ArgumentParser()
@@ -537,7 +545,11 @@ def bench_batched(api, W, steps=2, n_nets=4096, solo_sample=32, tune_samples=16,
                                      "sample_firings": solo_fir,
                                      "estimated_ms_for_all": est_ms,
                                      "value": per_step / (est_ms / 1e3), "unit": "firings/s"},
-            "speedup_vs_per_network": est_ms / ms_step, "cpu_baseline": cpu}
+            "speedup_vs_per_network": est_ms / ms_step, "cpu_baseline": cpu,
+            "valu_issue": None if BATCH_VALU_INSTR_PER_STEP is None else {
+                "bound": "alu", "valu_instr_per_step_profiled": BATCH_VALU_INSTR_PER_STEP,
+                "floor_ms": BATCH_VALU_INSTR_PER_STEP / SIMD_ISSUE_HZ * 1e3,
+                "frac": BATCH_VALU_INSTR_PER_STEP / SIMD_ISSUE_HZ / (ms_step / 1e3)}}
 
 
 def main():
