@@ -132,7 +132,8 @@ __global__ __launch_bounds__(L, g2_min_waves(S)) void rt_group_lds_kernel(rt_cla
             if (live) {
                 an = rt_propensity_mem(react[k], crate[k], Xb);
                 in = 1.0 / an;
-                const rt_u4 w = rt_philox4x32_10(rt_u4{0u, (uint32_t)k, traj, net_id}, key0, key1);
+                const rt_u4 w =
+                    rt_philox4x32_10<false>(rt_u4{0u, (uint32_t)k, traj, net_id}, key0, key1);
                 m0 = (((uint64_t)w.y << 32) | w.x) >> 11;
                 m1 = (((uint64_t)w.w << 32) | w.z) >> 11;
             }
@@ -264,8 +265,8 @@ __global__ __launch_bounds__(L, g2_min_waves(S)) void rt_group_lds_kernel(rt_cla
                 uint32_t n1 = 0u;
 #pragma unroll
                 for (int s = 0; s < S; ++s) n1 = s == s1 ? nk[s] : n1;
-                const uint64_t m = has ? rt_draw_m53(key0, key1, traj, net_id,
-                                                     (uint32_t)(tid + s1 * L), n1 + 1u)
+                const uint64_t m = has ? rt_draw_m53<false>(key0, key1, traj, net_id,
+                                                            (uint32_t)(tid + s1 * L), n1 + 1u)
                                        : 0x1FFFFFFFFFFFFFull;
                 const double E = rt_neglog_wave(m, false, &ws->slow_logs, sc);
 #pragma unroll

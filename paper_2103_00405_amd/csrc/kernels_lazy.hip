@@ -462,8 +462,8 @@ __global__ __launch_bounds__(64) void rt_lazy_kernel(rt_class_dev C, rt_lazy_rec
             uint64_t word = w_odd;
             unsigned long long w_keep = w_odd;              // wnext[mu] after this firing
             if ((nd & 1u) == 0u) {
-                const rt_u4 w =
-                    rt_philox4x32_10(rt_u4{nd >> 1, (uint32_t)mu, traj, net_id}, key0, key1);
+                const rt_u4 w = rt_philox4x32_10<SCHED>(
+                    rt_u4{nd >> 1, (uint32_t)mu, traj, net_id}, key0, key1);
                 word = ((uint64_t)w.y << 32) | w.x;
                 w_keep = ((unsigned long long)w.w << 32) | w.z;
                 if (lane == 0) wnext[mu] = w_keep;
@@ -581,7 +581,8 @@ __device__ __forceinline__ double dt_draw(uint32_t key0, uint32_t key1, uint32_t
                                           uint32_t net_id, uint32_t fired, uint64_t* m2,
                                           unsigned long long* slow, uint32_t* sc)
 {
-    const rt_u4 w = rt_philox4x32_10(rt_u4{fired, 0xFFFFFFFFu, traj, net_id}, key0, key1);
+    const rt_u4 w =
+        rt_philox4x32_10<false>(rt_u4{fired, 0xFFFFFFFFu, traj, net_id}, key0, key1);
     *m2 = (((uint64_t)w.w << 32) | w.z) >> 11;
     return rt_neglog_uniform((((uint64_t)w.y << 32) | w.x) >> 11, slow, sc);
 }

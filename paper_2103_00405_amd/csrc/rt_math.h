@@ -30,6 +30,24 @@ RT_HD double rt_u2d(uint64_t x) { return __builtin_bit_cast(double, x); }
 // --------------------------------------------------------------- Philox
 struct rt_u4 { uint32_t x, y, z, w; };
 
+// a ^ b ^ c; on the GPU one three-input bitwise instruction (v_bitop3_b32
+// with truth table 0x96, the parity of its three inputs), which the compiler
+// does not form from two xors by itself.
+RT_HD uint32_t rt_xor3(uint32_t a, uint32_t b, uint32_t c)
+{
+#if defined(__HIP_DEVICE_COMPILE__)
+    return __builtin_amdgcn_bitop3_b32(a, b, c, 0x96);
+#else
+    return a ^ b ^ c;
+#endif
+}
+
+// Each round's output words x and z are a product's high half xor a counter
+// word xor a key word, with rt_xor3 when XOR3, else two plain xors (the same
+// bits).  rt_xor3 runs on the vector unit: a block whose inputs are the same
+// in every lane, left to the scalar unit, takes the plain form, and so do the
+// kernels where the three-input form measured slower.
+template <bool XOR3 = true>
 RT_HD rt_u4 rt_philox4x32_10(rt_u4 c, uint32_t k0, uint32_t k1)
 {
 #pragma unroll
@@ -37,9 +55,9 @@ RT_HD rt_u4 rt_philox4x32_10(rt_u4 c, uint32_t k0, uint32_t k1)
         const uint64_t p0 = (uint64_t)0xD2511F53u * c.x;
         const uint64_t p1 = (uint64_t)0xCD9E8D57u * c.z;
         rt_u4 o;
-        o.x = (uint32_t)(p1 >> 32) ^ c.y ^ k0;
+        o.x = XOR3 ? rt_xor3((uint32_t)(p1 >> 32), c.y, k0) : (uint32_t)(p1 >> 32) ^ c.y ^ k0;
         o.y = (uint32_t)p1;
-        o.z = (uint32_t)(p0 >> 32) ^ c.w ^ k1;
+        o.z = XOR3 ? rt_xor3((uint32_t)(p0 >> 32), c.w, k1) : (uint32_t)(p0 >> 32) ^ c.w ^ k1;
         o.w = (uint32_t)p0;
         c = o;
         k0 += 0x9E3779B9u;
@@ -269,11 +287,12 @@ RT_HD double rt_neglog_u53(uint64_t m, bool force_accurate, bool* slow, uint32_t
 // at counter (n >> 1, k, traj, net) under key (seed_lo, seed_hi); the 64-bit
 // word is (w1:w0) for even n and (w3:w2) for odd n; m = word >> 11, and the
 // draw is E = RN(-ln((m + 1) 2^-53)).
+template <bool XOR3 = true>
 RT_HD uint64_t rt_draw_m53(uint32_t k0, uint32_t k1, uint32_t traj, uint32_t net, uint32_t k,
                            uint32_t n)
 {
     rt_u4 c = {n >> 1, k, traj, net};
-    rt_u4 w = rt_philox4x32_10(c, k0, k1);
+    rt_u4 w = rt_philox4x32_10<XOR3>(c, k0, k1);
     uint64_t word = (n & 1u) ? (((uint64_t)w.w << 32) | w.z) : (((uint64_t)w.y << 32) | w.x);
     return word >> 11;
 }
