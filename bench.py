@@ -47,7 +47,7 @@ ALG_SLOTS_PER_FIRING_LV = 255
 ITEMISED_SLOTS_PER_FIRING_LV = 286
 # Instructions the profiler counts per firing of the headline kernel
 # (SQ_INSTS_VALU x 64 / firings; profiles/rt_thread_kernel_lv_ensemble_sq_counters.md).
-ISSUED_VALU_PER_FIRING_LV = 319
+ISSUED_VALU_PER_FIRING_LV = 307
 
 
 # Algorithmic lane-ops of one firing of an M-channel network in the eager
@@ -73,7 +73,7 @@ PEAK_LANE_SLOTS = 256 * 4 * 16 * CLOCK_HZ   # CUs x SIMDs x lanes x clock = 3.93
 # from two rocprofv3 counter passes (FETCH_SIZE, WRITE_SIZE) scaled by the same
 # counters on a 1 GiB copy (factors 2.0 and 1.0).  Valid for the kernel as
 # profiled; set to None when the kernel changes until it is measured again.
-LV_TRAFFIC_BYTES_PER_LAUNCH = 1.329e+09
+LV_TRAFFIC_BYTES_PER_LAUNCH = 1.331e+09
 
 # VALU instructions (wave64) of one step of the batched workload: SQ_INSTS_VALU
 # summed over the timed replay's ten class kernels in one rocprofv3 counter
