@@ -33,13 +33,13 @@
 // A firing: the argmin gives mu; the wavefront loads mu's firing count and
 // kept word first, then mu's fixed-stride rows (its jump and the channels it
 // touches, so that one load round trip suffices before the records); mu's
-// next Exp(1) is drawn from wave-uniform values (the Philox rounds on the
-// scalar unit) while the records are on their way; the jump is checked and
-// applied, then one lane per touched channel updates it and writes its leaf;
-// the touched leaves' ancestors are recomputed level by level, one lane per
-// touched channel (lanes that share an ancestor compute the same node), and
-// the top level is reduced again.  No workgroup barrier is used: a
-// wavefront's LDS accesses complete in program order.
+// next Exp(1) is drawn from wave-uniform values (without a rate schedule its
+// Philox rounds run on the scalar unit) while the records are on their way;
+// the jump is checked and applied, then one lane per touched channel updates
+// it and writes its leaf; the touched leaves' ancestors are recomputed level
+// by level, one lane per touched channel (lanes that share an ancestor
+// compute the same node), and the top level is reduced again.  No workgroup
+// barrier is used: a wavefront's LDS accesses complete in program order.
 #include <hip/hip_runtime.h>
 
 #include "internal.h"
@@ -178,7 +178,7 @@ __device__ __forceinline__ lazy_top lazy_top_scan(const double* top_d, const int
         const int e = lane + 64 * i;
         dv[i] = __builtin_inf();
         kv[i] = 0x7FFFFFFF;
-        if (64 * i < top_cnt && e < top_cnt) {
+        if (64 * i < top_cnt && e < top_cnt) {           // the first test: every lane alike
             dv[i] = top_d[e];
             kv[i] = leaves_on_top ? e : top_k[e];
         }
