@@ -80,7 +80,7 @@ LV_TRAFFIC_BYTES_PER_LAUNCH = 1.331e+09
 # pass.  At 4 cycles per instruction on 256 x 4 SIMDs the step cannot take
 # less than this many cycles' worth of issue; valid for the kernels and the
 # autotuner's plan as profiled, None when they change until measured again.
-BATCH_VALU_INSTR_PER_STEP = 6.277e+11
+BATCH_VALU_INSTR_PER_STEP = 6.217e+11
 SIMD_ISSUE_HZ = 256 * 4 * CLOCK_HZ / 4        # wave64 VALU instructions per second
 
 
