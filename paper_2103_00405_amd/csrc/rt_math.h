@@ -10,7 +10,8 @@
 // Contents:
 //   rt_philox4x32_10  Philox4x32-10 block function (Salmon, Moraes, Dror &
 //                     Shaw, SC'11) -- the counter-based stream of the
-//                     unit-exponential internal-time gaps (paper Eq. 23, 26).
+//                     unit-exponential internal-time gaps (paper Eq. 23, 26);
+//                     rt_xor3 does each round's two xors in one instruction.
 //   rt_neglog_u53     correctly rounded -ln(u), u = (m+1) 2^-53, so that a
 //                     draw ln(1/r) has one exact binary64 value.
 //   rt_draw_m53       the 53-bit integer behind the n-th draw of channel k.
